@@ -1,0 +1,170 @@
+"""FP64 CPU oracle for the stencil sweeps (ctypes binding to ``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.  It shares no code
+with the GPU path.  Inputs are converted to float64 exactly (float32 and
+binary16 values are exactly representable), results are float64.
+
+Pins (tests/test_oracle_pins.py) tie it to the mathematics rather than to
+itself: brute-force operator matrices, Fourier symbols, conservation,
+polynomial moments, the leapfrog energy invariant and closed form, the
+dot-product identity and finite differences.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True) -> str:
+    from .build_oracle import build_liboracle
+    return build_liboracle(force=force)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.oracle_sweep.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _dp,
+                                 ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.oracle_sweep_adjoint.argtypes = lib.oracle_sweep.argtypes
+    lib.oracle_fd2_weights.argtypes = [ctypes.c_int, _dp]
+    lib.oracle_laplacian3d.argtypes = [ctypes.c_int, _dp]
+    lib.oracle_wave_forward.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                        _dp, _dp, _dp, _i64p, _dp, ctypes.c_int64, _dp]
+    lib.oracle_wave_adjoint.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                        _dp, _dp, _dp]
+    lib.oracle_wave_gradient.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                         _dp, _dp, _dp, _i64p, _dp, ctypes.c_int64, _dp,
+                                         ctypes.c_int, _dp, _dp]
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _n3(shape: Tuple[int, ...]):
+    if len(shape) == 2:
+        n = (shape[1], shape[0], 1)
+    elif len(shape) == 3:
+        n = (shape[2], shape[1], shape[0])
+    else:
+        raise ValueError("grid must be 2D or 3D")
+    return (ctypes.c_int64 * 3)(*n)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, r: int, boundary: int,
+          steps: int, adjoint: bool = False) -> np.ndarray:
+    """`steps` applications of the linear stencil (or its transpose) to u."""
+    lib = _load()
+    u64 = _f64(u)
+    c64 = _f64(coeffs)
+    ndim = u64.ndim
+    if c64.size != (2 * r + 1) ** ndim:
+        raise ValueError("coefficient array must be dense (2r+1)^ndim")
+    out = np.empty_like(u64)
+    fn = lib.oracle_sweep_adjoint if adjoint else lib.oracle_sweep
+    _check(fn(ndim, _n3(u64.shape), shape, r, _ptr(c64), boundary, steps, _ptr(u64), _ptr(out)),
+           "sweep")
+    return out
+
+
+def fd2_weights(r: int) -> np.ndarray:
+    w = np.empty(r + 1, dtype=np.float64)
+    _check(_load().oracle_fd2_weights(r, _ptr(w)), "fd2_weights")
+    return w
+
+
+def laplacian3d(r: int = 4) -> np.ndarray:
+    d = np.empty((2 * r + 1) ** 3, dtype=np.float64)
+    _check(_load().oracle_laplacian3d(r, _ptr(d)), "laplacian3d")
+    return d
+
+
+def wave_forward(u_prev, u0, kappa, steps: int, r: int = 4, boundary: int = 1,
+                 lap: Optional[np.ndarray] = None, src=None, wavelet=None,
+                 rec_z: int = -1):
+    """Leapfrog forward.  Returns (u_{T-1}, u_T, traces or None)."""
+    lib = _load()
+    a = _f64(u_prev).copy()
+    b = _f64(u0).copy()
+    k = _f64(kappa)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    nz, ny, nx = b.shape
+    srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
+    wv = _f64(wavelet) if wavelet is not None else None
+    traces = np.zeros((steps, ny, nx), dtype=np.float64) if rec_z >= 0 else None
+    _check(lib.oracle_wave_forward(_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k),
+                                   _ptr(a), _ptr(b), srcp, _ptr(wv) if wv is not None else None,
+                                   rec_z, _ptr(traces) if traces is not None else None),
+           "wave_forward")
+    return a, b, traces
+
+
+def wave_adjoint(a_in, b_in, kappa, steps: int, r: int = 4, boundary: int = 1,
+                 lap: Optional[np.ndarray] = None):
+    """Transpose of (u_{-1}, u_0) -> (u_{T-1}, u_T).  (a, b) are the co-states
+    of (u_{T-1}, u_T); returns the co-states of (u_{-1}, u_0)."""
+    lib = _load()
+    a = _f64(a_in).copy()
+    b = _f64(b_in).copy()
+    k = _f64(kappa)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    _check(lib.oracle_wave_adjoint(_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k),
+                                   _ptr(a), _ptr(b)), "wave_adjoint")
+    return a, b
+
+
+def wave_gradient(u_prev0, u0, kappa, steps: int, src, wavelet, rec_z: int, target,
+                  ckpt_every: int = 0, r: int = 4, boundary: int = 1,
+                  lap: Optional[np.ndarray] = None):
+    """(dJ/dkappa, J) for J = 1/2 sum_t ||u_t[rec_z] - target[t-1]||^2."""
+    lib = _load()
+    k = _f64(kappa)
+    up = _f64(u_prev0)
+    u = _f64(u0)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    tg = _f64(target)
+    wv = _f64(wavelet)
+    grad = np.empty_like(k)
+    loss = ctypes.c_double(0.0)
+    srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
+    _check(lib.oracle_wave_gradient(_n3(k.shape), r, _ptr(lp), boundary, steps, _ptr(k),
+                                    _ptr(up), _ptr(u), srcp, _ptr(wv), rec_z, _ptr(tg),
+                                    ckpt_every, _ptr(grad), ctypes.byref(loss)),
+           "wave_gradient")
+    return grad, float(loss.value)
