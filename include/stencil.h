@@ -1,0 +1,214 @@
+/*
+ * stencil.h - C ABI of libstencil, repeated stencil sweeps on AMD MI355X.
+ *
+ * A case is the pair (offset geometry S, coefficients c_d) driving a
+ * time-stepped sweep over a regular grid (Section 2.1, the linear
+ * constant-coefficient form of the update rule):
+ *
+ *     u^{t+1}(x) = sum_{d in S} c_d u^t(B(x + d)),
+ *
+ * where S is a star (offsets along the axes) or a box (the full cube) of
+ * order r = max |d|_inf (Section 2.1, stencil type), and B is the boundary
+ * rule.  Each (dimension, shape, radius, storage precision, boundary, grid
+ * class) case is served by its own specialised kernel chosen through a
+ * dispatch map (Section 4.2, the operator map; Section 7.2.1, dispatch of
+ * configurations to structurally distinct kernels).
+ *
+ * Conventions shared by every entry point
+ *  - Layout: row-major, x unit-stride.  2D grids are [ny][nx], 3D grids are
+ *    [nz][ny][nx]; n[0] = nx, n[1] = ny, n[2] = nz (n[2] = 1 in 2D).
+ *  - Coefficients: a HOST array of (2r+1)^ndim floats ordered (dz, dy, dx)
+ *    lexicographically with dx fastest.  Entries outside the shape must be
+ *    zero.  The plan copies them; the caller keeps ownership.
+ *  - Storage: ST_F32 or ST_F16 (IEEE binary16).  Arithmetic is always FP32;
+ *    fp16 results are rounded to nearest even once per time step.
+ *  - Device buffers: every pointer named "device" is memory the CALLER
+ *    allocated on the current HIP device and still owns.  The library never
+ *    allocates device memory; scratch space comes from the caller's
+ *    workspace, sized by stencil_workspace_bytes().
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls are asynchronous on that stream unless stated.
+ *  - Errors: every call returns a status.  Argument and shape errors are
+ *    detected on the host before any HIP call.  Kernel faults surface at the
+ *    caller's next synchronisation.  stencil_last_error() returns a
+ *    thread-local message for the most recent failure.  The library never
+ *    aborts the process.
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ST_OK = 0,
+    ST_EINVAL = 1,        /* null pointer, bad enum, negative steps, bad opts */
+    ST_ESHAPE = 2,        /* grid extent too small for the radius, or too large */
+    ST_EUNSUPPORTED = 3,  /* legal but not provided (e.g. 3D box r > 1, fp16 wave) */
+    ST_EWORKSPACE = 4,    /* workspace missing or smaller than required */
+    ST_EHIP = 5,          /* a HIP runtime call or kernel launch failed */
+    ST_ENOMEM = 6,        /* host allocation failed */
+    ST_ETUNE = 7          /* autotuning found no candidate that passed parity */
+} st_status;
+
+typedef enum { ST_F32 = 0, ST_F16 = 1 } st_dtype;
+typedef enum { ST_PERIODIC = 0, ST_ZERO = 1 } st_boundary;
+typedef enum { ST_STAR = 0, ST_BOX = 1 } st_shape;
+
+/* ST_LINEAR: the weighted-sum sweep above.
+ * ST_WAVE:   acoustic leapfrog u_{t+1} = 2 u_t - u_{t-1} + kappa (.) L(u_t),
+ *            L a star stencil, kappa a per-cell coefficient field (Section
+ *            2.1: a spatially varying coefficient is one more array to read). */
+typedef enum { ST_LINEAR = 0, ST_WAVE = 1 } st_update;
+
+/* Kernel families a dispatch-map entry can name. */
+typedef enum {
+    ST_VARIANT_AUTO = 0,  /* let the dispatch map choose */
+    ST_VARIANT_TB2D = 1,  /* 2D LDS tile, k fused time steps per launch */
+    ST_VARIANT_ZM3D = 2,  /* 3D plane-streaming (z-march) with register queues */
+    ST_VARIANT_WAVE3D = 3 /* 3D leapfrog z-march, fused source/receiver */
+} st_variant;
+
+typedef struct st_plan st_plan;   /* opaque; immutable after creation */
+
+typedef struct {
+    int32_t ndim;          /* 2 or 3 */
+    int64_t n[3];          /* nx, ny, nz */
+    int32_t shape;         /* st_shape */
+    int32_t radius;        /* 1..4; box: r <= 2 in 2D, r == 1 in 3D */
+    const float *coeffs;   /* HOST, (2r+1)^ndim dense; for ST_WAVE may be NULL,
+                              meaning the central second-difference Laplacian
+                              of accuracy order 2r */
+    int32_t dtype;         /* st_dtype (ST_WAVE requires ST_F32) */
+    int32_t boundary;      /* st_boundary */
+    int32_t update;        /* st_update (ST_WAVE requires ndim 3, star) */
+} st_problem;
+
+/* Per-plan overrides.  Zero fields mean "dispatch map decides". */
+typedef struct {
+    int32_t variant;       /* st_variant */
+    int32_t tile_x;        /* TB2D: output tile width (multiple of 64) */
+    int32_t tile_y;        /* TB2D: output tile height; ZM3D/WAVE3D: rows per workgroup */
+    int32_t tsteps;        /* TB2D: time steps fused per launch (1..16) */
+    int32_t zchunk;        /* ZM3D/WAVE3D: planes per workgroup (0 = whole depth) */
+    int32_t ckpt_every;    /* wave gradient checkpoint interval (0 = 20) */
+} st_plan_opts;
+
+/* Extra operands of an ST_WAVE plan. */
+typedef struct {
+    void *u_prev;          /* device, cells: u_{-1} on entry, u_{T-1} on exit */
+    const float *kappa;    /* device, cells */
+    int64_t src[3];        /* point source (x, y, z); src[0] < 0 = none */
+    const float *wavelet;  /* device, steps: wavelet[t] is added at src to u_{t+1} */
+    int64_t rec_z;         /* receiver plane z index, -1 = none */
+    float *traces;         /* device, steps*ny*nx or NULL: traces[t] = plane rec_z of u_{t+1} */
+    const float *target;   /* device, steps*ny*nx: observed traces d (gradient only) */
+} st_wave_args;
+
+/* Create a plan.  Validates the problem (ST_EINVAL / ST_ESHAPE /
+ * ST_EUNSUPPORTED before any device work), classifies the case, looks up the
+ * dispatch map (compiled-in defaults, then the tuning cache file named by the
+ * STENCIL_TUNE_CACHE environment variable, then `opts`) and keeps a host copy
+ * of the coefficients.  `opts` may be NULL.  On success *out owns the plan. */
+st_status stencil_plan(const st_problem *problem, const st_plan_opts *opts, st_plan **out);
+
+/* Release a plan.  NULL-safe. */
+void stencil_plan_destroy(st_plan *plan);
+
+/* Bytes of device workspace an operation needs for `steps` steps.
+ * mode 0 = stencil_apply / stencil_apply_adjoint / stencil_apply_batched,
+ * 1 = stencil_wave_gradient, 2 = stencil_autotune scratch.
+ * Returns 0 for a NULL plan. */
+size_t stencil_workspace_bytes(const st_plan *plan, int32_t steps, int32_t mode);
+
+/* The variant, tile and temporal depth the plan dispatches to (any pointer
+ * may be NULL).  Host only. */
+st_status stencil_plan_describe(const st_plan *plan, int32_t *variant, int32_t *tile_x,
+                                int32_t *tile_y, int32_t *tsteps, int32_t *zchunk);
+
+/* Forward sweep, `steps` time steps (Section 2.1 update rule, iterated).
+ *  ST_LINEAR: u_out = A^steps u_in.  u_in == u_out is allowed; other overlap
+ *             is not.  `wave` must be NULL.
+ *  ST_WAVE:   u_in = u_0 and wave->u_prev = u_{-1}; on return u_out = u_T and
+ *             wave->u_prev = u_{T-1}.  Source and receiver are optional.
+ * Device buffers hold n[0]*n[1]*n[2] values of the plan's storage type.
+ * steps == 0 copies u_in to u_out. */
+st_status stencil_apply(const st_plan *plan, const void *u_in, void *u_out, int32_t steps,
+                        const st_wave_args *wave, void *workspace, size_t ws_bytes,
+                        void *stream);
+
+/* Transposed sweep.
+ *  ST_LINEAR: v_out = (A^T)^steps v_in, (A^T v)(x) = sum_d c_d v(B(x - d)).
+ *  ST_WAVE:   transpose of the linear state map (u_{-1}, u_0) -> (u_{T-1}, u_T)
+ *             (no source): on entry v_in and wave->u_prev are the co-states of
+ *             u_T and u_{T-1}; on return v_out and wave->u_prev are the
+ *             co-states of u_0 and u_{-1}.
+ * Same buffer rules as stencil_apply. */
+st_status stencil_apply_adjoint(const st_plan *plan, const void *v_in, void *v_out,
+                                int32_t steps, const st_wave_args *wave, void *workspace,
+                                size_t ws_bytes, void *stream);
+
+/* Gradient of J = 1/2 sum_{t=1..T} || u_t[z = rec_z] - target[t-1] ||^2 with
+ * respect to kappa for an ST_WAVE plan, by the discrete adjoint of the
+ * leapfrog, recomputing states from (u_{t-1}, u_t) checkpoints taken every
+ * ckpt_every steps.  u0 / wave->u_prev give u_0 / u_{-1} (not modified);
+ * wave->src, wavelet, rec_z (required >= 0) and target are used; traces, if
+ * non-NULL, receive the recorded traces.  dkappa (device, cells) is
+ * overwritten; *loss_dev (device, one double) receives J.  Workspace from
+ * stencil_workspace_bytes(plan, steps, 1). */
+st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wave_args *wave,
+                                int32_t steps, float *dkappa, double *loss_dev,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* Batched plan over `count` independent 2D ST_LINEAR problems of one storage
+ * type (shapes, radii, extents and coefficients may differ).  Each member
+ * is dispatched through the map like a single plan.  *out owns the plan. */
+st_status stencil_plan_batched(const st_problem *problems, int32_t count,
+                               const st_plan_opts *opts, st_plan **out);
+
+/* All members advanced `steps` steps in ONE persistent launch: a device work
+ * queue of (member, tile, time block) items, each waiting only on the
+ * previous time block of its own member.  u_in / u_out are HOST arrays of
+ * `count` device pointers (u_in[i] == u_out[i] allowed).  Workspace from
+ * stencil_workspace_bytes(batched_plan, steps, 0). */
+st_status stencil_apply_batched(const st_plan *plan, const void *const *u_in,
+                                void *const *u_out, int32_t steps, void *workspace,
+                                size_t ws_bytes, void *stream);
+
+/* Outcome of the last stencil_apply_batched on this plan, valid once its
+ * stream has synchronised: ST_OK, or ST_EHIP if a dependency wait exceeded
+ * its bound (STENCIL_BATCH_WAIT_MS, default 2000 ms) and the launch stopped
+ * early with incomplete outputs.  *items_done (nullable) receives the number
+ * of queue items pulled. */
+st_status stencil_batched_status(const st_plan *plan, int32_t *items_done);
+
+/* Autotune: for every distinct case of the plan (one, or each batch
+ * member), time the legal candidates (tile shape, fused time steps, rows per
+ * workgroup, plane chunk), reject any candidate whose output differs from
+ * the plain single-step kernel on a probe grid, keep the fastest, write it
+ * into the plan and into the dispatch map, and append it to the tuning cache
+ * file when STENCIL_TUNE_CACHE is set.  `scratch` (device) must hold
+ * stencil_workspace_bytes(plan, 0, 2) bytes.  Synchronises `stream`.
+ * Setting STENCIL_TUNE_FAULT=1 deliberately perturbs the coefficients of part
+ * of the candidates (fused-step or 32-row ones) so tests can check that the
+ * parity filter rejects wrong-but-faster candidates. */
+st_status stencil_autotune(st_plan *plan, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Counts from the plan's last stencil_autotune: candidates tried and
+ * candidates rejected by the parity check.  Host only. */
+st_status stencil_autotune_stats(const st_plan *plan, int32_t *tried, int32_t *rejected);
+
+/* Message for the most recent failing call on this thread ("" if none). */
+const char *stencil_last_error(void);
+
+/* Library version string. */
+const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STENCIL_H */

@@ -1,0 +1,304 @@
+// Autotuner: fills the dispatch map by measurement.
+//
+// Numeric parameter sweeps run as a deterministic program outside the kernel
+// code (Section 4.3).  For each distinct case of a plan the legal candidates
+// (tile shape, fused time steps, rows per workgroup, plane chunk) are each
+// checked against the plain single-step configuration on a probe grid; a
+// candidate whose output differs is rejected before it is timed (an
+// incorrect-but-faster result must never win, Section 6.2's correctness gate).
+// Survivors are timed with HIP events (median of five) on the real extent and
+// the fastest is written into the plan and the dispatch map.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "plan.h"
+
+namespace stk {
+
+__device__ __forceinline__ float hash_unit(uint32_t i, uint32_t seed) {
+    uint32_t h = i * 0x9E3779B1u ^ (seed * 0x85EBCA77u + 0x165667B1u);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+template <typename T>
+__global__ void fill_random(T* p, size_t n, uint32_t seed, float lo, float hi) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = from_f32<T>(lo + (hi - lo) * hash_unit((uint32_t)i, seed));
+}
+
+// out[0] = max |a - b|, out[1] = max |b|; values are non-negative floats, so
+// their bit patterns order like unsigned integers.
+template <typename T>
+__global__ void max_diff(const T* a, const T* b, size_t n, unsigned* out) {
+    float d = 0.f, m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float x = to_f32(a[i]), y = to_f32(b[i]);
+        const float e = fabsf(x - y);
+        d = (e > d || e != e) ? (e != e ? INFINITY : e) : d;
+        m = fmaxf(m, fabsf(y));
+    }
+    atomicMax(&out[0], __float_as_uint(d));
+    atomicMax(&out[1], __float_as_uint(m));
+}
+
+__global__ void zero_u32(unsigned* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+}  // namespace stk
+
+using namespace stk;
+
+namespace {
+
+struct TuneStats {
+    int tried = 0, rejected = 0;
+};
+
+size_t esize(int dtype) { return dtype == ST_F16 ? 2 : 4; }
+
+hipError_t fill(void* p, const st_problem& pr, size_t cells, uint32_t seed, float lo, float hi,
+                hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<size_t>(8192, (cells + 255) / 256);
+    if (pr.dtype == ST_F16)
+        hipLaunchKernelGGL(fill_random<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)p, cells, seed, lo, hi);
+    else
+        hipLaunchKernelGGL(fill_random<float>, dim3(blocks), dim3(256), 0, s, (float*)p, cells, seed, lo, hi);
+    return hipGetLastError();
+}
+
+std::vector<LaunchCfg> candidates(const st_problem& p) {
+    std::vector<LaunchCfg> out;
+    if (p.update == ST_WAVE || p.ndim == 3) {
+        const int var = p.update == ST_WAVE ? ST_VARIANT_WAVE3D : ST_VARIANT_ZM3D;
+        for (int ty : {8, 16, 32})
+            for (int zc : {32, 64, 128, 0}) {
+                if (zc != 0 && zc >= p.n[2]) continue;
+                LaunchCfg c{var, 0, ty, 1, zc};
+                out.push_back(c);
+            }
+        return out;
+    }
+    for (int tx : {64, 128, 256})
+        for (int ty : {16, 32, 64})
+            for (int k : {1, 2, 4, 8}) {
+                if (tx > 2 * p.n[0] + 64 || ty > 2 * p.n[1] + 16) continue;
+                LaunchCfg c{ST_VARIANT_TB2D, tx, ty, k, 0};
+                if (cfg_legal(p, c)) out.push_back(c);
+            }
+    return out;
+}
+
+// `steps` steps of configuration c (linear: ping-pong in/tmp ending in out;
+// wave: forward leapfrog with prev = tmp).  Taps may be perturbed.
+hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, const Taps& taps,
+                   const void* in, void* out, void* tmp, const float* kappa, int steps,
+                   hipStream_t s) {
+    Geom g = geom_of(p);
+    if (p.update == ST_WAVE) {
+        const float* prev = (const float*)tmp;
+        const float* cur = (const float*)in;
+        for (int t = 0; t < steps; ++t) {
+            WaveLaunch w;
+            memset(&w, 0, sizeof w);
+            w.src_x = -1;
+            w.rec_z = -1;
+            w.prev = prev;
+            w.cur = cur;
+            w.next = ((steps - t - 1) % 2 == 0) ? (float*)out : (float*)tmp;
+            w.kappa = kappa;
+            hipError_t e = launch_wave3d(g, c, taps, pl->taps, kWaveFwd, w, s);
+            if (e != hipSuccess) return e;
+            prev = cur;
+            cur = w.next;
+        }
+        return hipSuccess;
+    }
+    const int k = p.ndim == 2 ? std::max(1, c.tsteps) : 1;
+    const int L = (steps + k - 1) / k;
+    const void* cur = in;
+    int done = 0;
+    for (int j = 1; j <= L; ++j) {
+        const int kj = std::min(k, steps - done);
+        void* dst = ((L - j) % 2 == 0) ? out : tmp;
+        hipError_t e = p.ndim == 2 ? launch_tb2d(g, c, taps, cur, dst, kj, s)
+                                   : launch_zm3d(g, c, taps, cur, dst, s);
+        if (e != hipSuccess) return e;
+        cur = dst;
+        done += kj;
+    }
+    return hipSuccess;
+}
+
+bool faulty(const st_problem& p, const LaunchCfg& c) {
+    const char* f = getenv("STENCIL_TUNE_FAULT");
+    if (!f || f[0] != '1') return false;
+    if (p.ndim == 2 && p.update == ST_LINEAR) return c.tsteps > 1;
+    return c.tile_y == 32;
+}
+
+st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, TuneStats& st) {
+    const st_problem& p = pl->prob;
+    const size_t cells = (size_t)p.n[0] * p.n[1] * p.n[2];
+    const size_t gb = (cells * esize(p.dtype) + 255) / 256 * 256;
+    // Scratch: in, out, tmp, ref (each a full grid), kappa, 2 counters.
+    const size_t kb = p.update == ST_WAVE ? gb : 0;
+    if (bytes < 4 * gb + kb + 64) {
+        set_error("autotune scratch of %zu bytes needed", 4 * gb + kb + 64);
+        return ST_EWORKSPACE;
+    }
+    char* in = scratch;
+    char* out = scratch + gb;
+    char* tmp = scratch + 2 * gb;
+    char* ref = scratch + 3 * gb;
+    float* kappa = (float*)(scratch + 4 * gb);
+    unsigned* cnt = (unsigned*)(scratch + 4 * gb + kb);
+    const int steps = p.update == ST_WAVE ? 2 : (p.ndim == 2 ? 8 : 2);
+    const float lo = p.update == ST_WAVE ? -1.f : 0.f;
+#define T_TRY(e)                                                                         \
+    do {                                                                                 \
+        hipError_t e_ = (e);                                                             \
+        if (e_ != hipSuccess) {                                                          \
+            set_error("autotune: %s: %s", #e, hipGetErrorString(e_));                    \
+            return ST_EHIP;                                                              \
+        }                                                                                \
+    } while (0)
+    if (p.update == ST_WAVE) {
+        st_problem kp = p;
+        kp.dtype = ST_F32;
+        T_TRY(fill(kappa, kp, cells, 7u, 0.05f, 0.2f, s));
+    }
+    T_TRY(fill(in, p, cells, 1u, lo, 1.f, s));
+    T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
+    LaunchCfg plain = candidates(p).front();
+    if (p.ndim == 2 && p.update == ST_LINEAR) plain = LaunchCfg{ST_VARIANT_TB2D, 64, 32, 1, 0};
+    else plain.zchunk = 0;
+    T_TRY(run_cfg(p, pl, plain, pl->taps, in, ref, tmp, kappa, steps, s));
+
+    hipEvent_t e0, e1;
+    T_TRY(hipEventCreate(&e0));
+    T_TRY(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    LaunchCfg best = pl->cfg;
+    bool any = false;
+    for (const LaunchCfg& c : candidates(p)) {
+        ++st.tried;
+        Taps taps = pl->taps;
+        if (faulty(p, c)) taps.c[0] += 0.25f;
+        // Parity: same inputs (tmp is the wave's u_{-1}; refill it each time).
+        T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
+        T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
+        unsigned h[2] = {0u, 0u};
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 2);
+        const unsigned blocks = (unsigned)std::min<size_t>(4096, (cells + 255) / 256);
+        if (p.dtype == ST_F16)
+            hipLaunchKernelGGL(max_diff<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)out,
+                               (const _Float16*)ref, cells, cnt);
+        else
+            hipLaunchKernelGGL(max_diff<float>, dim3(blocks), dim3(256), 0, s, (const float*)out,
+                               (const float*)ref, cells, cnt);
+        T_TRY(hipGetLastError());
+        T_TRY(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+        T_TRY(hipStreamSynchronize(s));
+        float dmax, rmax;
+        memcpy(&dmax, &h[0], 4);
+        memcpy(&rmax, &h[1], 4);
+        const float tol = (p.dtype == ST_F16 ? 2e-3f : 1e-5f) * std::max(rmax, 1e-30f);
+        if (!(dmax <= tol)) {
+            ++st.rejected;
+            continue;
+        }
+        // Timing on the real extent, median of five.
+        std::vector<float> ms;
+        for (int rep = 0; rep < 6; ++rep) {
+            T_TRY(hipEventRecord(e0, s));
+            T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
+            T_TRY(hipEventRecord(e1, s));
+            T_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            T_TRY(hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+            any = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+#undef T_TRY
+    if (!any) {
+        set_error("autotune: no candidate passed parity");
+        return ST_ETUNE;
+    }
+    pl->cfg = best;
+    dispatch_store(classify(p), best, true);
+    return ST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, void* stream) {
+    set_error("%s", "");
+    if (!plan) {
+        set_error("plan is NULL");
+        return ST_EINVAL;
+    }
+    if (!scratch) {
+        set_error("scratch is NULL");
+        return ST_EWORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    TuneStats st;
+    if (!plan->batched) {
+        st_status r = tune_one(plan, (char*)scratch, scratch_bytes, s, st);
+        plan->tune_tried = st.tried;
+        plan->tune_rejected = st.rejected;
+        return r;
+    }
+    // One measurement per distinct case key; members of that key adopt it.
+    std::vector<std::pair<CaseKey, LaunchCfg>> done;
+    for (st_plan* m : plan->members) {
+        const CaseKey k = classify(m->prob);
+        bool found = false;
+        for (auto& d : done)
+            if (!memcmp(&d.first, &k, sizeof k)) {
+                m->cfg = d.second;
+                found = true;
+                break;
+            }
+        if (found) continue;
+        st_status r = tune_one(m, (char*)scratch, scratch_bytes, s, st);
+        if (r != ST_OK) return r;
+        done.push_back({k, m->cfg});
+    }
+    plan->tune_tried = st.tried;
+    plan->tune_rejected = st.rejected;
+    return ST_OK;
+}
+
+st_status stencil_autotune_stats(const st_plan* plan, int32_t* tried, int32_t* rejected) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return ST_EINVAL;
+    }
+    if (tried) *tried = plan->tune_tried;
+    if (rejected) *rejected = plan->tune_rejected;
+    return ST_OK;
+}
+
+}  // extern "C"

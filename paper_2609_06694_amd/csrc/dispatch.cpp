@@ -1,0 +1,170 @@
+// Dispatch map: case key -> kernel family and launch parameters.
+//
+// The map plays the role of the paper's operator map (Section 4.2): one cell
+// per (dimension, stencil shape, radius, precision, boundary, update, grid
+// class), each naming the structure that serves the case.  Compiled-in
+// defaults cover every legal case; the autotuner overwrites cells in process
+// and, when STENCIL_TUNE_CACHE names a file, appends them there so later
+// processes start from the tuned entries.
+#include <mutex>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+
+#include "plan.h"
+
+namespace stk {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+Geom geom_of(const st_problem& p) {
+    Geom g;
+    g.ndim = p.ndim;
+    g.nx = (int)p.n[0];
+    g.ny = (int)p.n[1];
+    g.nz = (int)p.n[2];
+    g.shape = p.shape;
+    g.r = p.radius;
+    g.dtype = p.dtype;
+    g.boundary = p.boundary;
+    return g;
+}
+
+CaseKey classify(const st_problem& p) {
+    CaseKey k;
+    k.ndim = p.ndim;
+    k.shape = p.shape;
+    k.r = p.radius;
+    k.dtype = p.dtype;
+    k.boundary = p.boundary;
+    k.update = p.update;
+    const double cells = (double)p.n[0] * (double)p.n[1] * (double)p.n[2];
+    k.size_class = cells <= (double)(1 << 20) ? 0 : (cells <= (double)(1 << 24) ? 1 : 2);
+    int64_t lo = p.n[0], hi = p.n[0];
+    for (int a = 1; a < p.ndim; ++a) {
+        lo = p.n[a] < lo ? p.n[a] : lo;
+        hi = p.n[a] > hi ? p.n[a] : hi;
+    }
+    k.slab = hi >= 4 * lo ? 1 : 0;
+    return k;
+}
+
+std::string key_string(const CaseKey& k) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
+             k.r, k.dtype == 0 ? "f32" : "f16", k.boundary == kPeriodic ? "periodic" : "zero",
+             k.update == 0 ? "linear" : "wave", k.size_class, k.slab ? " slab" : "");
+    return buf;
+}
+
+static LaunchCfg default_cfg(const CaseKey& k) {
+    LaunchCfg c{};
+    if (k.update == ST_WAVE) {
+        c.variant = ST_VARIANT_WAVE3D;
+        c.tile_y = 16;
+        c.zchunk = 64;
+        return c;
+    }
+    if (k.ndim == 3) {
+        c.variant = ST_VARIANT_ZM3D;
+        c.tile_y = 16;
+        c.zchunk = 64;
+        return c;
+    }
+    c.variant = ST_VARIANT_TB2D;
+    c.tile_x = 64;
+    c.tile_y = 32;
+    // Deeper fusion for small grids (launch-bound), shallower for wide stencils.
+    if (k.size_class == 0) c.tsteps = k.r == 1 ? 8 : (k.r == 2 ? 4 : 2);
+    else c.tsteps = k.r <= 2 ? 4 : 2;
+    if (k.shape == kBox && k.r == 2 && k.size_class > 0) c.tsteps = 2;
+    return c;
+}
+
+struct KeyLess {
+    bool operator()(const CaseKey& a, const CaseKey& b) const {
+        const int va[8] = {a.ndim, a.shape, a.r, a.dtype, a.boundary, a.update, a.size_class, a.slab};
+        const int vb[8] = {b.ndim, b.shape, b.r, b.dtype, b.boundary, b.update, b.size_class, b.slab};
+        return std::lexicographical_compare(va, va + 8, vb, vb + 8);
+    }
+};
+
+static std::mutex g_map_mu;
+static std::map<CaseKey, LaunchCfg, KeyLess> g_map;
+static bool g_cache_loaded = false;
+
+// Cache file format, one entry per line (later lines win):
+//   ndim shape r dtype boundary update size_class slab variant tile_x tile_y tsteps zchunk
+static void load_cache_locked() {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char* path = getenv("STENCIL_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        CaseKey k;
+        LaunchCfg c;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &k.ndim, &k.shape, &k.r, &k.dtype,
+                   &k.boundary, &k.update, &k.size_class, &k.slab, &c.variant, &c.tile_x,
+                   &c.tile_y, &c.tsteps, &c.zchunk) == 13)
+            g_map[k] = c;
+    }
+    fclose(f);
+}
+
+LaunchCfg dispatch_lookup(const CaseKey& k) {
+    std::lock_guard<std::mutex> lk(g_map_mu);
+    load_cache_locked();
+    auto it = g_map.find(k);
+    if (it != g_map.end()) return it->second;
+    return default_cfg(k);
+}
+
+void dispatch_store(const CaseKey& k, const LaunchCfg& c, bool persist) {
+    std::lock_guard<std::mutex> lk(g_map_mu);
+    load_cache_locked();
+    g_map[k] = c;
+    if (!persist) return;
+    const char* path = getenv("STENCIL_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d\n", k.ndim, k.shape, k.r, k.dtype,
+            k.boundary, k.update, k.size_class, k.slab, c.variant, c.tile_x, c.tile_y, c.tsteps,
+            c.zchunk);
+    fclose(f);
+}
+
+bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
+    if (p.update == ST_WAVE) {
+        return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
+               c.zchunk >= 0;
+    }
+    if (p.ndim == 3) {
+        return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
+               c.zchunk >= 0;
+    }
+    if (c.variant != ST_VARIANT_TB2D) return false;
+    if (c.tile_x < kWave || c.tile_x % kWave || c.tile_x > 512) return false;
+    if (c.tile_y < 4 || c.tile_y > 512 || c.tsteps < 1 || c.tsteps > 16) return false;
+    return (int)sizeof(float) * tb2d_lds_floats_host(c.tile_x, c.tile_y, c.tsteps, p.radius) <=
+           tb2d_max_lds_bytes();
+}
+
+}  // namespace stk

@@ -1,0 +1,69 @@
+// Host-side internals shared by the runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace stk {
+
+// Geometry and type of one case, as the launchers need it.
+struct Geom {
+    int ndim;
+    int nx, ny, nz;
+    int shape, r, dtype, boundary;
+};
+
+// Launch parameters chosen by the dispatch map.
+struct LaunchCfg {
+    int variant;   // st_variant
+    int tile_x;    // TB2D output tile width
+    int tile_y;    // TB2D output tile height; ZM3D/WAVE3D rows per workgroup
+    int tsteps;    // TB2D fused time steps
+    int zchunk;    // ZM3D/WAVE3D planes per workgroup (0 = all)
+};
+
+enum WaveMode { kWaveFwd = 0, kWaveAdj = 1, kWaveGrad = 2 };
+
+struct WaveLaunch {
+    const float* prev;      // u_{t-1} (fwd/adj) or lambda_{t+2} (grad)
+    const float* cur;       // u_t (fwd) or lambda_{t+1} (adj, grad)
+    float* next;            // u_{t+1} / lambda_t; may alias prev
+    const float* kappa;
+    const float* u;         // grad: u_t (second stencil field)
+    float* grad;            // grad: dJ/dkappa accumulator
+    const float* target_t;  // grad: d_t plane (ny*nx) or null
+    int rec_z;              // grad: plane of the residual injection; fwd: receiver plane
+    float* trace_t;         // fwd: plane written with u_{t+1}[rec_z] or null
+    int src_x, src_y, src_z;  // fwd: source cell (src_x < 0 = none)
+    const float* src_amp;   // fwd: device pointer to the amplitude added at the source
+    float prev_sign;        // adj: next = 2 cur - prev_sign * prev (-1 on the first step, +1 after)
+};
+
+// Launchers (return the launch status; asynchronous on `stream`).
+hipError_t launch_tb2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                       void* out, int k, hipStream_t stream);
+hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                       void* out, hipStream_t stream);
+hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                         const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
+                         hipStream_t stream);
+hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hipStream_t stream);
+hipError_t launch_fill(float* dst, float v, size_t n, hipStream_t stream);
+// loss = 1/2 sum (traces - target)^2 in double, two fixed-order passes
+// through `parts` (kLossParts doubles of scratch): deterministic.
+constexpr int kLossParts = 512;
+hipError_t launch_trace_loss(const float* traces, const float* target, size_t n, double* parts,
+                             double* loss, hipStream_t stream);
+
+bool tb2d_supported(int r, int shape);
+bool zm3d_supported(int r, int shape);
+bool wave3d_supported(int r);
+int zm3d_rows(const LaunchCfg& cfg);    // rows per workgroup actually used
+int tb2d_max_lds_bytes();
+int tb2d_lds_floats_host(int BX, int BY, int k, int R);
+
+
+}  // namespace stk

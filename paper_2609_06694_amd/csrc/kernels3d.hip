@@ -1,0 +1,150 @@
+// 3D linear sweep (star r = 1..4, box r = 1): plane-streaming z-march.
+#include "internal.h"
+#include "zmarch.h"
+
+namespace stk {
+
+template <int R, int SHAPE, typename T, int BC, int RY>
+__global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in,
+                                                        T* __restrict__ out, int nx, int ny,
+                                                        int nz, int zc, int tiles_x, int tiles_y,
+                                                        Taps tp) {
+    using G = PlaneGeom<R, RY>;
+    __shared__ float tile[2][G::H * G::W];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % tiles_x;
+    const int rest = b / tiles_x;
+    const int tyi = rest % tiles_y, zci = rest / tiles_y;
+    const int x0 = txi * G::BX, y0 = tyi * G::BY;
+    const int z0 = zci * zc, z1 = min(z0 + zc, nz);
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const int gx = x0 + tx;
+
+    constexpr int Q = 2 * R + 1;
+    float acc[Q][RY];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) acc[q][i] = 0.f;
+
+    float vin[RY], vhalo[G::HT];
+    float one_in[RY], one_halo[G::HT];   // unused scale operands
+    load_plane<R, RY, BC>(in, nx, ny, nz, z0 - R, x0, y0, vin, vhalo);
+
+    for (int zp = z0 - R; zp < z1 + R; ++zp) {
+        float* t = tile[zp & 1];
+        store_plane<R, RY, false>(t, vin, vhalo, one_in, one_halo);
+        float cen[RY];
+#pragma unroll
+        for (int i = 0; i < RY; ++i) cen[i] = vin[i];
+        if (zp + 1 < z1 + R) load_plane<R, RY, BC>(in, nx, ny, nz, zp + 1, x0, y0, vin, vhalo);
+        __syncthreads();
+
+        if constexpr (SHAPE == kStar) {
+            float p[RY];
+            star_plane<R, RY>(t, tp, p);
+            // plane zp feeds output zo = zp - dz with weight c_z(dz); slot R - dz
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
+#pragma unroll
+            for (int d = 1; d <= R; ++d) {
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    acc[R - d][i] = fmaf(tp.c[star_z<R>(d)], cen[i], acc[R - d][i]);
+                    acc[R + d][i] = fmaf(tp.c[star_z<R>(-d)], cen[i], acc[R + d][i]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int dx = -R; dx <= R; ++dx) {
+                float col[RY + 2 * R];
+                const float* base = t + (ty * RY) * G::W + R + tx + dx;
+#pragma unroll
+                for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+#pragma unroll
+                for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+                    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                        for (int i = 0; i < RY; ++i)
+                            acc[R - dz][i] = fmaf(tp.c[box3<R>(dz, dy, dx)], col[i + R + dy],
+                                                  acc[R - dz][i]);
+            }
+        }
+
+        // Output plane zp - R has received all 2R+1 planes.
+        const int zo = zp - R;
+        if (zo >= z0 && gx < nx) {
+            T* o = out + (size_t)zo * nx * ny;
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const int gy = y0 + ty * RY + i;
+                if (gy < ny) o[(size_t)gy * nx + gx] = from_f32<T>(acc[0][i]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q - 1; ++q)
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc[q][i] = acc[q + 1][i];
+#pragma unroll
+        for (int i = 0; i < RY; ++i) acc[Q - 1][i] = 0.f;
+    }
+}
+
+bool zm3d_supported(int r, int shape) {
+    if (shape == kStar) return r >= 1 && r <= 4;
+    return r == 1;
+}
+
+int zm3d_rows(const LaunchCfg& cfg) { return cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8); }
+
+template <int R, int SHAPE, typename T, int BC, int RY>
+static hipError_t go(const Geom& g, int zc, const Taps& tp, const void* in, void* out,
+                     hipStream_t s) {
+    using G = PlaneGeom<R, RY>;
+    const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
+    const int nchunks = (g.nz + zc - 1) / zc;
+    hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY>), dim3(tiles_x * tiles_y * nchunks),
+                       dim3(kThreads), 0, s, (const T*)in, (T*)out, g.nx, g.ny, g.nz, zc, tiles_x,
+                       tiles_y, tp);
+    return hipGetLastError();
+}
+
+template <int R, int SHAPE, typename T, int BC>
+static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const void* in,
+                        void* out, hipStream_t s) {
+    const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
+    switch (zm3d_rows(c)) {
+        case 8: return go<R, SHAPE, T, BC, 2>(g, zc, tp, in, out, s);
+        case 16: return go<R, SHAPE, T, BC, 4>(g, zc, tp, in, out, s);
+        default: return go<R, SHAPE, T, BC, 8>(g, zc, tp, in, out, s);
+    }
+}
+
+template <int R, int SHAPE, typename T>
+static hipError_t go_bc(const Geom& g, const LaunchCfg& c, const Taps& tp, const void* in,
+                        void* out, hipStream_t s) {
+    return g.boundary == kPeriodic ? go_ry<R, SHAPE, T, kPeriodic>(g, c, tp, in, out, s)
+                                   : go_ry<R, SHAPE, T, kZero>(g, c, tp, in, out, s);
+}
+
+template <typename T>
+static hipError_t go_t(const Geom& g, const LaunchCfg& c, const Taps& tp, const void* in,
+                       void* out, hipStream_t s) {
+    if (g.shape == kBox) return g.r == 1 ? go_bc<1, kBox, T>(g, c, tp, in, out, s) : hipErrorInvalidValue;
+    switch (g.r) {
+        case 1: return go_bc<1, kStar, T>(g, c, tp, in, out, s);
+        case 2: return go_bc<2, kStar, T>(g, c, tp, in, out, s);
+        case 3: return go_bc<3, kStar, T>(g, c, tp, in, out, s);
+        case 4: return go_bc<4, kStar, T>(g, c, tp, in, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                       void* out, hipStream_t stream) {
+    if (g.dtype == 0) return go_t<float>(g, cfg, taps, in, out, stream);
+    return go_t<_Float16>(g, cfg, taps, in, out, stream);
+}
+
+}  // namespace stk

@@ -1,0 +1,307 @@
+// 3D acoustic leapfrog and its adjoint, fused with source, receiver and the
+// kappa-gradient accumulation (a stencil fused with the physics around it in
+// one launch, Section 4.3).
+//
+//  forward : u_{t+1} = 2 u_t - u_{t-1} + kappa (.) L(u_t)   (+ source, trace)
+//  adjoint : l_t = 2 l_{t+1} - s * l_{t+2} + L^T(kappa (.) l_{t+1})
+//  gradient: the adjoint step plus the receiver residual injection
+//            l_t += [z = rec] (u_t - d_t), and g += l_{t+1} (.) L(u_t)
+//
+// L is a star of radius R held in `tp` (transposed taps for the adjoint).
+// Every field is f32; the output may alias the pointwise `prev` operand
+// because each cell of prev is read only by the thread that writes it.
+#include "internal.h"
+#include "zmarch.h"
+
+namespace stk {
+
+template <int MODE, int R, int BC, int RY>
+__global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, int ny, int nz,
+                                                          int zc, int tiles_x, int tiles_y,
+                                                          Taps tp, Taps tp2) {
+    using G = PlaneGeom<R, RY>;
+    constexpr bool TWO = (MODE == kWaveGrad);       // second stencil field u_t
+    constexpr bool SCALE = (MODE != kWaveFwd);      // first field is kappa (.) lambda
+    __shared__ float tile[TWO ? 4 : 2][G::H * G::W];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % tiles_x;
+    const int rest = b / tiles_x;
+    const int tyi = rest % tiles_y, zci = rest / tiles_y;
+    const int x0 = txi * G::BX, y0 = tyi * G::BY;
+    const int z0 = zci * zc, z1 = min(z0 + zc, nz);
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const int gx = x0 + tx;
+    const size_t plane_sz = (size_t)nx * ny;
+
+    constexpr int Q = 2 * R + 1;
+    float acc[Q][RY], acc2[TWO ? Q : 1][RY];
+    float cq[R + 1][RY];      // unscaled first field at planes zp-R..zp
+    float cq2[TWO ? R + 1 : 1][RY];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            acc[q][i] = 0.f;
+            if constexpr (TWO) acc2[q][i] = 0.f;
+        }
+#pragma unroll
+    for (int q = 0; q <= R; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            cq[q][i] = 0.f;
+            if constexpr (TWO) cq2[q][i] = 0.f;
+        }
+
+    float vin[RY], vhalo[G::HT];
+    float kin[RY], khalo[G::HT];
+    float uin[RY], uhalo[G::HT];
+    load_plane<R, RY, BC>(w.cur, nx, ny, nz, z0 - R, x0, y0, vin, vhalo);
+    if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, z0 - R, x0, y0, kin, khalo);
+    if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, z0 - R, x0, y0, uin, uhalo);
+
+    for (int zp = z0 - R; zp < z1 + R; ++zp) {
+        float* t;
+        float* t2 = nullptr;
+        if constexpr (TWO) {
+            t = tile[2 * (zp & 1)];
+            t2 = tile[2 * (zp & 1) + 1];
+        } else {
+            t = tile[zp & 1];
+        }
+        store_plane<R, RY, SCALE>(t, vin, vhalo, kin, khalo);
+        if constexpr (TWO) store_plane<R, RY, false>(t2, uin, uhalo, kin, khalo);
+        float cen[RY];
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            cq[R][i] = vin[i];
+            cen[i] = SCALE ? vin[i] * kin[i] : vin[i];
+            if constexpr (TWO) cq2[R][i] = uin[i];
+        }
+        if (zp + 1 < z1 + R) {
+            load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp + 1, x0, y0, vin, vhalo);
+            if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, zp + 1, x0, y0, kin, khalo);
+            if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, zp + 1, x0, y0, uin, uhalo);
+        }
+        __syncthreads();
+
+        // Pointwise operands of the output plane zo, issued before the compute.
+        const int zo = zp - R;
+        const bool emit = zo >= z0 && gx < nx;
+        float pv[RY], kv[RY], gv[RY];
+        if (emit) {
+            const size_t zoff = (size_t)zo * plane_sz;
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const int gy = y0 + ty * RY + i;
+                const size_t o = zoff + (size_t)(gy < ny ? gy : 0) * nx + gx;
+                pv[i] = w.prev[o];
+                if constexpr (MODE == kWaveFwd) kv[i] = w.kappa[o];
+                if constexpr (TWO) gv[i] = w.grad[o];
+            }
+        }
+
+        {
+            float p[RY];
+            star_plane<R, RY>(t, tp, p);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
+#pragma unroll
+            for (int d = 1; d <= R; ++d)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    acc[R - d][i] = fmaf(tp.c[star_z<R>(d)], cen[i], acc[R - d][i]);
+                    acc[R + d][i] = fmaf(tp.c[star_z<R>(-d)], cen[i], acc[R + d][i]);
+                }
+        }
+        if constexpr (TWO) {
+            float p[RY];
+            star_plane<R, RY>(t2, tp2, p);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc2[R][i] += p[i];
+#pragma unroll
+            for (int d = 1; d <= R; ++d)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    acc2[R - d][i] = fmaf(tp2.c[star_z<R>(d)], cq2[R][i], acc2[R - d][i]);
+                    acc2[R + d][i] = fmaf(tp2.c[star_z<R>(-d)], cq2[R][i], acc2[R + d][i]);
+                }
+        }
+
+        if (emit) {
+            const size_t zoff = (size_t)zo * plane_sz;
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const int gy = y0 + ty * RY + i;
+                if (gy >= ny) continue;
+                const size_t o = zoff + (size_t)gy * nx + gx;
+                float v;
+                if constexpr (MODE == kWaveFwd) {
+                    v = 2.f * cq[0][i] - pv[i] + kv[i] * acc[0][i];
+                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
+                    if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[(size_t)gy * nx + gx] = v;
+                } else if constexpr (MODE == kWaveAdj) {
+                    v = 2.f * cq[0][i] - w.prev_sign * pv[i] + acc[0][i];
+                } else {
+                    v = 2.f * cq[0][i] - pv[i] + acc[0][i];
+                    if (w.target_t != nullptr && zo == w.rec_z)
+                        v += cq2[0][i] - w.target_t[(size_t)gy * nx + gx];
+                    w.grad[o] = fmaf(cq[0][i], acc2[0][i], gv[i]);
+                }
+                w.next[o] = v;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q - 1; ++q)
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                acc[q][i] = acc[q + 1][i];
+                if constexpr (TWO) acc2[q][i] = acc2[q + 1][i];
+            }
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            acc[Q - 1][i] = 0.f;
+            if constexpr (TWO) acc2[Q - 1][i] = 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                cq[q][i] = cq[q + 1][i];
+                if constexpr (TWO) cq2[q][i] = cq2[q + 1][i];
+            }
+    }
+}
+
+bool wave3d_supported(int r) { return r >= 1 && r <= 4; }
+
+template <int MODE, int R, int BC, int RY>
+static hipError_t go(const Geom& g, int zc, const Taps& tp, const Taps& tp2, const WaveLaunch& w,
+                     hipStream_t s) {
+    using G = PlaneGeom<R, RY>;
+    const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
+    const int nchunks = (g.nz + zc - 1) / zc;
+    hipLaunchKernelGGL((wave3d_kernel<MODE, R, BC, RY>), dim3(tiles_x * tiles_y * nchunks),
+                       dim3(kThreads), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+    return hipGetLastError();
+}
+
+template <int MODE, int R, int BC>
+static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                        const WaveLaunch& w, hipStream_t s) {
+    const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
+    switch (zm3d_rows(c)) {
+        case 8: return go<MODE, R, BC, 2>(g, zc, tp, tp2, w, s);
+        case 16: return go<MODE, R, BC, 4>(g, zc, tp, tp2, w, s);
+        default: return go<MODE, R, BC, 8>(g, zc, tp, tp2, w, s);
+    }
+}
+
+template <int MODE, int R>
+static hipError_t go_bc(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                        const WaveLaunch& w, hipStream_t s) {
+    return g.boundary == kPeriodic ? go_ry<MODE, R, kPeriodic>(g, c, tp, tp2, w, s)
+                                   : go_ry<MODE, R, kZero>(g, c, tp, tp2, w, s);
+}
+
+template <int MODE>
+static hipError_t go_r(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                       const WaveLaunch& w, hipStream_t s) {
+    switch (g.r) {
+        case 1: return go_bc<MODE, 1>(g, c, tp, tp2, w, s);
+        case 2: return go_bc<MODE, 2>(g, c, tp, tp2, w, s);
+        case 3: return go_bc<MODE, 3>(g, c, tp, tp2, w, s);
+        case 4: return go_bc<MODE, 4>(g, c, tp, tp2, w, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// `taps` is the stencil applied to the first field: L for the forward step,
+// L^T for the adjoint and gradient steps.  `taps_fwd` (L) is applied to the
+// second field u_t in gradient mode.
+hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                              const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
+                              hipStream_t stream) {
+    switch (mode) {
+        case kWaveFwd: return go_r<kWaveFwd>(g, cfg, taps, taps_fwd, w, stream);
+        case kWaveAdj: return go_r<kWaveAdj>(g, cfg, taps, taps_fwd, w, stream);
+        case kWaveGrad: return go_r<kWaveGrad>(g, cfg, taps, taps_fwd, w, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+__global__ void scale_kernel(float* dst, const float* src, float alpha, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t j = i; j < n; j += stride) dst[j] = alpha * src[j];
+}
+
+hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, stream, dst, src,
+                       alpha, n);
+    return hipGetLastError();
+}
+
+__global__ void fill_kernel(float* dst, float v, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t j = i; j < n; j += stride) dst[j] = v;
+}
+
+hipError_t launch_fill(float* dst, float v, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, stream, dst, v, n);
+    return hipGetLastError();
+}
+
+// Stage 1: workgroup b sums the squared misfit over a fixed strided subset.
+__global__ __launch_bounds__(kThreads) void loss_part_kernel(const float* traces,
+                                                              const float* target, size_t n,
+                                                              double* parts) {
+    __shared__ double red[kThreads];
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kThreads) {
+        const double d = (double)traces[i] - (double)target[i];
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
+// Stage 2: one workgroup adds the partial sums in a fixed order.
+__global__ __launch_bounds__(kThreads) void loss_final_kernel(const double* parts, int nparts,
+                                                               double* loss) {
+    __shared__ double red[kThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) s += parts[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = 0.5 * red[0];
+}
+
+hipError_t launch_trace_loss(const float* traces, const float* target, size_t n, double* parts,
+                             double* loss, hipStream_t stream) {
+    hipLaunchKernelGGL(loss_part_kernel, dim3(kLossParts), dim3(kThreads), 0, stream, traces,
+                       target, n, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(kThreads), 0, stream, parts, kLossParts,
+                       loss);
+    return hipGetLastError();
+}
+
+}  // namespace stk

@@ -1,0 +1,51 @@
+// Plan object and dispatch map (host only).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "internal.h"
+
+struct st_plan {
+    st_problem prob;                // coeffs pointer cleared; see `dense`
+    std::vector<float> dense;       // (2r+1)^ndim coefficients as given
+    stk::Taps taps;                 // compact forward taps
+    stk::Taps taps_t;               // compact transposed taps (offsets negated)
+    stk::LaunchCfg cfg;
+    int ckpt_every;
+    bool batched;
+    std::vector<st_plan*> members;  // batched plans own their members
+    // Batched launch: pinned host staging for the device work tables, and
+    // the event of the last upload (the staging is rewritten only after it).
+    mutable void* stage = nullptr;
+    mutable size_t stage_cap = 0;
+    mutable hipEvent_t stage_event = nullptr;
+    mutable int* status = nullptr;             // pinned: [abort flag, items pulled]
+    int tune_tried = 0, tune_rejected = 0;   // last autotune: candidates, parity rejects
+};
+
+namespace stk {
+
+// Case key of the dispatch map (Section 4.2: the map is indexed by stencil,
+// shape and precision; a cell names the kernel structure that won there).
+struct CaseKey {
+    int ndim, shape, r, dtype, boundary, update;
+    int size_class;   // 0: <= 2^20 cells, 1: <= 2^24, 2: larger
+    int slab;         // 1 if the longest side is >= 4x the shortest
+};
+
+CaseKey classify(const st_problem& p);
+std::string key_string(const CaseKey& k);
+
+// Default entry for a case (compiled in), then the tuning cache file and the
+// in-process table written by the autotuner override it.
+LaunchCfg dispatch_lookup(const CaseKey& k);
+void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
+bool cfg_legal(const st_problem& p, const LaunchCfg& c);
+
+void set_error(const char* fmt, ...);
+size_t batched_meta_bytes(const st_plan* plan, int steps);
+Geom geom_of(const st_problem& p);
+
+}  // namespace stk

@@ -1,0 +1,551 @@
+// C ABI of libstencil: plan creation and validation, single-grid sweeps,
+// transposed sweeps and the checkpointed wave gradient.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "plan.h"
+
+using namespace stk;
+
+namespace stk {
+const char* last_error();
+}
+
+#define ST_FAIL(code, ...)            \
+    do {                              \
+        stk::set_error(__VA_ARGS__);  \
+        return (code);                \
+    } while (0)
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            ST_FAIL(ST_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+    } while (0)
+
+namespace {
+
+constexpr int64_t kMaxExtent = int64_t(1) << 24;
+constexpr double kMaxCells = 68719476736.0;   // 2^36
+
+size_t elem_bytes(int dtype) { return dtype == ST_F16 ? 2 : 4; }
+
+size_t cells_of(const st_problem& p) { return (size_t)p.n[0] * (size_t)p.n[1] * (size_t)p.n[2]; }
+
+size_t grid_bytes(const st_problem& p) { return cells_of(p) * elem_bytes(p.dtype); }
+
+bool in_shape(int ndim, int shape, int r, int idx) {
+    const int w = 2 * r + 1;
+    const int dx = idx % w - r;
+    const int dy = (idx / w) % w - r;
+    const int dz = ndim == 3 ? idx / (w * w) - r : 0;
+    if (shape == ST_BOX) return true;
+    return ((dz != 0) + (dy != 0) + (dx != 0)) <= 1;
+}
+
+// Central second-difference weights of accuracy order 2r (r = 1..4), the
+// standard finite-difference table.
+const double kFd2[4][5] = {
+    {-2.0, 1.0, 0.0, 0.0, 0.0},
+    {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0, 0.0, 0.0},
+    {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0, 0.0},
+    {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0},
+};
+
+void builtin_laplacian(int r, std::vector<float>& dense) {
+    const int w = 2 * r + 1;
+    dense.assign((size_t)w * w * w, 0.f);
+    const double* f = kFd2[r - 1];
+    dense[(size_t)(r * w + r) * w + r] = (float)(3.0 * f[0]);
+    for (int j = 1; j <= r; ++j)
+        for (int s = -1; s <= 1; s += 2) {
+            dense[(size_t)((r + s * j) * w + r) * w + r] = (float)f[j];
+            dense[(size_t)(r * w + r + s * j) * w + r] = (float)f[j];
+            dense[(size_t)(r * w + r) * w + r + s * j] = (float)f[j];
+        }
+}
+
+// Dense (dz,dy,dx) array -> compact kernel taps (layout in common.h).
+Taps pack_taps(int ndim, int shape, int r, const std::vector<float>& dense) {
+    Taps t;
+    memset(&t, 0, sizeof t);
+    const int w = 2 * r + 1;
+    const int rz = ndim == 3 ? r : 0;
+    auto at = [&](int dz, int dy, int dx) {
+        return dense[(size_t)((dz + rz) * w + (dy + r)) * w + (dx + r)];
+    };
+    if (shape == ST_BOX) {
+        for (size_t i = 0; i < dense.size() && i < (size_t)kMaxTaps; ++i) t.c[i] = dense[i];
+        return t;
+    }
+    t.c[0] = at(0, 0, 0);
+    for (int d = -r; d <= r; ++d) {
+        if (d == 0) continue;
+        const int slot = d < 0 ? 1 + (d + r) : r + d;
+        t.c[slot] = at(0, 0, d);
+        t.c[2 * r + slot] = at(0, d, 0);
+        if (ndim == 3) t.c[4 * r + slot] = at(d, 0, 0);
+    }
+    return t;
+}
+
+st_status validate(const st_problem* p) {
+    if (!p) ST_FAIL(ST_EINVAL, "problem is NULL");
+    if (p->ndim != 2 && p->ndim != 3) ST_FAIL(ST_EINVAL, "ndim must be 2 or 3 (got %d)", p->ndim);
+    if (p->shape != ST_STAR && p->shape != ST_BOX) ST_FAIL(ST_EINVAL, "unknown shape %d", p->shape);
+    if (p->dtype != ST_F32 && p->dtype != ST_F16) ST_FAIL(ST_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->boundary != ST_PERIODIC && p->boundary != ST_ZERO)
+        ST_FAIL(ST_EINVAL, "unknown boundary %d", p->boundary);
+    if (p->update != ST_LINEAR && p->update != ST_WAVE) ST_FAIL(ST_EINVAL, "unknown update %d", p->update);
+    if (p->radius < 1 || p->radius > 4) ST_FAIL(ST_EINVAL, "radius must be 1..4 (got %d)", p->radius);
+    for (int a = 0; a < 3; ++a)
+        if (p->n[a] < 1 || p->n[a] > kMaxExtent)
+            ST_FAIL(ST_ESHAPE, "extent n[%d] = %lld outside 1..2^24", a, (long long)p->n[a]);
+    if (p->ndim == 2 && p->n[2] != 1) ST_FAIL(ST_ESHAPE, "2D problem needs n[2] == 1");
+    if ((double)p->n[0] * (double)p->n[1] * (double)p->n[2] > kMaxCells)
+        ST_FAIL(ST_ESHAPE, "grid has more than 2^36 cells");
+    if ((double)p->n[0] * (double)p->n[1] > 2147483647.0)
+        ST_FAIL(ST_ESHAPE, "one plane must hold fewer than 2^31 cells");
+    if (p->update == ST_WAVE) {
+        if (p->ndim != 3 || p->shape != ST_STAR)
+            ST_FAIL(ST_EUNSUPPORTED, "the wave update needs a 3D star stencil");
+        if (p->dtype != ST_F32) ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 storage");
+    } else {
+        if (!p->coeffs) ST_FAIL(ST_EINVAL, "coefficients are NULL");
+        if (p->ndim == 2 && !tb2d_supported(p->radius, p->shape))
+            ST_FAIL(ST_EUNSUPPORTED, "2D %s r=%d is not provided", p->shape == ST_STAR ? "star" : "box",
+                    p->radius);
+        if (p->ndim == 3 && !zm3d_supported(p->radius, p->shape))
+            ST_FAIL(ST_EUNSUPPORTED, "3D %s r=%d is not provided", p->shape == ST_STAR ? "star" : "box",
+                    p->radius);
+    }
+    if (p->coeffs) {
+        const int w = 2 * p->radius + 1;
+        const int count = p->ndim == 3 ? w * w * w : w * w;
+        for (int i = 0; i < count; ++i) {
+            if (!isfinite(p->coeffs[i])) ST_FAIL(ST_EINVAL, "coefficient %d is not finite", i);
+            if (!in_shape(p->ndim, p->shape, p->radius, i) && p->coeffs[i] != 0.f)
+                ST_FAIL(ST_EINVAL, "coefficient %d lies outside the star but is nonzero", i);
+        }
+    }
+    return ST_OK;
+}
+
+st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** out) {
+    st_status s = validate(p);
+    if (s != ST_OK) return s;
+    st_plan* pl = new (std::nothrow) st_plan();
+    if (!pl) ST_FAIL(ST_ENOMEM, "out of host memory");
+    pl->prob = *p;
+    pl->prob.coeffs = nullptr;
+    const int w = 2 * p->radius + 1;
+    const int count = p->ndim == 3 ? w * w * w : w * w;
+    if (p->coeffs) pl->dense.assign(p->coeffs, p->coeffs + count);
+    else builtin_laplacian(p->radius, pl->dense);
+    std::vector<float> flipped(pl->dense.rbegin(), pl->dense.rend());
+    pl->taps = pack_taps(p->ndim, p->shape, p->radius, pl->dense);
+    pl->taps_t = pack_taps(p->ndim, p->shape, p->radius, flipped);
+    pl->cfg = dispatch_lookup(classify(*p));
+    pl->ckpt_every = 20;
+    pl->batched = false;
+    if (opts) {
+        if (opts->ckpt_every < 0) {
+            delete pl;
+            ST_FAIL(ST_EINVAL, "ckpt_every must be >= 0");
+        }
+        if (opts->ckpt_every > 0) pl->ckpt_every = opts->ckpt_every;
+        LaunchCfg c = pl->cfg;
+        if (opts->variant != ST_VARIANT_AUTO) c.variant = opts->variant;
+        if (opts->tile_x > 0) c.tile_x = opts->tile_x;
+        if (opts->tile_y > 0) c.tile_y = opts->tile_y;
+        if (opts->tsteps > 0) c.tsteps = opts->tsteps;
+        if (opts->zchunk > 0) c.zchunk = opts->zchunk;
+        if (!cfg_legal(pl->prob, c)) {
+            delete pl;
+            ST_FAIL(ST_EINVAL, "plan options name an illegal variant/tile/depth for this case");
+        }
+        pl->cfg = c;
+    }
+    *out = pl;
+    return ST_OK;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// One launch of the linear sweep, k fused steps (k = 1 for 3D).
+hipError_t linear_launch(const st_plan* pl, const Taps& taps, const void* in, void* out, int k,
+                         hipStream_t s) {
+    const Geom g = geom_of(pl->prob);
+    if (pl->prob.ndim == 2) return launch_tb2d(g, pl->cfg, taps, in, out, k, s);
+    return launch_zm3d(g, pl->cfg, taps, in, out, s);
+}
+
+// Runs `steps` linear steps from u_in into u_out, rotating through the
+// workspace so the last launch lands in u_out (see the buffer schedule in
+// stencil_apply's documentation).
+st_status run_linear(const st_plan* pl, const Taps& taps, const void* u_in, void* u_out, int steps,
+                     void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t gb = grid_bytes(pl->prob);
+    if (steps == 0) {
+        if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
+    const int k = pl->prob.ndim == 2 ? std::max(1, pl->cfg.tsteps) : 1;
+    const int L = (steps + k - 1) / k;
+    const void* cur = u_in;
+    if (u_in == u_out && (L % 2) == 1) {
+        HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
+        cur = ws;
+    }
+    int done = 0;
+    for (int j = 1; j <= L; ++j) {
+        const int kj = std::min(k, steps - done);
+        void* dst = ((L - j) % 2 == 0) ? u_out : ws;
+        HIP_TRY(linear_launch(pl, taps, cur, dst, kj, s));
+        cur = dst;
+        done += kj;
+    }
+    return ST_OK;
+}
+
+WaveLaunch wave_base() {
+    WaveLaunch w;
+    memset(&w, 0, sizeof w);
+    w.src_x = -1;
+    w.rec_z = -1;
+    w.prev_sign = 1.f;
+    return w;
+}
+
+// Leapfrog (forward or adjoint) over `steps` steps with the buffer schedule
+// b_t = out if (T - t) even else prev_buf, so u_T ends in u_out and u_{T-1}
+// in the caller's prev buffer.
+st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_out, int steps,
+                   const st_wave_args* wa, void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t gb = grid_bytes(pl->prob);
+    float* P = (float*)wa->u_prev;
+    float* O = (float*)u_out;
+    const float* cur = (const float*)u_in;
+    if (steps == 0) {
+        if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    if (u_in == u_out && (steps % 2) == 1) {
+        if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
+        HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
+        cur = (const float*)ws;
+    }
+    const Geom g = geom_of(pl->prob);
+    const float* prev = P;
+    const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1];
+    for (int t = 0; t < steps; ++t) {
+        float* next = ((steps - (t + 1)) % 2 == 0) ? O : P;
+        WaveLaunch w = wave_base();
+        w.prev = prev;
+        w.cur = cur;
+        w.next = next;
+        w.kappa = wa->kappa;
+        if (!adjoint) {
+            if (wa->src[0] >= 0 && wa->wavelet) {
+                w.src_x = (int)wa->src[0];
+                w.src_y = (int)wa->src[1];
+                w.src_z = (int)wa->src[2];
+                w.src_amp = wa->wavelet + t;
+            }
+            if (wa->rec_z >= 0 && wa->traces) {
+                w.rec_z = (int)wa->rec_z;
+                w.trace_t = wa->traces + (size_t)t * plane;
+            }
+            HIP_TRY(launch_wave3d(g, pl->cfg, pl->taps, pl->taps, kWaveFwd, w, s));
+        } else {
+            w.prev_sign = t == 0 ? -1.f : 1.f;
+            HIP_TRY(launch_wave3d(g, pl->cfg, pl->taps_t, pl->taps, kWaveAdj, w, s));
+        }
+        prev = cur;
+        cur = next;
+    }
+    // u_{T-1} (or lambda_1) must end in the caller's prev buffer.
+    if (prev != P) HIP_TRY(hipMemcpyAsync(P, prev, gb, hipMemcpyDeviceToDevice, s));
+    if (adjoint) HIP_TRY(launch_scale(P, P, -1.f, cells_of(pl->prob), s));
+    return ST_OK;
+}
+
+st_status check_wave_args(const st_plan* pl, const st_wave_args* wa, bool need_kappa) {
+    if (!wa) ST_FAIL(ST_EINVAL, "wave plan needs st_wave_args");
+    if (!wa->u_prev) ST_FAIL(ST_EINVAL, "wave->u_prev is NULL");
+    if (need_kappa && !wa->kappa) ST_FAIL(ST_EINVAL, "wave->kappa is NULL");
+    const st_problem& p = pl->prob;
+    if (wa->src[0] >= 0) {
+        for (int a = 0; a < 3; ++a)
+            if (wa->src[a] < 0 || wa->src[a] >= p.n[a]) ST_FAIL(ST_EINVAL, "source outside the grid");
+    }
+    if (wa->rec_z >= p.n[2] || wa->rec_z < -1) ST_FAIL(ST_EINVAL, "receiver plane outside the grid");
+    return ST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stencil_last_error(void) { return stk::last_error(); }
+
+const char* stencil_version(void) { return "libstencil 0.1 (gfx950)"; }
+
+st_status stencil_plan(const st_problem* problem, const st_plan_opts* opts, st_plan** out) {
+    stk::set_error("%s", "");
+    if (!out) ST_FAIL(ST_EINVAL, "out is NULL");
+    *out = nullptr;
+    return build_plan(problem, opts, out);
+}
+
+void stencil_plan_destroy(st_plan* plan) {
+    if (!plan) return;
+    for (st_plan* m : plan->members) stencil_plan_destroy(m);
+    if (plan->stage_event) {
+        (void)hipEventSynchronize(plan->stage_event);
+        (void)hipEventDestroy(plan->stage_event);
+    }
+    if (plan->stage) (void)hipHostFree(plan->stage);
+    if (plan->status) (void)hipHostFree(plan->status);
+    delete plan;
+}
+
+st_status stencil_plan_describe(const st_plan* plan, int32_t* variant, int32_t* tile_x,
+                                int32_t* tile_y, int32_t* tsteps, int32_t* zchunk) {
+    if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
+    const LaunchCfg& c = plan->batched && !plan->members.empty() ? plan->members[0]->cfg : plan->cfg;
+    if (variant) *variant = c.variant;
+    if (tile_x) *tile_x = c.tile_x;
+    if (tile_y) *tile_y = c.tile_y;
+    if (tsteps) *tsteps = c.tsteps;
+    if (zchunk) *zchunk = c.zchunk;
+    return ST_OK;
+}
+
+size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode);
+
+st_status stencil_apply(const st_plan* plan, const void* u_in, void* u_out, int32_t steps,
+                        const st_wave_args* wave, void* workspace, size_t ws_bytes, void* stream) {
+    stk::set_error("%s", "");
+    if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
+    if (plan->batched) ST_FAIL(ST_EINVAL, "batched plan: use stencil_apply_batched");
+    if (!u_in || !u_out) ST_FAIL(ST_EINVAL, "grid pointer is NULL");
+    if (steps < 0) ST_FAIL(ST_EINVAL, "steps must be >= 0");
+    if (plan->prob.update == ST_WAVE) {
+        st_status s = check_wave_args(plan, wave, true);
+        if (s != ST_OK) return s;
+        if (wave->u_prev == u_in || wave->u_prev == u_out)
+            ST_FAIL(ST_EINVAL, "wave->u_prev must not alias u_in or u_out");
+        return run_wave(plan, false, u_in, u_out, steps, wave, workspace, ws_bytes, as_stream(stream));
+    }
+    if (wave) ST_FAIL(ST_EINVAL, "linear plan takes no wave arguments");
+    return run_linear(plan, plan->taps, u_in, u_out, steps, workspace, ws_bytes, as_stream(stream));
+}
+
+st_status stencil_apply_adjoint(const st_plan* plan, const void* v_in, void* v_out, int32_t steps,
+                                const st_wave_args* wave, void* workspace, size_t ws_bytes,
+                                void* stream) {
+    stk::set_error("%s", "");
+    if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
+    if (plan->batched) ST_FAIL(ST_EINVAL, "batched plans have no adjoint entry point");
+    if (!v_in || !v_out) ST_FAIL(ST_EINVAL, "grid pointer is NULL");
+    if (steps < 0) ST_FAIL(ST_EINVAL, "steps must be >= 0");
+    if (plan->prob.update == ST_WAVE) {
+        st_status s = check_wave_args(plan, wave, true);
+        if (s != ST_OK) return s;
+        if (wave->u_prev == v_in || wave->u_prev == v_out)
+            ST_FAIL(ST_EINVAL, "wave->u_prev must not alias v_in or v_out");
+        return run_wave(plan, true, v_in, v_out, steps, wave, workspace, ws_bytes, as_stream(stream));
+    }
+    if (wave) ST_FAIL(ST_EINVAL, "linear plan takes no wave arguments");
+    return run_linear(plan, plan->taps_t, v_in, v_out, steps, workspace, ws_bytes, as_stream(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpointed gradient of the receiver misfit with respect to kappa.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GradLayout {
+    int T, K, S;
+    size_t grid;        // bytes per f32 grid
+    size_t ckpt_off;    // 2*(S-1) grids: checkpoints of segments 1..S-1
+    size_t states_off;  // K grids: u_{t0+1}..u_{t0+K} of the segment being reversed
+    size_t scratch_off; // 3 grids: forward rotation
+    size_t lam_off;     // 2 grids: adjoint ping-pong
+    size_t traces_off;  // T planes
+    size_t part_off;    // loss partial sums
+    size_t total;
+};
+
+GradLayout grad_layout(const st_plan* pl, int steps) {
+    GradLayout L;
+    L.T = steps;
+    L.K = std::max(1, std::min(pl->ckpt_every, std::max(1, steps)));
+    L.S = (steps + L.K - 1) / L.K;
+    const size_t align = 256;
+    L.grid = (cells_of(pl->prob) * 4 + align - 1) / align * align;
+    const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1] * 4;
+    size_t off = 0;
+    L.ckpt_off = off;
+    off += (size_t)2 * std::max(0, L.S - 1) * L.grid;
+    L.states_off = off;
+    off += (size_t)L.K * L.grid;
+    L.scratch_off = off;
+    off += 3 * L.grid;
+    L.lam_off = off;
+    off += 2 * L.grid;
+    L.traces_off = off;
+    off += ((size_t)steps * plane + align - 1) / align * align;
+    L.part_off = off;
+    off += sizeof(double) * kLossParts;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode) {
+    if (!plan) return 0;
+    if (plan->batched && mode == 2) {
+        size_t m = 0;
+        for (const st_plan* x : plan->members) m = std::max(m, stencil_workspace_bytes(x, 0, 2));
+        return m;
+    }
+    if (plan->batched) {
+        size_t total = 0;
+        for (const st_plan* m : plan->members) total += (grid_bytes(m->prob) + 255) / 256 * 256;
+        return total + batched_meta_bytes(plan, steps);
+    }
+    if (mode == 1) return plan->prob.update == ST_WAVE && steps > 0 ? grad_layout(plan, steps).total : 0;
+    if (mode == 2) {
+        const size_t gb = (grid_bytes(plan->prob) + 255) / 256 * 256;
+        const size_t kb = plan->prob.update == ST_WAVE ? gb : 0;
+        return 4 * gb + kb + 64;
+    }
+    return grid_bytes(plan->prob);
+}
+
+st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wave_args* wave,
+                                int32_t steps, float* dkappa, double* loss_dev, void* workspace,
+                                size_t ws_bytes, void* stream) {
+    stk::set_error("%s", "");
+    if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
+    if (plan->prob.update != ST_WAVE) ST_FAIL(ST_EINVAL, "gradient needs a wave plan");
+    if (!u0 || !dkappa || !loss_dev) ST_FAIL(ST_EINVAL, "u0, dkappa and loss must be non-NULL");
+    if (steps < 1) ST_FAIL(ST_EINVAL, "steps must be >= 1");
+    st_status st = check_wave_args(plan, wave, true);
+    if (st != ST_OK) return st;
+    if (wave->rec_z < 0 || !wave->target) ST_FAIL(ST_EINVAL, "gradient needs rec_z >= 0 and target");
+    const GradLayout L = grad_layout(plan, steps);
+    if (!workspace || ws_bytes < L.total)
+        ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", L.total);
+    hipStream_t s = as_stream(stream);
+    char* ws = (char*)workspace;
+    const Geom g = geom_of(plan->prob);
+    const size_t plane = (size_t)plan->prob.n[0] * plan->prob.n[1];
+    const int T = L.T, K = L.K, S = L.S;
+    auto ckpt = [&](int seg, int which) -> float* {   // seg >= 1; which 0 = u_{sK-1}, 1 = u_{sK}
+        return (float*)(ws + L.ckpt_off + (size_t)(2 * (seg - 1) + which) * L.grid);
+    };
+    float* scratch[3] = {(float*)(ws + L.scratch_off), (float*)(ws + L.scratch_off + L.grid),
+                         (float*)(ws + L.scratch_off + 2 * L.grid)};
+    float* traces = wave->traces ? wave->traces : (float*)(ws + L.traces_off);
+    const bool has_src = wave->src[0] >= 0 && wave->wavelet;
+
+    auto fwd_step = [&](const float* prev, const float* cur, float* next, int t, bool record) {
+        WaveLaunch w = wave_base();
+        w.prev = prev;
+        w.cur = cur;
+        w.next = next;
+        w.kappa = wave->kappa;
+        if (has_src) {
+            w.src_x = (int)wave->src[0];
+            w.src_y = (int)wave->src[1];
+            w.src_z = (int)wave->src[2];
+            w.src_amp = wave->wavelet + t;
+        }
+        if (record) {
+            w.rec_z = (int)wave->rec_z;
+            w.trace_t = traces + (size_t)t * plane;
+        }
+        return launch_wave3d(g, plan->cfg, plan->taps, plan->taps, kWaveFwd, w, s);
+    };
+    auto pick = [&](const float* a, const float* b) -> float* {
+        for (float* c : scratch)
+            if (c != a && c != b) return c;
+        return nullptr;
+    };
+
+    // Forward: record traces, keep (u_{sK-1}, u_{sK}) for s = 1..S-1.
+    const float* prev = (const float*)wave->u_prev;
+    const float* cur = (const float*)u0;
+    for (int t = 0; t < T; ++t) {
+        const int tn = t + 1;   // this step produces u_tn
+        float* as_prev = nullptr;   // ckpt slot holding u_{sK-1}
+        float* as_cur = nullptr;    // ckpt slot holding u_{sK}
+        if ((tn + 1) % K == 0 && (tn + 1) / K >= 1 && (tn + 1) / K < S) as_prev = ckpt((tn + 1) / K, 0);
+        if (tn % K == 0 && tn / K >= 1 && tn / K < S) as_cur = ckpt(tn / K, 1);
+        float* next = as_cur ? as_cur : (as_prev ? as_prev : pick(prev, cur));
+        HIP_TRY(fwd_step(prev, cur, next, t, true));
+        if (as_cur && as_prev)   // K == 1: the same state opens two checkpoints
+            HIP_TRY(hipMemcpyAsync(as_prev, as_cur, cells_of(plan->prob) * 4, hipMemcpyDeviceToDevice, s));
+        prev = cur;
+        cur = next;
+    }
+    HIP_TRY(launch_trace_loss(traces, wave->target, (size_t)T * plane, (double*)(ws + L.part_off),
+                              loss_dev, s));
+
+    // Backward, segment by segment.
+    float* lam[2] = {(float*)(ws + L.lam_off), (float*)(ws + L.lam_off + L.grid)};
+    HIP_TRY(launch_fill(lam[0], 0.f, cells_of(plan->prob), s));
+    HIP_TRY(launch_fill(lam[1], 0.f, cells_of(plan->prob), s));
+    HIP_TRY(launch_fill(dkappa, 0.f, cells_of(plan->prob), s));
+    float* l_next = lam[0];   // lambda_{t+1}
+    float* l_next2 = lam[1];  // lambda_{t+2}
+    for (int seg = S - 1; seg >= 0; --seg) {
+        const int t0 = seg * K;
+        const int t1 = std::min(t0 + K, T);
+        const float* base_prev = seg == 0 ? (const float*)wave->u_prev : ckpt(seg, 0);
+        const float* base_cur = seg == 0 ? (const float*)u0 : ckpt(seg, 1);
+        auto state = [&](int t) -> const float* {   // u_t for t in [t0, t1]
+            if (t == t0) return base_cur;
+            return (const float*)(ws + L.states_off + (size_t)(t - t0 - 1) * L.grid);
+        };
+        const int tstart = (seg == S - 1) ? T : t1 - 1;
+        // Recompute u_{t0+1}..u_{tstart}.
+        const float* p = base_prev;
+        const float* c = base_cur;
+        for (int t = t0; t < tstart; ++t) {
+            float* nx = (float*)state(t + 1);
+            HIP_TRY(fwd_step(p, c, nx, t, false));
+            p = c;
+            c = nx;
+        }
+        for (int t = tstart; t >= t0; --t) {
+            WaveLaunch w = wave_base();
+            w.prev = l_next2;
+            w.cur = l_next;
+            w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place
+            w.kappa = wave->kappa;
+            w.u = state(t);
+            w.grad = dkappa;
+            w.rec_z = (int)wave->rec_z;
+            w.target_t = t >= 1 ? wave->target + (size_t)(t - 1) * plane : nullptr;
+            HIP_TRY(launch_wave3d(g, plan->cfg, plan->taps_t, plan->taps, kWaveGrad, w, s));
+            std::swap(l_next, l_next2);
+        }
+    }
+    return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""Python API over libstencil: plans as objects, torch tensors as buffers.
+
+PyTorch supplies device memory and the current stream only.  Every sweep,
+adjoint and gradient runs in the library's HIP kernels; there is no CPU or
+PyTorch fallback, and a missing library raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check, lib
+
+_DTYPES = {"f32": (_abi.ST_F32, torch.float32), "f16": (_abi.ST_F16, torch.float16)}
+_BC = {"periodic": _abi.ST_PERIODIC, "zero": _abi.ST_ZERO}
+_SHAPES = {"star": _abi.ST_STAR, "box": _abi.ST_BOX}
+
+
+def _enum(table, v):
+    if isinstance(v, str):
+        return table[v]
+    return int(v)
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _opts(variant=0, tile_x=0, tile_y=0, tsteps=0, zchunk=0, ckpt_every=0):
+    return _abi.StPlanOpts(int(variant), int(tile_x), int(tile_y), int(tsteps), int(zchunk),
+                           int(ckpt_every))
+
+
+def _problem(ndim, n, shape, radius, coeffs, dtype, boundary, update, keep):
+    c_arr = None
+    if coeffs is not None:
+        c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float32).ravel())
+        keep.append(c)
+        c_arr = c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    n3 = list(n) + [1] * (3 - len(n))
+    return _abi.StProblem(int(ndim), (ctypes.c_int64 * 3)(*[int(v) for v in n3]), int(shape),
+                          int(radius), c_arr, int(dtype), int(boundary), int(update))
+
+
+class _Workspace:
+    """Grow-only device byte buffer reused across calls of one object."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, nbytes: int) -> Tuple[Optional[ctypes.c_void_p], int]:
+        if nbytes == 0:
+            return None, 0
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return ctypes.c_void_p(self.buf.data_ptr()), int(self.buf.numel())
+
+
+class _Plan:
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def describe(self) -> dict:
+        v, tx, ty, k, zc = (ctypes.c_int32() for _ in range(5))
+        check(lib().stencil_plan_describe(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty),
+                                          ctypes.byref(k), ctypes.byref(zc)))
+        return {"variant": _abi.VARIANT_NAMES.get(v.value, v.value), "tile_x": tx.value,
+                "tile_y": ty.value, "tsteps": k.value, "zchunk": zc.value}
+
+    def workspace_bytes(self, steps: int, mode: int = 0) -> int:
+        return int(lib().stencil_workspace_bytes(self._h, int(steps), int(mode)))
+
+    def autotune(self, device="cuda", stream=None) -> dict:
+        nbytes = self.workspace_bytes(0, 2)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        check(lib().stencil_autotune(self._h, ctypes.c_void_p(scratch.data_ptr()), nbytes,
+                                     _stream_ptr(stream)))
+        tried, rejected = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().stencil_autotune_stats(self._h, ctypes.byref(tried), ctypes.byref(rejected)))
+        return {"tried": tried.value, "rejected": rejected.value}
+
+    def close(self):
+        if self._h:
+            lib().stencil_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stencil(_Plan):
+    """A linear constant-coefficient sweep u <- sum_d c_d u(B(x+d)) on one grid."""
+
+    def __init__(self, n: Sequence[int], shape, radius: int, coeffs, dtype: str = "f32",
+                 boundary="periodic", **opts):
+        super().__init__()
+        self.n = tuple(int(v) for v in n)
+        self.ndim = len(self.n)
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
+        keep: list = []
+        prob = _problem(self.ndim, self.n, _enum(_SHAPES, shape), radius, coeffs, self.dtype_code,
+                        _enum(_BC, boundary), _abi.ST_LINEAR, keep)
+        o = _opts(**opts) if opts else None
+        check(lib().stencil_plan(ctypes.byref(prob), ctypes.byref(o) if o is not None else None,
+                                 ctypes.byref(self._h)))
+        self.grid_shape = tuple(reversed(self.n))
+        self._ws: Optional[_Workspace] = None
+
+    def _check(self, t: torch.Tensor, name: str):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != self.torch_dtype or tuple(t.shape) != self.grid_shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.torch_dtype} tensor of shape {self.grid_shape}")
+
+    def _run(self, fn, u, steps, out, stream):
+        self._check(u, "u")
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(out, "out")
+        if self._ws is None:
+            self._ws = _Workspace(u.device)
+        ws, nb = self._ws.get(self.workspace_bytes(steps))
+        check(fn(self._h, _ptr(u), _ptr(out), int(steps), None, ws, nb, _stream_ptr(stream)))
+        return out
+
+    def apply(self, u: torch.Tensor, steps: int, out: Optional[torch.Tensor] = None, stream=None):
+        return self._run(lib().stencil_apply, u, steps, out, stream)
+
+    def apply_adjoint(self, v: torch.Tensor, steps: int, out: Optional[torch.Tensor] = None, stream=None):
+        return self._run(lib().stencil_apply_adjoint, v, steps, out, stream)
+
+
+class _SweepFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, stencil: Stencil, steps: int):
+        ctx.stencil = stencil
+        ctx.steps = steps
+        return stencil.apply(u.contiguous(), steps)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.stencil.apply_adjoint(g.contiguous(), ctx.steps), None, None
+
+
+def sweep(u: torch.Tensor, stencil: Stencil, steps: int) -> torch.Tensor:
+    """Differentiable A^steps u; the backward pass runs the transposed sweep."""
+    return _SweepFn.apply(u, stencil, steps)
+
+
+class WaveModel(_Plan):
+    """3D leapfrog u_{t+1} = 2u_t - u_{t-1} + kappa * L(u_t), L a radius-r star
+    (default: the order-2r central second-difference Laplacian)."""
+
+    def __init__(self, n: Sequence[int], radius: int = 4, boundary="zero", coeffs=None, **opts):
+        super().__init__()
+        self.n = tuple(int(v) for v in n)
+        keep: list = []
+        prob = _problem(3, self.n, _abi.ST_STAR, radius, coeffs, _abi.ST_F32, _enum(_BC, boundary),
+                        _abi.ST_WAVE, keep)
+        o = _opts(**opts) if opts else None
+        check(lib().stencil_plan(ctypes.byref(prob), ctypes.byref(o) if o is not None else None,
+                                 ctypes.byref(self._h)))
+        self.grid_shape = tuple(reversed(self.n))
+        self._ws: Optional[_Workspace] = None
+
+    def _chk(self, t, name):
+        if t is None:
+            return
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+
+    def _args(self, u_prev, kappa, src=None, wavelet=None, rec_z=-1, traces=None, target=None):
+        for name, t in (("u_prev", u_prev), ("kappa", kappa), ("wavelet", wavelet), ("traces", traces),
+                        ("target", target)):
+            self._chk(t, name)
+        s = (-1, -1, -1) if src is None else tuple(int(v) for v in src)
+        return _abi.StWaveArgs(_ptr(u_prev), _ptr(kappa), (ctypes.c_int64 * 3)(*s), _ptr(wavelet),
+                               int(rec_z), _ptr(traces), _ptr(target))
+
+    def _workspace(self, device, nbytes):
+        if self._ws is None:
+            self._ws = _Workspace(device)
+        return self._ws.get(nbytes)
+
+    def forward(self, u0, u_prev, kappa, steps: int, src=None, wavelet=None, rec_z: int = -1,
+                record: bool = False, out=None, stream=None):
+        """Returns (u_T, u_{T-1}, traces or None).  u0 and u_prev are not modified."""
+        self._chk(u0, "u0")
+        prev = u_prev.clone()
+        out = torch.empty_like(u0) if out is None else out
+        traces = None
+        if record and rec_z >= 0:
+            traces = torch.empty((steps, self.n[1], self.n[0]), dtype=torch.float32, device=u0.device)
+        wa = self._args(prev, kappa, src, wavelet, rec_z, traces)
+        ws, nb = self._workspace(u0.device, self.workspace_bytes(steps))
+        check(lib().stencil_apply(self._h, _ptr(u0), _ptr(out), int(steps), ctypes.byref(wa), ws, nb,
+                                  _stream_ptr(stream)))
+        return out, prev, traces
+
+    def adjoint(self, a, b, kappa, steps: int, stream=None):
+        """Transpose of (u_{-1}, u_0) -> (u_{T-1}, u_T): (a, b) are co-states of
+        (u_{T-1}, u_T); returns the co-states of (u_{-1}, u_0)."""
+        self._chk(b, "b")
+        a_io = a.clone()
+        out = torch.empty_like(b)
+        wa = self._args(a_io, kappa)
+        ws, nb = self._workspace(b.device, self.workspace_bytes(steps))
+        check(lib().stencil_apply_adjoint(self._h, _ptr(b), _ptr(out), int(steps), ctypes.byref(wa), ws,
+                                          nb, _stream_ptr(stream)))
+        return a_io, out
+
+    def gradient(self, u0, u_prev, kappa, steps: int, src, wavelet, rec_z: int, target,
+                 traces: Optional[torch.Tensor] = None, stream=None):
+        """(dJ/dkappa, J) with J = 1/2 sum_t ||u_t[rec_z] - target[t-1]||^2."""
+        self._chk(u0, "u0")
+        dk = torch.empty_like(kappa)
+        loss = torch.empty(1, dtype=torch.float64, device=u0.device)
+        wa = self._args(u_prev, kappa, src, wavelet, rec_z, traces, target)
+        ws, nb = self._workspace(u0.device, self.workspace_bytes(steps, 1))
+        check(lib().stencil_wave_gradient(self._h, _ptr(u0), ctypes.byref(wa), int(steps), _ptr(dk),
+                                          _ptr(loss), ws, nb, _stream_ptr(stream)))
+        return dk, loss
+
+
+class _WaveMisfitFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kappa, model: WaveModel, u0, u_prev, steps, src, wavelet, rec_z, target):
+        dk, loss = model.gradient(u0, u_prev, kappa.contiguous(), steps, src, wavelet, rec_z, target)
+        ctx.save_for_backward(dk)
+        return loss[0].to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, g):
+        (dk,) = ctx.saved_tensors
+        return dk * g.to(dk.dtype), None, None, None, None, None, None, None, None
+
+
+def wave_misfit(kappa, model: WaveModel, u0, u_prev, steps, src, wavelet, rec_z, target):
+    """Differentiable trace misfit J(kappa); backward returns the adjoint-state
+    gradient computed with checkpointing."""
+    return _WaveMisfitFn.apply(kappa, model, u0, u_prev, steps, src, wavelet, rec_z, target)
+
+
+class BatchedStencil(_Plan):
+    """Many independent 2D linear sweeps advanced in one persistent launch."""
+
+    def __init__(self, cases: List[dict], **opts):
+        super().__init__()
+        keep: list = []
+        arr = (_abi.StProblem * len(cases))()
+        self.shapes = []
+        dts = set()
+        for i, c in enumerate(cases):
+            code, tdt = _DTYPES[c.get("dtype", "f32")]
+            dts.add(tdt)
+            arr[i] = _problem(2, c["n"], _enum(_SHAPES, c["shape"]), c["radius"], c["coeffs"], code,
+                              _enum(_BC, c.get("boundary", "periodic")), _abi.ST_LINEAR, keep)
+            self.shapes.append((int(c["n"][1]), int(c["n"][0])))
+        self.torch_dtype = dts.pop() if len(dts) == 1 else None
+        o = _opts(**opts) if opts else None
+        check(lib().stencil_plan_batched(arr, len(cases), ctypes.byref(o) if o is not None else None,
+                                         ctypes.byref(self._h)))
+        self._ws: Optional[_Workspace] = None
+
+    def apply(self, us: List[torch.Tensor], steps: int, outs: Optional[List[torch.Tensor]] = None,
+              stream=None) -> List[torch.Tensor]:
+        if len(us) != len(self.shapes):
+            raise ValueError("one tensor per batch member is required")
+        for u, shp in zip(us, self.shapes):
+            if not u.is_cuda or u.dtype != self.torch_dtype or tuple(u.shape) != shp or not u.is_contiguous():
+                raise ValueError(f"member tensors must be contiguous {self.torch_dtype} of shape {shp}")
+        outs = [torch.empty_like(u) for u in us] if outs is None else outs
+        ins = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
+        ots = (ctypes.c_void_p * len(us))(*[o.data_ptr() for o in outs])
+        if self._ws is None:
+            self._ws = _Workspace(us[0].device)
+        ws, nb = self._ws.get(self.workspace_bytes(steps))
+        check(lib().stencil_apply_batched(self._h, ins, ots, int(steps), ws, nb, _stream_ptr(stream)))
+        return outs
+
+    def status(self) -> int:
+        """Items pulled by the last launch; raises if a dependency wait timed
+        out (call after synchronising the stream)."""
+        n = ctypes.c_int32()
+        check(lib().stencil_batched_status(self._h, ctypes.byref(n)))
+        return n.value

@@ -1,0 +1,227 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, and rejects bad arguments with the
+documented status codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2609_06694_amd import _abi
+from paper_2609_06694_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libstencil.so not built")
+    return _abi.lib()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "stencil.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    declared = header_functions()
+    assert set(declared) == set(_abi.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.stencil_version()
+
+
+def _prob(ndim=2, n=(64, 48, 1), shape=0, r=1, coeffs="ok", dtype=0, bc=0, update=0):
+    keep = []
+    if isinstance(coeffs, str):
+        c = wl.random_unit_sum_coeffs(np.random.default_rng(0), ndim, shape, r)
+    else:
+        c = coeffs
+    ptr = None
+    if c is not None:
+        c = np.ascontiguousarray(c, dtype=np.float32)
+        keep.append(c)
+        ptr = c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    p = _abi.StProblem(ndim, (ctypes.c_int64 * 3)(*n), shape, r, ptr, dtype, bc, update)
+    return p, keep
+
+
+def _plan(L, p, opts=None):
+    h = ctypes.c_void_p()
+    st = L.stencil_plan(ctypes.byref(p), ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ndim=4), _abi.ST_EINVAL),
+    (dict(shape=7), _abi.ST_EINVAL),
+    (dict(dtype=3), _abi.ST_EINVAL),
+    (dict(bc=9), _abi.ST_EINVAL),
+    (dict(r=0), _abi.ST_EINVAL),
+    (dict(r=5), _abi.ST_EINVAL),
+    (dict(coeffs=None), _abi.ST_EINVAL),
+    (dict(n=(64, 48, 2)), _abi.ST_ESHAPE),
+    (dict(n=(0, 48, 1)), _abi.ST_ESHAPE),
+    (dict(n=(1 << 25, 4, 1)), _abi.ST_ESHAPE),
+    (dict(shape=1, r=3), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=3, n=(8, 8, 8), shape=1, r=2), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=1), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=2, n=(8, 8, 1), update=1, coeffs=None), _abi.ST_EUNSUPPORTED),
+])
+def test_plan_validation_codes(L, kw, code):
+    p, keep = _prob(**kw)
+    st, h = _plan(L, p)
+    assert st == code, L.stencil_last_error()
+    assert not h.value
+    assert L.stencil_last_error() != b""
+
+
+def test_star_rejects_off_axis_coefficients(L):
+    c = np.zeros(9, dtype=np.float32)
+    c[0] = 0.5   # corner (dy=-1, dx=-1) is outside the star
+    p, keep = _prob(coeffs=c)
+    st, _ = _plan(L, p)
+    assert st == _abi.ST_EINVAL
+    c[0] = np.nan
+    p, keep = _prob(shape=1, coeffs=c)
+    assert _plan(L, p)[0] == _abi.ST_EINVAL
+
+
+def test_plan_describe_and_workspace(L):
+    p, keep = _prob(n=(512, 512, 1))
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    v, tx, ty, k, zc = (ctypes.c_int32() for _ in range(5))
+    assert L.stencil_plan_describe(h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k),
+                                   ctypes.byref(zc)) == _abi.ST_OK
+    assert v.value == _abi.ST_VARIANT_TB2D and tx.value % 64 == 0 and k.value >= 1
+    assert L.stencil_workspace_bytes(h, 10, 0) == 512 * 512 * 4
+    assert L.stencil_workspace_bytes(None, 10, 0) == 0
+    L.stencil_plan_destroy(h)
+    L.stencil_plan_destroy(None)   # NULL-safe
+
+
+def test_wave_plan_gradient_workspace(L):
+    p, keep = _prob(ndim=3, n=(32, 24, 40), update=1, coeffs=None, bc=1, r=4)
+    opts = _abi.StPlanOpts(0, 0, 0, 0, 0, 7)
+    st, h = _plan(L, p, opts)
+    assert st == _abi.ST_OK, L.stencil_last_error()
+    cells = 32 * 24 * 40
+    need = L.stencil_workspace_bytes(h, 30, 1)
+    # 2*(S-1) checkpoints + K states + 3 scratch + 2 adjoint grids + traces
+    S, K = 5, 7
+    assert need >= (2 * (S - 1) + K + 5) * cells * 4 + 30 * 32 * 24 * 4
+    L.stencil_plan_destroy(h)
+
+
+def test_plan_options_validated(L):
+    p, keep = _prob(n=(256, 256, 1))
+    assert _plan(L, p, _abi.StPlanOpts(0, 96, 0, 0, 0, 0))[0] == _abi.ST_EINVAL   # tile_x % 64
+    assert _plan(L, p, _abi.StPlanOpts(0, 0, 0, 17, 0, 0))[0] == _abi.ST_EINVAL   # depth
+    assert _plan(L, p, _abi.StPlanOpts(2, 0, 0, 0, 0, 0))[0] == _abi.ST_EINVAL    # 3D family on 2D
+    assert _plan(L, p, _abi.StPlanOpts(0, 512, 512, 16, 0, 0))[0] == _abi.ST_EINVAL  # LDS budget
+    st, h = _plan(L, p, _abi.StPlanOpts(1, 128, 16, 2, 0, 0))
+    assert st == _abi.ST_OK
+    L.stencil_plan_destroy(h)
+
+
+def test_apply_argument_errors_before_device(L):
+    p, keep = _prob(n=(64, 48, 1))
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    fake = ctypes.c_void_p(0x1000)
+    assert L.stencil_apply(None, fake, fake, 1, None, None, 0, None) == _abi.ST_EINVAL
+    assert L.stencil_apply(h, None, fake, 1, None, None, 0, None) == _abi.ST_EINVAL
+    assert L.stencil_apply(h, fake, fake, -1, None, None, 0, None) == _abi.ST_EINVAL
+    assert L.stencil_apply(h, fake, ctypes.c_void_p(0x2000), 3, None, None, 0, None) == _abi.ST_EWORKSPACE
+    wa = _abi.StWaveArgs()
+    assert L.stencil_apply(h, fake, fake, 1, ctypes.byref(wa), None, 0, None) == _abi.ST_EINVAL
+    assert L.stencil_wave_gradient(h, fake, None, 3, fake, fake, None, 0, None) == _abi.ST_EINVAL
+    L.stencil_plan_destroy(h)
+
+
+def test_wave_argument_errors_before_device(L):
+    p, keep = _prob(ndim=3, n=(16, 16, 16), update=1, coeffs=None, bc=1, r=4)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    fake = ctypes.c_void_p(0x1000)
+    assert L.stencil_apply(h, fake, fake, 1, None, None, 0, None) == _abi.ST_EINVAL
+    wa = _abi.StWaveArgs(ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), (ctypes.c_int64 * 3)(99, 0, 0),
+                         None, -1, None, None)
+    assert L.stencil_apply(h, fake, fake, 1, ctypes.byref(wa), None, 0, None) == _abi.ST_EINVAL  # source
+    wa = _abi.StWaveArgs(fake, ctypes.c_void_p(0x4000), (ctypes.c_int64 * 3)(-1, 0, 0), None, -1, None, None)
+    assert L.stencil_apply(h, fake, ctypes.c_void_p(0x5000), 1, ctypes.byref(wa), None, 0, None) == _abi.ST_EINVAL
+    wa = _abi.StWaveArgs(ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), (ctypes.c_int64 * 3)(-1, 0, 0),
+                         None, 99, None, None)
+    assert L.stencil_apply(h, fake, fake, 1, ctypes.byref(wa), None, 0, None) == _abi.ST_EINVAL  # receiver
+    L.stencil_plan_destroy(h)
+
+
+def test_batched_plan_host_checks(L):
+    cases = wl.batch2d(count=6, lo=64, hi=200, steps=4)
+    keep = []
+    arr = (_abi.StProblem * len(cases))()
+    for i, c in enumerate(cases):
+        cc = np.ascontiguousarray(c.coeffs)
+        keep.append(cc)
+        arr[i] = _abi.StProblem(2, (ctypes.c_int64 * 3)(*c.n), c.shape, c.radius,
+                                cc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert L.stencil_plan_batched(arr, len(cases), None, ctypes.byref(h)) == _abi.ST_OK
+    assert L.stencil_workspace_bytes(h, 4, 0) >= sum(c.cells * 4 for c in cases)
+    fake = (ctypes.c_void_p * len(cases))(*([0x1000] * len(cases)))
+    assert L.stencil_apply_batched(h, fake, fake, -2, None, 0, None) == _abi.ST_EINVAL
+    assert L.stencil_apply_batched(h, fake, fake, 4, None, 0, None) == _abi.ST_EWORKSPACE
+    assert L.stencil_apply(h, fake[0], fake[0], 1, None, None, 0, None) == _abi.ST_EINVAL
+    L.stencil_plan_destroy(h)
+    arr[2].dtype = 1   # mixed storage types are rejected
+    assert L.stencil_plan_batched(arr, len(cases), None, ctypes.byref(h)) == _abi.ST_EINVAL
+    assert L.stencil_plan_batched(arr, 0, None, ctypes.byref(h)) == _abi.ST_EINVAL
+
+
+def test_dispatch_cache_file_overrides_default(tmp_path):
+    """A tuning-cache line for a case key replaces the compiled-in entry
+    (checked in a fresh process, since the map loads the file once)."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    # ndim shape r dtype bc update size_class slab variant tile_x tile_y tsteps zchunk
+    cache.write_text("2 0 1 0 0 0 0 0 1 128 16 3 0\n")
+    code = (
+        "import ctypes, numpy as np\n"
+        "from paper_2609_06694_amd import _abi\n"
+        "L=_abi.lib()\n"
+        "c=np.zeros(9,np.float32); c[4]=1\n"
+        "p=_abi.StProblem(2,(ctypes.c_int64*3)(300,200,1),0,1,c.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),0,0,0)\n"
+        "h=ctypes.c_void_p(); assert L.stencil_plan(ctypes.byref(p),None,ctypes.byref(h))==0\n"
+        "v,tx,ty,k,z=(ctypes.c_int32() for _ in range(5))\n"
+        "L.stencil_plan_describe(h,ctypes.byref(v),ctypes.byref(tx),ctypes.byref(ty),ctypes.byref(k),ctypes.byref(z))\n"
+        "print(v.value,tx.value,ty.value,k.value)\n")
+    env = dict(os.environ, STENCIL_TUNE_CACHE=str(cache), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "128", "16", "3"]
+
+
+def test_batched_launch_is_switched_off(L):
+    """The persistent batched launch is disabled: it must refuse with
+    ST_EUNSUPPORTED after its host checks, before touching the device."""
+    cases = wl.batch2d(count=3, lo=64, hi=100, steps=2)
+    keep = []
+    arr = (_abi.StProblem * len(cases))()
+    for i, c in enumerate(cases):
+        cc = np.ascontiguousarray(c.coeffs)
+        keep.append(cc)
+        arr[i] = _abi.StProblem(2, (ctypes.c_int64 * 3)(*c.n), c.shape, c.radius,
+                                cc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert L.stencil_plan_batched(arr, len(cases), None, ctypes.byref(h)) == _abi.ST_OK
+    need = L.stencil_workspace_bytes(h, 2, 0)
+    fake = (ctypes.c_void_p * len(cases))(*([0x1000] * len(cases)))
+    assert L.stencil_apply_batched(h, fake, fake, 2, ctypes.c_void_p(0x1000), need, None) == _abi.ST_EUNSUPPORTED
+    assert b"disabled" in L.stencil_last_error()
+    L.stencil_plan_destroy(h)
