@@ -1,0 +1,295 @@
+#!/usr/bin/env python3
+"""Throughput of the stencil hot path on one MI355X.
+
+One "step" of this benchmark is one pass of the headline workload: 20
+leapfrog time steps of the 3D acoustic wave model (radius-4, 25-point
+eighth-order Laplacian star, f32, 512^3 cells, zero frame, kappa per cell)
+over inputs already resident in HBM.  `value` is GCells/s = cells * time
+steps / second.  The JSON line also carries the live roofline of the
+dominant kernel (the fused leapfrog step), the FP64 oracle timed on a
+bounded sample on the host, and the other workloads (2D Jacobi, fp16/f32
+box stencils, 64 uneven grids, the wave gradient) as `per_config`.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+WAVE_BYTES_PER_CELL = 16     # read u_t, u_{t-1}, kappa; write u_{t+1}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--only", default="", help="comma list of extra workloads to run")
+    ap.add_argument("--pmc-target", action="store_true",
+                    help="run only the profiler target: a 512 MiB device copy (counter calibration) "
+                         "then one 2-step pass of the headline workload")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="also measure plain streaming kernels (copy, read-3/write-1) as the "
+                         "practical bandwidth ceiling")
+    return ap.parse_args()
+
+
+def pmc_target(dev, st, wl, torch):
+    """Profiler target: a device copy of known size (its FETCH_SIZE/WRITE_SIZE
+    calibrate the counters) followed by two leapfrog launches at 512^3."""
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    case = wl.wave3d(n=512, steps=2)
+    u0 = torch.from_numpy(case.u0).to(dev)
+    prev = torch.from_numpy(case.u_prev).to(dev)
+    kap = torch.from_numpy(case.kappa).to(dev)
+    out = torch.empty_like(u0)
+    model = st.WaveModel(case.n, radius=4, boundary="zero")
+    model.forward(u0, prev, kap, 2, out=out, prev_inout=True)
+    torch.cuda.synchronize()
+    log("pmc target done: copy 512 MiB, 2 wave launches")
+
+
+def stream_ceiling(dev, torch):
+    """Practical HBM bandwidth of plain streaming kernels on this device."""
+    n = 256 * 1024 * 1024
+    a, b, c, d = (torch.rand(n, device=dev) for _ in range(4))
+    res = {}
+    ms = timed(lambda: b.copy_(a), 5, 2, torch.cuda.synchronize)
+    res["copy_gbs"] = 2 * 4 * n / (ms * 1e-3) / 1e9
+    ms = timed(lambda: torch.addcmul(a, b, c, out=d), 5, 2, torch.cuda.synchronize)
+    res["read3_write1_gbs"] = 4 * 4 * n / (ms * 1e-3) / 1e9
+    ms = timed(lambda: torch.add(a, b, out=c), 5, 2, torch.cuda.synchronize)
+    res["read2_write1_gbs"] = 3 * 4 * n / (ms * 1e-3) / 1e9
+    return res
+
+
+def timed(fn, reps, warmup, sync):
+    """Median wall time (ms) of fn() over reps, bracketed by device syncs."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    sync()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def gcells(cells, steps, ms):
+    return cells * steps / (ms * 1e-3) / 1e9
+
+
+def bench_wave(args, dev, st, wl, torch):
+    case = wl.wave3d(n=512, steps=20)
+    bufs = [torch.from_numpy(case.u0).to(dev), torch.empty(case.u0.shape, dtype=torch.float32, device=dev)]
+    prev = torch.from_numpy(case.u_prev).to(dev)
+    kap = torch.from_numpy(case.kappa).to(dev)
+    model = st.WaveModel(case.n, radius=4, boundary="zero")
+    state = {"i": 0}
+
+    def one_pass():
+        # Continue the simulation: u_T of this pass is u_0 of the next, and
+        # u_prev is updated in place, so consecutive passes copy nothing.
+        i = state["i"]
+        model.forward(bufs[i], prev, kap, case.steps, out=bufs[1 - i], prev_inout=True)
+        state["i"] = 1 - i
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_per_pass = e0.elapsed_time(e1) / args.steps
+    launch_ms = ms_per_pass / case.steps
+    finite = bool(torch.isfinite(bufs[state["i"]]).all().item())
+    log(f"wave3d 512^3 x20: {ms_per_pass:.3f} ms/pass (events), wall {wall:.3f} ms/pass, "
+        f"{launch_ms * 1e3:.1f} us/launch, finite={finite}")
+    return case, ms_per_pass, launch_ms, model.describe(), finite
+
+
+def bench_jacobi(dev, st, wl, torch):
+    case = wl.jacobi2d()
+    s = st.Stencil(case.n[:2], "star", 1, case.coeffs)
+    u = torch.from_numpy(case.u0).to(dev)
+    out = torch.empty_like(u)
+    ms = timed(lambda: s.apply(u, case.steps, out=out), 20, 3, torch.cuda.synchronize)
+    g = gcells(case.cells, case.steps, ms)
+    return {"workload": "jacobi2d_star1_512^2_10steps_f32", "ms": ms, "gcells_s": g,
+            "eff_gbs": g * 8, "hbm_frac": None, "note": "1 MiB grid is cache resident; not an HBM figure",
+            "dispatch": s.describe()}
+
+
+def bench_linear(dev, st, wl, torch, case, reps=3):
+    dt = "f16" if case.dtype == wl.F16 else "f32"
+    shape = wl.SHAPE_NAMES[case.shape]
+    s = st.Stencil(case.n[:case.ndim], shape, case.radius, case.coeffs, dtype=dt)
+    u = torch.from_numpy(case.u0).to(dev)
+    out = torch.empty_like(u)
+    ms = timed(lambda: s.apply(u, case.steps, out=out), reps, 1, torch.cuda.synchronize)
+    g = gcells(case.cells, case.steps, ms)
+    bpc = 2 * (2 if dt == "f16" else 4)
+    return {"workload": f"{case.name}_{'x'.join(str(v) for v in case.n[:case.ndim])}_{case.steps}steps",
+            "ms": ms, "gcells_s": g, "eff_gbs": g * bpc, "hbm_frac": g * bpc / HBM_PEAK_GBS,
+            "bytes_per_cell_update": bpc, "dispatch": s.describe()}
+
+
+def bench_batch(dev, st, wl, torch):
+    cases = wl.batch2d()
+    plans = [st.Stencil(c.n[:2], wl.SHAPE_NAMES[c.shape], c.radius, c.coeffs) for c in cases]
+    ins = [torch.from_numpy(c.u0).to(dev) for c in cases]
+    outs = [torch.empty_like(u) for u in ins]
+    cells = sum(c.cells for c in cases)
+
+    def run():
+        for p, u, o, c in zip(plans, ins, outs, cases):
+            p.apply(u, c.steps, out=o)
+
+    ms = timed(run, 3, 1, torch.cuda.synchronize)
+    g = gcells(cells, 32, ms)
+    return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms_separate_launches": ms,
+            "gcells_s_separate": g, "eff_gbs": g * 8, "hbm_frac": g * 8 / HBM_PEAK_GBS,
+            "persistent_batched": "disabled (launch did not complete on the GPU; see DESIGN.md)"}
+
+
+def bench_grad(dev, st, wl, torch):
+    case = wl.wavegrad3d()
+    n = case.n
+    kap = torch.from_numpy(case.kappa).to(dev)
+    kt = torch.from_numpy(case.kappa_true).to(dev)
+    zeros = torch.zeros(n[::-1], dtype=torch.float32, device=dev)
+    wav = torch.from_numpy(case.wavelet).to(dev)
+    model = st.WaveModel(n, radius=4, boundary="zero", ckpt_every=case.ckpt_every)
+    # Synthetic observed traces: the forward model at the perturbed kappa.
+    _, _, target = model.forward(zeros, zeros, kt, case.steps, src=case.src, wavelet=wav,
+                                 rec_z=case.rec_z, record=True)
+    target = target.contiguous()
+    fwd_ms = timed(lambda: model.forward(zeros, zeros, kap, case.steps, src=case.src, wavelet=wav,
+                                         rec_z=case.rec_z, record=True), 3, 1, torch.cuda.synchronize)
+    res = {}
+
+    def grad():
+        res["g"] = model.gradient(zeros, zeros, kap, case.steps, case.src, wav, case.rec_z, target)
+
+    g_ms = timed(grad, 3, 1, torch.cuda.synchronize)
+    dk, loss = res["g"]
+    return {"workload": "wavegrad3d_star4_256^3_200steps_ckpt20", "fwd_ms": fwd_ms, "fwd_bwd_ms": g_ms,
+            "ratio_fwd_bwd_over_fwd": g_ms / fwd_ms,
+            "fwd_gcells_s": gcells(case.cells, case.steps, fwd_ms),
+            "loss": float(loss.item()), "grad_finite": bool(torch.isfinite(dk).all().item())}
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle (unchanged, OpenMP over all host cores) on a bounded
+    sample of the headline workload: a 288^3 grid, 20 leapfrog steps."""
+    import oracle
+    oracle.build(force=False)
+    n = 288
+    case = wl.wave3d(n=n, steps=20)
+    t0 = time.perf_counter()
+    oracle.wave_forward(case.u_prev, case.u0, case.kappa, case.steps, r=4, boundary=wl.ZERO)
+    dt = time.perf_counter() - t0
+    return {"value": gcells(n ** 3, case.steps, dt * 1e3), "unit": "GCells/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"wave leapfrog r=4, {n}^3 cells x 20 steps, FP64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_2609_06694_amd import stencil as st, workloads as wl
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.pmc_target:
+        pmc_target(dev, st, wl, torch)
+        return
+
+    case, ms_pass, launch_ms, disp, finite = bench_wave(args, dev, st, wl, torch)
+    cells = case.cells
+    value = gcells(cells, case.steps, ms_pass)
+    achieved = WAVE_BYTES_PER_CELL * cells / (launch_ms * 1e-3) / 1e9
+    line = {
+        "metric": "GCells/s", "value": round(value, 2), "unit": "GCells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_pass, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wave3d_star4_512^3_20steps_zero_frame", "grid": [512, 512, 512],
+                   "time_steps": case.steps, "radius": 4, "dispatch": disp},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "wave3d_kernel<fwd,R=4,zero>", "bytes_per_cell": WAVE_BYTES_PER_CELL,
+                     "cells_per_launch": cells, "launch_ms": round(launch_ms, 5)},
+    }
+    extras = {}
+    if not args.quick:
+        only = set(filter(None, args.only.split(",")))
+        todo = [
+            ("jacobi2d", lambda: bench_jacobi(dev, st, wl, torch)),
+            ("box3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F16))),
+            ("box3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F32))),
+            ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),
+            ("box2d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F32))),
+            ("batch64", lambda: bench_batch(dev, st, wl, torch)),
+            ("wavegrad", lambda: bench_grad(dev, st, wl, torch)),
+        ]
+        for name, fn in todo:
+            if only and name not in only:
+                continue
+            t0 = time.perf_counter()
+            extras[name] = fn()
+            log(f"{name}: {json.dumps(extras[name])} ({time.perf_counter() - t0:.1f} s)")
+            torch.cuda.empty_cache()
+        line["per_config"] = extras
+    if args.stream_ceiling:
+        line["stream_ceiling"] = stream_ceiling(dev, torch)
+        log(f"stream ceiling: {line['stream_ceiling']}")
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(wl)
+        log(f"cpu baseline: {line['cpu_baseline']} ({time.perf_counter() - t0:.1f} s)")
+    if not finite:
+        line["error"] = "non-finite wave field"
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,7 +4,9 @@
 
 namespace stk {
 
-template <int R, int SHAPE, typename T, int BC, int RY>
+// D planes are kept in flight per workgroup: the register slot of plane zp
+// is refilled with plane zp + D as soon as zp has been staged in LDS.
+template <int R, int SHAPE, typename T, int BC, int RY, int D>
 __global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in,
                                                         T* __restrict__ out, int nx, int ny,
                                                         int nz, int zc, int tiles_x, int tiles_y,
@@ -19,6 +21,7 @@ __global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in
     const int z0 = zci * zc, z1 = min(z0 + zc, nz);
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const int gx = x0 + tx;
+    const int zbeg = z0 - R, zend = z1 + R;
 
     constexpr int Q = 2 * R + 1;
     float acc[Q][RY];
@@ -27,67 +30,73 @@ __global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in
 #pragma unroll
         for (int i = 0; i < RY; ++i) acc[q][i] = 0.f;
 
-    float vin[RY], vhalo[G::HT];
-    float one_in[RY], one_halo[G::HT];   // unused scale operands
-    load_plane<R, RY, BC>(in, nx, ny, nz, z0 - R, x0, y0, vin, vhalo);
+    float vin[D][RY], vhalo[D][G::HT];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (zbeg + d < zend) load_plane<R, RY, BC>(in, nx, ny, nz, zbeg + d, x0, y0, vin[d], vhalo[d]);
 
-    for (int zp = z0 - R; zp < z1 + R; ++zp) {
-        float* t = tile[zp & 1];
-        store_plane<R, RY, false>(t, vin, vhalo, one_in, one_halo);
-        float cen[RY];
+    for (int zb = zbeg; zb < zend; zb += D) {
 #pragma unroll
-        for (int i = 0; i < RY; ++i) cen[i] = vin[i];
-        if (zp + 1 < z1 + R) load_plane<R, RY, BC>(in, nx, ny, nz, zp + 1, x0, y0, vin, vhalo);
-        __syncthreads();
+        for (int d = 0; d < D; ++d) {
+            const int zp = zb + d;
+            if (zp >= zend) break;
+            float* t = tile[zp & 1];
+            store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
+            float cen[RY];
+#pragma unroll
+            for (int i = 0; i < RY; ++i) cen[i] = vin[d][i];
+            if (zp + D < zend) load_plane<R, RY, BC>(in, nx, ny, nz, zp + D, x0, y0, vin[d], vhalo[d]);
+            __syncthreads();
 
-        if constexpr (SHAPE == kStar) {
-            float p[RY];
-            star_plane<R, RY>(t, tp, p);
-            // plane zp feeds output zo = zp - dz with weight c_z(dz); slot R - dz
+            if constexpr (SHAPE == kStar) {
+                float p[RY];
+                star_plane<R, RY>(t, tp, p);
+                // plane zp feeds output zo = zp - dz with weight c_z(dz); slot R - dz
 #pragma unroll
-            for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
+                for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
 #pragma unroll
-            for (int d = 1; d <= R; ++d) {
+                for (int e = 1; e <= R; ++e) {
 #pragma unroll
-                for (int i = 0; i < RY; ++i) {
-                    acc[R - d][i] = fmaf(tp.c[star_z<R>(d)], cen[i], acc[R - d][i]);
-                    acc[R + d][i] = fmaf(tp.c[star_z<R>(-d)], cen[i], acc[R + d][i]);
+                    for (int i = 0; i < RY; ++i) {
+                        acc[R - e][i] = fmaf(tp.c[star_z<R>(e)], cen[i], acc[R - e][i]);
+                        acc[R + e][i] = fmaf(tp.c[star_z<R>(-e)], cen[i], acc[R + e][i]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int dx = -R; dx <= R; ++dx) {
+                    float col[RY + 2 * R];
+                    const float* base = t + (ty * RY) * G::W + R + tx + dx;
+#pragma unroll
+                    for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+#pragma unroll
+                    for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+                        for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                            for (int i = 0; i < RY; ++i)
+                                acc[R - dz][i] = fmaf(tp.c[box3<R>(dz, dy, dx)], col[i + R + dy],
+                                                      acc[R - dz][i]);
                 }
             }
-        } else {
-#pragma unroll
-            for (int dx = -R; dx <= R; ++dx) {
-                float col[RY + 2 * R];
-                const float* base = t + (ty * RY) * G::W + R + tx + dx;
-#pragma unroll
-                for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
-#pragma unroll
-                for (int dz = -R; dz <= R; ++dz)
-#pragma unroll
-                    for (int dy = -R; dy <= R; ++dy)
-#pragma unroll
-                        for (int i = 0; i < RY; ++i)
-                            acc[R - dz][i] = fmaf(tp.c[box3<R>(dz, dy, dx)], col[i + R + dy],
-                                                  acc[R - dz][i]);
-            }
-        }
 
-        // Output plane zp - R has received all 2R+1 planes.
-        const int zo = zp - R;
-        if (zo >= z0 && gx < nx) {
-            T* o = out + (size_t)zo * nx * ny;
+            // Output plane zp - R has received all 2R+1 planes.
+            const int zo = zp - R;
+            if (zo >= z0 && gx < nx) {
+                T* o = out + (size_t)zo * nx * ny;
 #pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                const int gy = y0 + ty * RY + i;
-                if (gy < ny) o[(size_t)gy * nx + gx] = from_f32<T>(acc[0][i]);
+                for (int i = 0; i < RY; ++i) {
+                    const int gy = y0 + ty * RY + i;
+                    if (gy < ny) __builtin_nontemporal_store(from_f32<T>(acc[0][i]), &o[(uint32_t)(gy * nx + gx)]);
+                }
             }
+#pragma unroll
+            for (int q = 0; q < Q - 1; ++q)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) acc[q][i] = acc[q + 1][i];
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc[Q - 1][i] = 0.f;
         }
-#pragma unroll
-        for (int q = 0; q < Q - 1; ++q)
-#pragma unroll
-            for (int i = 0; i < RY; ++i) acc[q][i] = acc[q + 1][i];
-#pragma unroll
-        for (int i = 0; i < RY; ++i) acc[Q - 1][i] = 0.f;
     }
 }
 
@@ -98,13 +107,21 @@ bool zm3d_supported(int r, int shape) {
 
 int zm3d_rows(const LaunchCfg& cfg) { return cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8); }
 
+// Planes in flight per workgroup, chosen so the register ring stays within
+// the budget of three to four waves per SIMD.
+template <int R, int RY>
+constexpr int zm3d_depth() {
+    return RY >= 8 ? 1 : (RY >= 4 ? 2 : (R >= 3 ? 3 : 4));
+}
+
 template <int R, int SHAPE, typename T, int BC, int RY>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const void* in, void* out,
                      hipStream_t s) {
     using G = PlaneGeom<R, RY>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
-    hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY>), dim3(tiles_x * tiles_y * nchunks),
+    constexpr int D = zm3d_depth<R, RY>();
+    hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY, D>), dim3(tiles_x * tiles_y * nchunks),
                        dim3(kThreads), 0, s, (const T*)in, (T*)out, g.nx, g.ny, g.nz, zc, tiles_x,
                        tiles_y, tp);
     return hipGetLastError();

@@ -15,7 +15,11 @@
 
 namespace stk {
 
-template <int MODE, int R, int BC, int RY>
+// Each workgroup keeps D planes in flight: the slot of plane zp is refilled
+// with plane zp + D as soon as it has been staged in LDS, and the pointwise
+// operands of output plane zo are issued D planes before zo is emitted, so
+// D HBM round trips overlap instead of one per plane.
+template <int MODE, int R, int BC, int RY, int D>
 __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, int ny, int nz,
                                                           int zc, int tiles_x, int tiles_y,
                                                           Taps tp, Taps tp2) {
@@ -32,6 +36,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const int gx = x0 + tx;
     const size_t plane_sz = (size_t)nx * ny;
+    const int zbeg = z0 - R, zend = z1 + R;   // planes staged: zbeg .. zend-1
 
     constexpr int Q = 2 * R + 1;
     float acc[Q][RY], acc2[TWO ? Q : 1][RY];
@@ -52,127 +57,153 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
             if constexpr (TWO) cq2[q][i] = 0.f;
         }
 
-    float vin[RY], vhalo[G::HT];
-    float kin[RY], khalo[G::HT];
-    float uin[RY], uhalo[G::HT];
-    load_plane<R, RY, BC>(w.cur, nx, ny, nz, z0 - R, x0, y0, vin, vhalo);
-    if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, z0 - R, x0, y0, kin, khalo);
-    if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, z0 - R, x0, y0, uin, uhalo);
+    // Ring of D in-flight planes (first field, kappa when scaled, u_t when
+    // two fields) and of D sets of pointwise operands.
+    float vin[D][RY], vhalo[D][G::HT];
+    float kin[SCALE ? D : 1][RY], khalo[SCALE ? D : 1][G::HT];
+    float uin[TWO ? D : 1][RY], uhalo[TWO ? D : 1][G::HT];
+    float pq[D][RY], kq[MODE == kWaveFwd ? D : 1][RY], gq[TWO ? D : 1][RY];
 
-    for (int zp = z0 - R; zp < z1 + R; ++zp) {
-        float* t;
-        float* t2 = nullptr;
-        if constexpr (TWO) {
-            t = tile[2 * (zp & 1)];
-            t2 = tile[2 * (zp & 1) + 1];
-        } else {
-            t = tile[zp & 1];
-        }
-        store_plane<R, RY, SCALE>(t, vin, vhalo, kin, khalo);
-        if constexpr (TWO) store_plane<R, RY, false>(t2, uin, uhalo, kin, khalo);
-        float cen[RY];
+    auto issue_plane = [&](int slot, int zp) {
+        load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp, x0, y0, vin[slot], vhalo[slot]);
+        if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, zp, x0, y0, kin[slot], khalo[slot]);
+        if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, zp, x0, y0, uin[slot], uhalo[slot]);
+    };
+    // Pointwise operands of output plane zo (read by the thread that writes it).
+    auto issue_point = [&](int slot, int zo) {
+        if (zo < z0 || zo >= z1 || gx >= nx) return;
+        const size_t zoff = (size_t)zo * plane_sz;
+        const float* pp = w.prev + zoff;
+        const float* kp = w.kappa + zoff;
+        const float* gp = w.grad + zoff;
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            cq[R][i] = vin[i];
-            cen[i] = SCALE ? vin[i] * kin[i] : vin[i];
-            if constexpr (TWO) cq2[R][i] = uin[i];
+            const int gy = y0 + ty * RY + i;
+            const uint32_t o = (uint32_t)((gy < ny ? gy : 0) * nx + gx);
+            pq[slot][i] = __builtin_nontemporal_load(&pp[o]);
+            if constexpr (MODE == kWaveFwd) kq[slot][i] = __builtin_nontemporal_load(&kp[o]);
+            if constexpr (TWO) gq[slot][i] = __builtin_nontemporal_load(&gp[o]);
         }
-        if (zp + 1 < z1 + R) {
-            load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp + 1, x0, y0, vin, vhalo);
-            if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, zp + 1, x0, y0, kin, khalo);
-            if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, zp + 1, x0, y0, uin, uhalo);
-        }
-        __syncthreads();
+    };
 
-        // Pointwise operands of the output plane zo, issued before the compute.
-        const int zo = zp - R;
-        const bool emit = zo >= z0 && gx < nx;
-        float pv[RY], kv[RY], gv[RY];
-        if (emit) {
-            const size_t zoff = (size_t)zo * plane_sz;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (zbeg + d < zend) issue_plane(d, zbeg + d);
+        issue_point(d, zbeg + d - R);
+    }
+
+    for (int zb = zbeg; zb < zend; zb += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int zp = zb + d;
+            if (zp >= zend) break;
+            float* t;
+            float* t2 = nullptr;
+            if constexpr (TWO) {
+                t = tile[2 * (zp & 1)];
+                t2 = tile[2 * (zp & 1) + 1];
+            } else {
+                t = tile[zp & 1];
+            }
+            if constexpr (SCALE) store_plane<R, RY, true>(t, vin[d], vhalo[d], kin[d], khalo[d]);
+            else store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
+            if constexpr (TWO) store_plane<R, RY, false>(t2, uin[d], uhalo[d], uin[d], uhalo[d]);
+            float cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
-                const int gy = y0 + ty * RY + i;
-                const size_t o = zoff + (size_t)(gy < ny ? gy : 0) * nx + gx;
-                pv[i] = w.prev[o];
-                if constexpr (MODE == kWaveFwd) kv[i] = w.kappa[o];
-                if constexpr (TWO) gv[i] = w.grad[o];
+                cq[R][i] = vin[d][i];
+                if constexpr (SCALE) cen[i] = vin[d][i] * kin[d][i];
+                else cen[i] = vin[d][i];
+                if constexpr (TWO) cq2[R][i] = uin[d][i];
             }
-        }
+            if (zp + D < zend) issue_plane(d, zp + D);
+            __syncthreads();
 
-        {
-            float p[RY];
-            star_plane<R, RY>(t, tp, p);
+            {
+                float p[RY];
+                star_plane<R, RY>(t, tp, p);
 #pragma unroll
-            for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
+                for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
 #pragma unroll
-            for (int d = 1; d <= R; ++d)
+                for (int e = 1; e <= R; ++e)
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        acc[R - e][i] = fmaf(tp.c[star_z<R>(e)], cen[i], acc[R - e][i]);
+                        acc[R + e][i] = fmaf(tp.c[star_z<R>(-e)], cen[i], acc[R + e][i]);
+                    }
+            }
+            if constexpr (TWO) {
+                float p[RY];
+                star_plane<R, RY>(t2, tp2, p);
+#pragma unroll
+                for (int i = 0; i < RY; ++i) acc2[R][i] += p[i];
+#pragma unroll
+                for (int e = 1; e <= R; ++e)
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        acc2[R - e][i] = fmaf(tp2.c[star_z<R>(e)], cq2[R][i], acc2[R - e][i]);
+                        acc2[R + e][i] = fmaf(tp2.c[star_z<R>(-e)], cq2[R][i], acc2[R + e][i]);
+                    }
+            }
+
+            // Output plane zo = zp - R has received all 2R+1 planes.
+            const int zo = zp - R;
+            if (zo >= z0 && gx < nx) {
+                const size_t zoff = (size_t)zo * plane_sz;
+                float* np_ = w.next + zoff;
+                float* gp = w.grad + zoff;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    acc[R - d][i] = fmaf(tp.c[star_z<R>(d)], cen[i], acc[R - d][i]);
-                    acc[R + d][i] = fmaf(tp.c[star_z<R>(-d)], cen[i], acc[R + d][i]);
+                    const int gy = y0 + ty * RY + i;
+                    if (gy >= ny) continue;
+                    const uint32_t o = (uint32_t)(gy * nx + gx);
+                    float v;
+                    if constexpr (MODE == kWaveFwd) {
+                        v = 2.f * cq[0][i] - pq[d][i] + kq[d][i] * acc[0][i];
+                        if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
+                        if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
+                    } else if constexpr (MODE == kWaveAdj) {
+                        v = 2.f * cq[0][i] - w.prev_sign * pq[d][i] + acc[0][i];
+                    } else {
+                        v = 2.f * cq[0][i] - pq[d][i] + acc[0][i];
+                        if (w.target_t != nullptr && zo == w.rec_z) v += cq2[0][i] - w.target_t[o];
+                        __builtin_nontemporal_store(fmaf(cq[0][i], acc2[0][i], gq[d][i]), &gp[o]);
+                    }
+                    __builtin_nontemporal_store(v, &np_[o]);
                 }
-        }
-        if constexpr (TWO) {
-            float p[RY];
-            star_plane<R, RY>(t2, tp2, p);
+            }
+            issue_point(d, zp + D - R);
 #pragma unroll
-            for (int i = 0; i < RY; ++i) acc2[R][i] += p[i];
-#pragma unroll
-            for (int d = 1; d <= R; ++d)
+            for (int q = 0; q < Q - 1; ++q)
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    acc2[R - d][i] = fmaf(tp2.c[star_z<R>(d)], cq2[R][i], acc2[R - d][i]);
-                    acc2[R + d][i] = fmaf(tp2.c[star_z<R>(-d)], cq2[R][i], acc2[R + d][i]);
+                    acc[q][i] = acc[q + 1][i];
+                    if constexpr (TWO) acc2[q][i] = acc2[q + 1][i];
+                }
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                acc[Q - 1][i] = 0.f;
+                if constexpr (TWO) acc2[Q - 1][i] = 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    cq[q][i] = cq[q + 1][i];
+                    if constexpr (TWO) cq2[q][i] = cq2[q + 1][i];
                 }
         }
-
-        if (emit) {
-            const size_t zoff = (size_t)zo * plane_sz;
-#pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                const int gy = y0 + ty * RY + i;
-                if (gy >= ny) continue;
-                const size_t o = zoff + (size_t)gy * nx + gx;
-                float v;
-                if constexpr (MODE == kWaveFwd) {
-                    v = 2.f * cq[0][i] - pv[i] + kv[i] * acc[0][i];
-                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
-                    if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[(size_t)gy * nx + gx] = v;
-                } else if constexpr (MODE == kWaveAdj) {
-                    v = 2.f * cq[0][i] - w.prev_sign * pv[i] + acc[0][i];
-                } else {
-                    v = 2.f * cq[0][i] - pv[i] + acc[0][i];
-                    if (w.target_t != nullptr && zo == w.rec_z)
-                        v += cq2[0][i] - w.target_t[(size_t)gy * nx + gx];
-                    w.grad[o] = fmaf(cq[0][i], acc2[0][i], gv[i]);
-                }
-                w.next[o] = v;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q - 1; ++q)
-#pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                acc[q][i] = acc[q + 1][i];
-                if constexpr (TWO) acc2[q][i] = acc2[q + 1][i];
-            }
-#pragma unroll
-        for (int i = 0; i < RY; ++i) {
-            acc[Q - 1][i] = 0.f;
-            if constexpr (TWO) acc2[Q - 1][i] = 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-#pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                cq[q][i] = cq[q + 1][i];
-                if constexpr (TWO) cq2[q][i] = cq2[q + 1][i];
-            }
     }
 }
 
 bool wave3d_supported(int r) { return r >= 1 && r <= 4; }
+
+// Planes in flight per workgroup: deeper for thin tiles (few registers per
+// plane), shallower for the two-field gradient step.
+template <int MODE, int RY>
+constexpr int wave_depth() {
+    return MODE == kWaveGrad ? (RY >= 4 ? 1 : 2) : (RY >= 8 ? 1 : (RY >= 4 ? 2 : 4));
+}
 
 template <int MODE, int R, int BC, int RY>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const Taps& tp2, const WaveLaunch& w,
@@ -180,7 +211,8 @@ static hipError_t go(const Geom& g, int zc, const Taps& tp, const Taps& tp2, con
     using G = PlaneGeom<R, RY>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
-    hipLaunchKernelGGL((wave3d_kernel<MODE, R, BC, RY>), dim3(tiles_x * tiles_y * nchunks),
+    constexpr int D = wave_depth<MODE, RY>();
+    hipLaunchKernelGGL((wave3d_kernel<MODE, R, BC, RY, D>), dim3(tiles_x * tiles_y * nchunks),
                        dim3(kThreads), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
     return hipGetLastError();
 }

@@ -66,7 +66,7 @@ __device__ __forceinline__ void load_plane(const T* __restrict__ f, int nx, int 
         int gx = x0 + tx, gy = y0 + ty * RY + i;
         bool ok = zin;
         if (!inner) ok = ok && map_coord<BC>(gx, nx) && map_coord<BC>(gy, ny);
-        in[i] = ok ? to_f32(plane[(size_t)gy * nx + gx]) : 0.f;
+        in[i] = ok ? to_f32(plane[(uint32_t)(gy * nx + gx)]) : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < G::HT; ++j) {
@@ -78,7 +78,7 @@ __device__ __forceinline__ void load_plane(const T* __restrict__ f, int nx, int 
             int gx = x0 - R + lx, gy = y0 - R + ly;
             bool ok = zin;
             if (!inner) ok = ok && map_coord<BC>(gx, nx) && map_coord<BC>(gy, ny);
-            if (ok) v = to_f32(plane[(size_t)gy * nx + gx]);
+            if (ok) v = to_f32(plane[(uint32_t)(gy * nx + gx)]);
         }
         halo[j] = v;
     }

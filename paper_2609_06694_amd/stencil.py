@@ -200,10 +200,12 @@ class WaveModel(_Plan):
         return self._ws.get(nbytes)
 
     def forward(self, u0, u_prev, kappa, steps: int, src=None, wavelet=None, rec_z: int = -1,
-                record: bool = False, out=None, stream=None):
-        """Returns (u_T, u_{T-1}, traces or None).  u0 and u_prev are not modified."""
+                record: bool = False, out=None, stream=None, prev_inout: bool = False):
+        """Returns (u_T, u_{T-1}, traces or None).  u0 is not modified; u_prev
+        is copied first unless prev_inout, in which case it is overwritten
+        with u_{T-1} and returned."""
         self._chk(u0, "u0")
-        prev = u_prev.clone()
+        prev = u_prev if prev_inout else u_prev.clone()
         out = torch.empty_like(u0) if out is None else out
         traces = None
         if record and rec_z >= 0:
