@@ -84,6 +84,28 @@ def stream_ceiling(dev, torch):
     return res
 
 
+WAVE_SOURCES = ["paper_2609_06694_amd/csrc/kernels_wave.hip", "paper_2609_06694_amd/csrc/zmarch.h",
+                "paper_2609_06694_amd/csrc/common.h"]
+TRAFFIC_PROFILE = "profiles/wave3d_fwd_r4_512cube_pmc_traffic.md"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the leapfrog kernel from the committed PMC
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in WAVE_SOURCES)
+        h = hashlib.sha256(src).hexdigest()[:16]
+        for line in open(os.path.join(ROOT, TRAFFIC_PROFILE)):
+            if line.startswith("traffic_json:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("source_hash") == h:
+                    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def timed(fn, reps, warmup, sync):
     """Median wall time (ms) of fn() over reps, bracketed by device syncs."""
     import torch
@@ -247,6 +269,8 @@ def main():
     cells = case.cells
     value = gcells(cells, case.steps, ms_pass)
     achieved = WAVE_BYTES_PER_CELL * cells / (launch_ms * 1e-3) / 1e9
+    tbytes = measured_traffic()
+    traffic = None if tbytes is None else round(tbytes / (launch_ms * 1e-3) / 1e9, 1)
     line = {
         "metric": "GCells/s", "value": round(value, 2), "unit": "GCells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_pass, 4),
@@ -255,7 +279,8 @@ def main():
         "config": {"workload": "wave3d_star4_512^3_20steps_zero_frame", "grid": [512, 512, 512],
                    "time_steps": case.steps, "radius": 4, "dispatch": disp},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_bytes_per_launch": tbytes, "traffic_source": TRAFFIC_PROFILE,
                      "kernel": "wave3d_kernel<fwd,R=4,zero>", "bytes_per_cell": WAVE_BYTES_PER_CELL,
                      "cells_per_launch": cells, "launch_ms": round(launch_ms, 5)},
     }
