@@ -70,7 +70,8 @@ typedef enum {
     ST_VARIANT_AUTO = 0,  /* let the dispatch map choose */
     ST_VARIANT_TB2D = 1,  /* 2D LDS tile, k fused time steps per launch */
     ST_VARIANT_ZM3D = 2,  /* 3D plane-streaming (z-march) with register queues */
-    ST_VARIANT_WAVE3D = 3 /* 3D leapfrog z-march, fused source/receiver */
+    ST_VARIANT_WAVE3D = 3, /* 3D leapfrog z-march, fused source/receiver */
+    ST_VARIANT_WAVE3D_LDS = 4 /* 3D leapfrog forward with z-neighbours in an LDS ring */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */
@@ -93,7 +94,8 @@ typedef struct {
     int32_t variant;       /* st_variant */
     int32_t tile_x;        /* TB2D: output tile width (multiple of 64) */
     int32_t tile_y;        /* TB2D: output tile height; ZM3D/WAVE3D: rows per workgroup */
-    int32_t tsteps;        /* TB2D: time steps fused per launch (1..16) */
+    int32_t tsteps;        /* TB2D: time steps fused per launch (1..16);
+                              WAVE3D: 1, or 2 = two fused leapfrog steps (radius 2 or 4) */
     int32_t zchunk;        /* ZM3D/WAVE3D: planes per workgroup (0 = whole depth) */
     int32_t ckpt_every;    /* wave gradient checkpoint interval (0 = 20) */
 } st_plan_opts;

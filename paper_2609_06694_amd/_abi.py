@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libstencil.so")
+# STENCIL_LIBRARY may name another build of the same library (same ABI).
+LIB_PATH = os.environ.get("STENCIL_LIBRARY") or os.path.join(HERE, "libstencil.so")
 
 ST_OK, ST_EINVAL, ST_ESHAPE, ST_EUNSUPPORTED, ST_EWORKSPACE, ST_EHIP, ST_ENOMEM, ST_ETUNE = range(8)
 STATUS_NAMES = {0: "ST_OK", 1: "ST_EINVAL", 2: "ST_ESHAPE", 3: "ST_EUNSUPPORTED", 4: "ST_EWORKSPACE",
@@ -19,8 +20,8 @@ ST_F32, ST_F16 = 0, 1
 ST_PERIODIC, ST_ZERO = 0, 1
 ST_STAR, ST_BOX = 0, 1
 ST_LINEAR, ST_WAVE = 0, 1
-ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D = 0, 1, 2, 3
-VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d"}
+ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D, ST_VARIANT_WAVE3D_LDS = 0, 1, 2, 3, 4
+VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",

@@ -40,6 +40,13 @@ Geom geom_of(const st_problem& p) {
     g.r = p.radius;
     g.dtype = p.dtype;
     g.boundary = p.boundary;
+    g.iso = false;
+    return g;
+}
+
+Geom plan_geom(const st_plan* pl) {
+    Geom g = geom_of(pl->prob);
+    g.iso = pl->iso;
     return g;
 }
 
@@ -75,13 +82,14 @@ static LaunchCfg default_cfg(const CaseKey& k) {
     if (k.update == ST_WAVE) {
         c.variant = ST_VARIANT_WAVE3D;
         c.tile_y = 16;
-        c.zchunk = 64;
+        c.tsteps = 1;
+        c.zchunk = kAutoChunk;
         return c;
     }
     if (k.ndim == 3) {
         c.variant = ST_VARIANT_ZM3D;
-        c.tile_y = 16;
-        c.zchunk = 64;
+        c.tile_y = k.dtype == 1 ? 16 : 32;
+        c.zchunk = kAutoChunk;
         return c;
     }
     c.variant = ST_VARIANT_TB2D;
@@ -151,10 +159,24 @@ void dispatch_store(const CaseKey& k, const LaunchCfg& c, bool persist) {
     fclose(f);
 }
 
+// Plane chunk giving about 512 workgroups: enough to fill 256 CUs twice
+// while keeping the z-halo re-read (2R planes per chunk) small.
+int auto_zchunk(const st_problem& p, const LaunchCfg& c) {
+    const int rows = c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8);
+    const int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
+    int64_t zc = p.n[2] * tiles / 512;
+    zc = zc < 16 ? 16 : zc;
+    zc = (zc + 7) / 8 * 8;
+    return zc >= p.n[2] ? 0 : (int)zc;
+}
+
 bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
     if (p.update == ST_WAVE) {
+        if (c.tsteps == 2 && !wave3d_tb2_supported(p.radius)) return false;
+        if (c.variant == ST_VARIANT_WAVE3D_LDS)
+            return (c.tile_y == 8 || c.tile_y == 16) && c.zchunk >= 0 && c.tsteps <= 1;
         return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
-               c.zchunk >= 0;
+               c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }
     if (p.ndim == 3) {
         return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&

@@ -14,6 +14,7 @@ struct Geom {
     int ndim;
     int nx, ny, nz;
     int shape, r, dtype, boundary;
+    bool iso;   // star with one weight per distance on every arm and sign
 };
 
 // Launch parameters chosen by the dispatch map.
@@ -42,6 +43,22 @@ struct WaveLaunch {
     float prev_sign;        // adj: next = 2 cur - prev_sign * prev (-1 on the first step, +1 after)
 };
 
+// Two fused forward leapfrog steps: (u_{t-1}, u_t) -> (u_{t+1}, u_{t+2}).
+// out1/out2 must not alias prev/cur (other workgroups read their halos).
+struct WaveTB2 {
+    const float* prev;
+    const float* cur;
+    float* out1;
+    float* out2;
+    const float* kappa;
+    int src_x, src_y, src_z;     // src_x < 0 = none
+    const float* amp1;           // added at the source to u_{t+1}
+    const float* amp2;           // added at the source to u_{t+2}
+    int rec_z;
+    float* trace1;               // plane for u_{t+1}[rec_z] or null
+    float* trace2;               // plane for u_{t+2}[rec_z] or null
+};
+
 // Launchers (return the launch status; asynchronous on `stream`).
 hipError_t launch_tb2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, int k, hipStream_t stream);
@@ -50,6 +67,12 @@ hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
 hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
                          const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
                          hipStream_t stream);
+hipError_t launch_wave3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                             const WaveTB2& w, hipStream_t stream);
+bool wave3d_tb2_supported(int r);
+hipError_t launch_wave3d_ring(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                              const WaveLaunch& w, hipStream_t stream);
+bool wave3d_ring_supported(int r);
 hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hipStream_t stream);
 hipError_t launch_fill(float* dst, float v, size_t n, hipStream_t stream);
 // loss = 1/2 sum (traces - target)^2 in double, two fixed-order passes

@@ -1,0 +1,168 @@
+// Forward leapfrog with the z-neighbours held in an LDS ring.
+//
+// Each arriving plane is staged once: its halo tile feeds the in-plane (x, y)
+// taps and its interior also enters a ring of 2R+2 interior planes in LDS.
+// The in-plane partial sum of plane z waits R planes in a short register
+// queue; when plane z+R has arrived, the z-taps of output z are read from the
+// ring.  Keeping the z-neighbours in LDS instead of a (2R+1)-deep register
+// queue of partial sums lowers the per-thread state to the in-plane partials,
+// which lets several workgroups share a CU (the plane stream of one
+// workgroup alone cannot cover HBM latency and the per-plane barrier).
+#include "internal.h"
+#include "zmarch.h"
+
+namespace stk {
+
+template <int R, int BC, int RY, int D, bool ISO>
+__global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
+                                                               int zc, int tiles_x, int tiles_y,
+                                                               Taps tp) {
+    using G = PlaneGeom<R, RY>;
+    constexpr int NR = 2 * R + 2;          // ring depth: one spare slot separates writers and readers
+    constexpr int IP = G::BX * G::BY;      // interior cells per plane
+    __shared__ float tile[2][G::H * G::W];
+    __shared__ float ring[NR][IP];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % tiles_x;
+    const int rest = b / tiles_x;
+    const int tyi = rest % tiles_y, zci = rest / tiles_y;
+    const int x0 = txi * G::BX, y0 = tyi * G::BY;
+    const int z0 = zci * zc, z1 = min(z0 + zc, nz);
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const int gx = x0 + tx;
+    const size_t plane_sz = (size_t)nx * ny;
+    const int zbeg = z0 - R, zend = z1 + R;
+
+    float pq[R + 1][RY];                   // in-plane partials of planes zp-R..zp
+    float vin[D][RY], vhalo[D][G::HT];
+    float pv[D][RY], kv[D][RY];            // u_{t-1}, kappa of the output plane
+#pragma unroll
+    for (int q = 0; q <= R; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) pq[q][i] = 0.f;
+
+    auto issue_point = [&](int slot, int zo) {
+        if (zo < z0 || zo >= z1 || gx >= nx) return;
+        const size_t zoff = (size_t)zo * plane_sz;
+        const float* pp = w.prev + zoff;
+        const float* kp = w.kappa + zoff;
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            const int gy = y0 + ty * RY + i;
+            const uint32_t o = (uint32_t)((gy < ny ? gy : 0) * nx + gx);
+            pv[slot][i] = __builtin_nontemporal_load(&pp[o]);
+            kv[slot][i] = __builtin_nontemporal_load(&kp[o]);
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (zbeg + d < zend) load_plane<R, RY, BC>(w.cur, nx, ny, nz, zbeg + d, x0, y0, vin[d], vhalo[d]);
+        issue_point(d, zbeg + d - R);
+    }
+
+    int slot = 0;   // ring slot of plane zp
+    for (int zs = zbeg; zs < zend; zs += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int zp = zs + d;
+            if (zp >= zend) break;
+            float* t = tile[zp & 1];
+            store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = vin[d][i];
+            if (zp + D < zend) load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp + D, x0, y0, vin[d], vhalo[d]);
+            __syncthreads();
+
+            float p[RY];
+            if constexpr (ISO) star_plane_iso<R, RY>(t, tp, p);
+            else star_plane<R, RY>(t, tp, p);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) pq[R][i] = p[i];
+
+            const int zo = zp - R;
+            if (zo >= z0 && gx < nx) {
+                const size_t zoff = (size_t)zo * plane_sz;
+                float* np_ = w.next + zoff;
+                // ring slots of planes zo-R .. zo+R: slot(zp - 2R + j), j = 0..2R
+                int sl[2 * R + 1];
+#pragma unroll
+                for (int j = 0; j <= 2 * R; ++j) {
+                    const int s2 = slot - 2 * R + j;
+                    sl[j] = s2 < 0 ? s2 + NR : s2;
+                }
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    const int cell = (ty * RY + i) * G::BX + tx;
+                    float a = pq[0][i];
+#pragma unroll
+                    for (int e = 1; e <= R; ++e) {
+                        if constexpr (ISO) {
+                            a = fmaf(tp.c[star_x<R>(e)], ring[sl[R - e]][cell] + ring[sl[R + e]][cell], a);
+                        } else {
+                            a = fmaf(tp.c[star_z<R>(-e)], ring[sl[R - e]][cell], a);
+                            a = fmaf(tp.c[star_z<R>(e)], ring[sl[R + e]][cell], a);
+                        }
+                    }
+                    const int gy = y0 + ty * RY + i;
+                    if (gy >= ny) continue;
+                    const uint32_t o = (uint32_t)(gy * nx + gx);
+                    float v = 2.f * ring[sl[R]][cell] - pv[d][i] + kv[d][i] * a;
+                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
+                    if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
+                    __builtin_nontemporal_store(v, &np_[o]);
+                }
+            }
+            issue_point(d, zp + D - R);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) pq[q][i] = pq[q + 1][i];
+            slot = slot + 1 == NR ? 0 : slot + 1;
+        }
+    }
+}
+
+bool wave3d_ring_supported(int r) { return r >= 1 && r <= 4; }
+
+template <int R, int BC, int RY>
+static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
+    using G = PlaneGeom<R, RY>;
+    constexpr int D = 2;
+    const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
+    const int nchunks = (g.nz + zc - 1) / zc;
+    const dim3 grid(tiles_x * tiles_y * nchunks), block(kThreads);
+    if (g.iso)
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, D, true>), grid, block, 0, s, w, g.nx, g.ny,
+                           g.nz, zc, tiles_x, tiles_y, tp);
+    else
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, D, false>), grid, block, 0, s, w, g.nx, g.ny,
+                           g.nz, zc, tiles_x, tiles_y, tp);
+    return hipGetLastError();
+}
+
+template <int R, int BC>
+static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const WaveLaunch& w,
+                        hipStream_t s) {
+    const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
+    if (c.tile_y >= 16) return go<R, BC, 4>(g, zc, tp, w, s);
+    return go<R, BC, 2>(g, zc, tp, w, s);
+}
+
+template <int R>
+static hipError_t go_bc(const Geom& g, const LaunchCfg& c, const Taps& tp, const WaveLaunch& w,
+                        hipStream_t s) {
+    return g.boundary == kPeriodic ? go_ry<R, kPeriodic>(g, c, tp, w, s) : go_ry<R, kZero>(g, c, tp, w, s);
+}
+
+hipError_t launch_wave3d_ring(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                              const WaveLaunch& w, hipStream_t stream) {
+    switch (g.r) {
+        case 1: return go_bc<1>(g, cfg, taps, w, stream);
+        case 2: return go_bc<2>(g, cfg, taps, w, stream);
+        case 3: return go_bc<3>(g, cfg, taps, w, stream);
+        case 4: return go_bc<4>(g, cfg, taps, w, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stk

@@ -4,7 +4,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/stencil.h"
+#include "stencil.h"
 #include "internal.h"
 
 struct st_plan {
@@ -14,6 +14,7 @@ struct st_plan {
     stk::Taps taps_t;               // compact transposed taps (offsets negated)
     stk::LaunchCfg cfg;
     int ckpt_every;
+    bool iso;                       // isotropic star: one weight per distance
     bool batched;
     std::vector<st_plan*> members;  // batched plans own their members
     // Batched launch: pinned host staging for the device work tables, and
@@ -43,9 +44,12 @@ std::string key_string(const CaseKey& k);
 LaunchCfg dispatch_lookup(const CaseKey& k);
 void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
 bool cfg_legal(const st_problem& p, const LaunchCfg& c);
+constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk from the grid
+int auto_zchunk(const st_problem& p, const LaunchCfg& c);
 
 void set_error(const char* fmt, ...);
 size_t batched_meta_bytes(const st_plan* plan, int steps);
 Geom geom_of(const st_problem& p);
+Geom plan_geom(const st_plan* pl);
 
 }  // namespace stk

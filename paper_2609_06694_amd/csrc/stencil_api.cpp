@@ -149,7 +149,23 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
     std::vector<float> flipped(pl->dense.rbegin(), pl->dense.rend());
     pl->taps = pack_taps(p->ndim, p->shape, p->radius, pl->dense);
     pl->taps_t = pack_taps(p->ndim, p->shape, p->radius, flipped);
+    pl->iso = false;
+    if (p->shape == ST_STAR) {
+        // One weight per distance on every arm and sign (e.g. a Laplacian).
+        bool iso = true;
+        const int arms = p->ndim == 3 ? 6 : 4;
+        for (int d = 1; d <= p->radius && iso; ++d) {
+            const float w = pl->taps.c[p->radius + d];   // +x arm at distance d
+            for (int a = 0; a < arms / 2; ++a)
+                for (int sgn = 0; sgn < 2; ++sgn) {
+                    const int slot = 2 * p->radius * a + (sgn ? p->radius + d : 1 + (-d + p->radius));
+                    iso = iso && pl->taps.c[slot] == w;
+                }
+        }
+        pl->iso = iso;
+    }
     pl->cfg = dispatch_lookup(classify(*p));
+    if (pl->cfg.zchunk == kAutoChunk) pl->cfg.zchunk = auto_zchunk(*p, pl->cfg);
     pl->ckpt_every = 20;
     pl->batched = false;
     if (opts) {
@@ -175,6 +191,14 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
 }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// One forward leapfrog step through the plan's forward kernel family.
+hipError_t wave_forward_launch(const st_plan* pl, const WaveLaunch& w, hipStream_t s) {
+    const Geom g = plan_geom(pl);
+    if (pl->cfg.variant == ST_VARIANT_WAVE3D_LDS) return launch_wave3d_ring(g, pl->cfg, pl->taps, w, s);
+    LaunchCfg c = pl->cfg;
+    return launch_wave3d(g, c, pl->taps, pl->taps, kWaveFwd, w, s);
+}
 
 // One launch of the linear sweep, k fused steps (k = 1 for 3D).
 hipError_t linear_launch(const st_plan* pl, const Taps& taps, const void* in, void* out, int k,
@@ -222,6 +246,93 @@ WaveLaunch wave_base() {
     return w;
 }
 
+bool use_tb2(const st_plan* pl) {
+    return pl->cfg.variant == ST_VARIANT_WAVE3D && pl->cfg.tsteps == 2 &&
+           wave3d_tb2_supported(pl->prob.radius);
+}
+
+// Forward leapfrog with two fused steps per launch.  A fused launch must not
+// write either of its inputs (other workgroups read their halos), so its
+// outputs rotate over three buffer pairs: A = (caller prev, caller out),
+// B and C in the workspace.  The pairs are chosen backwards from the last
+// launch (which writes A) as B, C, B, C, ...; the first launch therefore
+// never writes A, whose prev buffer is one of its inputs.  An odd step count
+// starts with one single-step launch done in place on the prev buffer.
+st_status run_wave_tb2(const st_plan* pl, const void* u_in, void* u_out, int steps,
+                       const st_wave_args* wa, void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t cells = cells_of(pl->prob);
+    const size_t gb = (cells * 4 + 255) / 256 * 256;
+    if (!ws || ws_bytes < 4 * gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", 4 * gb);
+    const Geom g = geom_of(pl->prob);
+    const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1];
+    float* P = (float*)wa->u_prev;
+    float* O = (float*)u_out;
+    float* W[4] = {(float*)ws, (float*)((char*)ws + gb), (float*)((char*)ws + 2 * gb),
+                   (float*)((char*)ws + 3 * gb)};
+    const float* prev = P;
+    const float* cur = (const float*)u_in;
+    const bool has_src = wa->src[0] >= 0 && wa->wavelet;
+    const bool rec = wa->rec_z >= 0 && wa->traces;
+    int t = 0;
+    if (steps % 2 == 1) {
+        // One single step in place on the prev buffer: (P, I) -> (I, P).
+        WaveLaunch w = wave_base();
+        w.prev = P;
+        w.cur = cur;
+        w.next = P;
+        w.kappa = wa->kappa;
+        if (has_src) {
+            w.src_x = (int)wa->src[0];
+            w.src_y = (int)wa->src[1];
+            w.src_z = (int)wa->src[2];
+            w.src_amp = wa->wavelet;
+        }
+        if (rec) {
+            w.rec_z = (int)wa->rec_z;
+            w.trace_t = wa->traces;
+        }
+        HIP_TRY(wave_forward_launch(pl, w, s));
+        prev = cur;
+        cur = P;
+        t = 1;
+    }
+    const int L = (steps - t) / 2;
+    if (L == 1 && (prev == P || cur == P || cur == O)) {
+        // The only fused launch cannot write A; land in B and copy.
+        WaveTB2 w{};
+        w.prev = prev; w.cur = cur; w.out1 = W[0]; w.out2 = W[1]; w.kappa = wa->kappa;
+        w.src_x = has_src ? (int)wa->src[0] : -1; w.src_y = (int)wa->src[1]; w.src_z = (int)wa->src[2];
+        w.amp1 = has_src ? wa->wavelet + t : nullptr; w.amp2 = has_src ? wa->wavelet + t + 1 : nullptr;
+        w.rec_z = rec ? (int)wa->rec_z : -1;
+        w.trace1 = rec ? wa->traces + (size_t)t * plane : nullptr;
+        w.trace2 = rec ? wa->traces + (size_t)(t + 1) * plane : nullptr;
+        HIP_TRY(launch_wave3d_tb2(g, pl->cfg, pl->taps, w, s));
+        HIP_TRY(hipMemcpyAsync(P, W[0], cells * 4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(O, W[1], cells * 4, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    for (int j = 1; j <= L; ++j) {
+        float* o1;
+        float* o2;
+        const int back = L - j;          // launches after this one
+        if (back == 0) { o1 = P; o2 = O; }
+        else if (back % 2 == 1) { o1 = W[0]; o2 = W[1]; }
+        else { o1 = W[2]; o2 = W[3]; }
+        WaveTB2 w{};
+        w.prev = prev; w.cur = cur; w.out1 = o1; w.out2 = o2; w.kappa = wa->kappa;
+        w.src_x = has_src ? (int)wa->src[0] : -1; w.src_y = (int)wa->src[1]; w.src_z = (int)wa->src[2];
+        w.amp1 = has_src ? wa->wavelet + t : nullptr; w.amp2 = has_src ? wa->wavelet + t + 1 : nullptr;
+        w.rec_z = rec ? (int)wa->rec_z : -1;
+        w.trace1 = rec ? wa->traces + (size_t)t * plane : nullptr;
+        w.trace2 = rec ? wa->traces + (size_t)(t + 1) * plane : nullptr;
+        HIP_TRY(launch_wave3d_tb2(g, pl->cfg, pl->taps, w, s));
+        prev = o1;
+        cur = o2;
+        t += 2;
+    }
+    return ST_OK;
+}
+
 // Leapfrog (forward or adjoint) over `steps` steps with the buffer schedule
 // b_t = out if (T - t) even else prev_buf, so u_T ends in u_out and u_{T-1}
 // in the caller's prev buffer.
@@ -235,6 +346,8 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
         if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
         return ST_OK;
     }
+    if (!adjoint && steps >= 2 && use_tb2(pl))
+        return run_wave_tb2(pl, u_in, u_out, steps, wa, ws, ws_bytes, s);
     if (u_in == u_out && (steps % 2) == 1) {
         if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
         HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
@@ -261,7 +374,7 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
                 w.rec_z = (int)wa->rec_z;
                 w.trace_t = wa->traces + (size_t)t * plane;
             }
-            HIP_TRY(launch_wave3d(g, pl->cfg, pl->taps, pl->taps, kWaveFwd, w, s));
+            HIP_TRY(wave_forward_launch(pl, w, s));
         } else {
             w.prev_sign = t == 0 ? -1.f : 1.f;
             HIP_TRY(launch_wave3d(g, pl->cfg, pl->taps_t, pl->taps, kWaveAdj, w, s));
@@ -427,6 +540,8 @@ size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode)
         return total + batched_meta_bytes(plan, steps);
     }
     if (mode == 1) return plan->prob.update == ST_WAVE && steps > 0 ? grad_layout(plan, steps).total : 0;
+    if (mode == 0 && plan->prob.update == ST_WAVE && use_tb2(plan))
+        return 4 * ((grid_bytes(plan->prob) + 255) / 256 * 256);
     if (mode == 2) {
         const size_t gb = (grid_bytes(plan->prob) + 255) / 256 * 256;
         const size_t kb = plan->prob.update == ST_WAVE ? gb : 0;
@@ -478,7 +593,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
             w.rec_z = (int)wave->rec_z;
             w.trace_t = traces + (size_t)t * plane;
         }
-        return launch_wave3d(g, plan->cfg, plan->taps, plan->taps, kWaveFwd, w, s);
+        return wave_forward_launch(plan, w, s);
     };
     auto pick = [&](const float* a, const float* b) -> float* {
         for (float* c : scratch)

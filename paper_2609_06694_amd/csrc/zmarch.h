@@ -50,7 +50,10 @@ __device__ __forceinline__ bool map_coord(int& i, int n) {
 }
 
 // Loads one plane of `f` (interior RY values and this thread's halo share)
-// into registers, converted to f32.  Out-of-domain cells read as zero.
+// into registers, converted to f32.  Out-of-domain cells read as zero.  The
+// loads are predicated rather than followed by a select: a select would
+// consume each value as soon as it is loaded and force a wait right there,
+// while predicated loads stay in flight until the plane is staged in LDS.
 template <int R, int RY, int BC, typename T>
 __device__ __forceinline__ void load_plane(const T* __restrict__ f, int nx, int ny, int nz, int zp,
                                            int x0, int y0, float (&in)[RY],
@@ -104,6 +107,29 @@ __device__ __forceinline__ void store_plane(float* __restrict__ tile, const floa
             halo_coord<R, RY>(h, ly, lx);
             tile[ly * G::W + lx] = SCALED ? halo[j] * scale_halo[j] : halo[j];
         }
+    }
+}
+
+// In-plane contribution of an isotropic star (one weight per distance, equal
+// on every arm): c0 u + sum_d w_d (u(x-d) + u(x+d) + u(y-d) + u(y+d)).
+// Taps: c[0] = centre, c[star_x<R>(d)] = w_d.
+template <int R, int RY>
+__device__ __forceinline__ void star_plane_iso(const float* __restrict__ tile, const Taps& tp,
+                                               float (&p)[RY]) {
+    using G = PlaneGeom<R, RY>;
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const float* base = tile + (ty * RY) * G::W + R + tx;
+    float col[RY + 2 * R];
+#pragma unroll
+    for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const float* row = tile + (R + ty * RY + i) * G::W + R + tx;
+        float a = tp.c[0] * col[i + R];
+#pragma unroll
+        for (int d = 1; d <= R; ++d)
+            a = fmaf(tp.c[star_x<R>(d)], (col[i + R - d] + col[i + R + d]) + (row[-d] + row[d]), a);
+        p[i] = a;
     }
 }
 

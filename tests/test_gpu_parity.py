@@ -138,8 +138,11 @@ def _wave_inputs(rng, n):
 
 
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
-@pytest.mark.parametrize("ty,zc", [(16, 0), (8, 9), (32, 64)])
-def test_wave_forward_vs_oracle(st, bc, ty, zc):
+@pytest.mark.parametrize("variant,ty,zc", [(3, 16, 0), (3, 8, 9), (3, 32, 64), (4, 8, 0), (4, 16, 9), (4, 8, 5)])
+@pytest.mark.parametrize("aniso", [False, True])
+def test_wave_forward_vs_oracle(st, bc, variant, ty, zc, aniso):
+    """Both forward kernel families (partial-sum queue, LDS ring), with the
+    isotropic Laplacian and with an anisotropic radius-4 star."""
     rng = np.random.default_rng(21)
     n = (75, 41, 33)
     kappa, u0, up = _wave_inputs(rng, n)
@@ -147,13 +150,55 @@ def test_wave_forward_vs_oracle(st, bc, ty, zc):
     src = (30, 20, 17)
     wav = wl.ricker(steps, 4.0)
     bcode = wl.ZERO if bc == "zero" else wl.PERIODIC
-    m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc)
+    lap = None
+    if aniso:   # a valid but anisotropic star: different weights per axis and sign
+        lap = oracle.laplacian3d(4)
+        for j, f in ((1, 1.1), (2, 0.9), (3, 1.2), (4, 0.8)):
+            lap[(4 * 9 + 4) * 9 + 4 + j] *= f
+            lap[(4 * 9 + 4 - j) * 9 + 4] *= 1.0 / f
+        lap = lap.astype(np.float32)
+    m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc, variant=variant, coeffs=lap)
     uT, uT1, tr = m.forward(_dev(u0), _dev(up), _dev(kappa), steps, src=src, wavelet=_dev(wav), rec_z=5,
                             record=True)
-    ra, rb, rtr = oracle.wave_forward(up, u0, kappa, steps, boundary=bcode, src=src, wavelet=wav, rec_z=5)
+    ra, rb, rtr = oracle.wave_forward(up, u0, kappa, steps, boundary=bcode, src=src, wavelet=wav, rec_z=5,
+                                      lap=None if lap is None else lap.astype(np.float64))
     assert rel_l2(_host(uT), rb) <= 1e-5
     assert rel_l2(_host(uT1), ra) <= 1e-5
     assert rel_l2(_host(tr), rtr) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("n,ty,zc", [((75, 41, 33), 8, 0), ((130, 37, 29), 16, 9), ((20, 9, 11), 8, 4)])
+@pytest.mark.parametrize("steps", [2, 3, 4, 7])
+def test_wave_two_step_fused_vs_oracle(st, bc, n, ty, zc, steps):
+    """Two leapfrog steps per launch (temporal blocking) against the oracle,
+    with source and receiver, on grids narrower and wider than one tile."""
+    rng = np.random.default_rng(23 + steps)
+    kappa, u0, up = _wave_inputs(rng, n)
+    src = (n[0] // 2 + 1, n[1] // 2, n[2] // 2 - 1)
+    wav = wl.ricker(steps, 3.0)
+    rec = n[2] // 3
+    bcode = wl.ZERO if bc == "zero" else wl.PERIODIC
+    m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc, tsteps=2)
+    assert m.describe()["tsteps"] == 2
+    uT, uT1, tr = m.forward(_dev(u0), _dev(up), _dev(kappa), steps, src=src, wavelet=_dev(wav), rec_z=rec,
+                            record=True)
+    ra, rb, rtr = oracle.wave_forward(up, u0, kappa, steps, boundary=bcode, src=src, wavelet=wav, rec_z=rec)
+    e = (rel_l2(_host(uT), rb), rel_l2(_host(uT1), ra), rel_l2(_host(tr), rtr))
+    assert max(e) <= 1e-5, e
+
+
+def test_wave_two_step_inplace_output(st):
+    rng = np.random.default_rng(29)
+    n = (70, 30, 26)
+    kappa, u0, up = _wave_inputs(rng, n)
+    m = st.WaveModel(n, tsteps=2)
+    for steps in (4, 5, 6):
+        d = _dev(u0)
+        p = _dev(up)
+        m.forward(d, p, _dev(kappa), steps, out=d, prev_inout=True)
+        ra, rb, _ = oracle.wave_forward(up, u0, kappa, steps)
+        assert rel_l2(_host(d), rb) <= 1e-5 and rel_l2(_host(p), ra) <= 1e-5, steps
 
 
 @pytest.mark.parametrize("steps", [1, 2, 5])
