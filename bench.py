@@ -84,7 +84,7 @@ def stream_ceiling(dev, torch):
     return res
 
 
-WAVE_SOURCES = ["paper_2609_06694_amd/csrc/kernels_wave.hip", "paper_2609_06694_amd/csrc/zmarch.h",
+WAVE_SOURCES = ["paper_2609_06694_amd/csrc/kernels_wave_ring.hip", "paper_2609_06694_amd/csrc/zmarch.h",
                 "paper_2609_06694_amd/csrc/common.h"]
 TRAFFIC_PROFILE = "profiles/wave3d_fwd_r4_512cube_pmc_traffic.md"
 
@@ -281,7 +281,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_bytes_per_launch": tbytes, "traffic_source": TRAFFIC_PROFILE,
-                     "kernel": "wave3d_kernel<fwd,R=4,zero>", "bytes_per_cell": WAVE_BYTES_PER_CELL,
+                     "kernel": "wave3d_ring_kernel<R=4,zero,RY=2,D=2,iso>", "bytes_per_cell": WAVE_BYTES_PER_CELL,
                      "cells_per_launch": cells, "launch_ms": round(launch_ms, 5)},
     }
     extras = {}

@@ -20,6 +20,7 @@ constexpr int kMaxTaps = 81;       // 2D box r = 4
 //  star: [centre, x:-r..-1,+1..+r, y:-r..-1,+1..+r, z:-r..-1,+1..+r]
 struct Taps {
     float c[kMaxTaps];
+    float sum;   // sum of all weights (for the difference form of a star)
 };
 
 template <int R>

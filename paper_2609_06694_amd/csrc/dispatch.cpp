@@ -80,8 +80,8 @@ std::string key_string(const CaseKey& k) {
 static LaunchCfg default_cfg(const CaseKey& k) {
     LaunchCfg c{};
     if (k.update == ST_WAVE) {
-        c.variant = ST_VARIANT_WAVE3D;
-        c.tile_y = 16;
+        c.variant = ST_VARIANT_WAVE3D_LDS;
+        c.tile_y = 8;
         c.tsteps = 1;
         c.zchunk = kAutoChunk;
         return c;

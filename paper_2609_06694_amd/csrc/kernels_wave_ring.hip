@@ -1,5 +1,9 @@
 // Forward leapfrog with the z-neighbours held in an LDS ring.
 //
+// L(u) is evaluated in difference form, sum_{d != 0} c_d (u(x+d) - u(x)) plus
+// (sum of weights) u(x): the same operator, with far less cancellation error
+// than the direct weighted sum for high-order Laplacians.
+//
 // Each arriving plane is staged once: its halo tile feeds the in-plane (x, y)
 // taps and its interior also enters a ring of 2R+2 interior planes in LDS.
 // The in-plane partial sum of plane z waits R planes in a short register
@@ -73,9 +77,8 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
             if (zp + D < zend) load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp + D, x0, y0, vin[d], vhalo[d]);
             __syncthreads();
 
-            float p[RY];
-            if constexpr (ISO) star_plane_iso<R, RY>(t, tp, p);
-            else star_plane<R, RY>(t, tp, p);
+            float p[RY], uc[RY];
+            star_plane_diff<R, RY, ISO>(t, tp, p, uc);
 #pragma unroll
             for (int i = 0; i < RY; ++i) pq[R][i] = p[i];
 
@@ -93,20 +96,22 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     const int cell = (ty * RY + i) * G::BX + tx;
+                    const float uo = ring[sl[R]][cell];
                     float a = pq[0][i];
 #pragma unroll
                     for (int e = 1; e <= R; ++e) {
                         if constexpr (ISO) {
-                            a = fmaf(tp.c[star_x<R>(e)], ring[sl[R - e]][cell] + ring[sl[R + e]][cell], a);
+                            a = fmaf(tp.c[star_x<R>(e)], (ring[sl[R - e]][cell] - uo) + (ring[sl[R + e]][cell] - uo), a);
                         } else {
-                            a = fmaf(tp.c[star_z<R>(-e)], ring[sl[R - e]][cell], a);
-                            a = fmaf(tp.c[star_z<R>(e)], ring[sl[R + e]][cell], a);
+                            a = fmaf(tp.c[star_z<R>(-e)], ring[sl[R - e]][cell] - uo, a);
+                            a = fmaf(tp.c[star_z<R>(e)], ring[sl[R + e]][cell] - uo, a);
                         }
                     }
+                    a = fmaf(tp.sum, uo, a);
                     const int gy = y0 + ty * RY + i;
                     if (gy >= ny) continue;
                     const uint32_t o = (uint32_t)(gy * nx + gx);
-                    float v = 2.f * ring[sl[R]][cell] - pv[d][i] + kv[d][i] * a;
+                    float v = 2.f * uo - pv[d][i] + kv[d][i] * a;
                     if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
                     if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
                     __builtin_nontemporal_store(v, &np_[o]);

@@ -78,6 +78,9 @@ Taps pack_taps(int ndim, int shape, int r, const std::vector<float>& dense) {
     auto at = [&](int dz, int dy, int dx) {
         return dense[(size_t)((dz + rz) * w + (dy + r)) * w + (dx + r)];
     };
+    double sum = 0.0;
+    for (float v : dense) sum += (double)v;
+    t.sum = (float)sum;
     if (shape == ST_BOX) {
         for (size_t i = 0; i < dense.size() && i < (size_t)kMaxTaps; ++i) t.c[i] = dense[i];
         return t;

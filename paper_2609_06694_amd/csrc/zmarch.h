@@ -110,6 +110,43 @@ __device__ __forceinline__ void store_plane(float* __restrict__ tile, const floa
     }
 }
 
+// In-plane arms of a star in difference form, sum over the x and y arms of
+// c_d (u(x+d) - u(x)), for this thread's RY rows; u0 receives u(x).  Adding
+// (sum of all weights) * u(x) and the z arms later gives L(u) exactly in real
+// arithmetic, while each difference of nearby values is formed with little
+// rounding: a high-order Laplacian otherwise cancels terms of size ~8|u| to a
+// result much smaller than u.
+template <int R, int RY, bool ISO>
+__device__ __forceinline__ void star_plane_diff(const float* __restrict__ tile, const Taps& tp,
+                                                float (&p)[RY], float (&u0)[RY]) {
+    using G = PlaneGeom<R, RY>;
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const float* base = tile + (ty * RY) * G::W + R + tx;
+    float col[RY + 2 * R];
+#pragma unroll
+    for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const float* row = tile + (R + ty * RY + i) * G::W + R + tx;
+        const float c = col[i + R];
+        u0[i] = c;
+        float a = 0.f;
+#pragma unroll
+        for (int d = 1; d <= R; ++d) {
+            if constexpr (ISO) {
+                a = fmaf(tp.c[star_x<R>(d)], ((col[i + R - d] - c) + (col[i + R + d] - c)) +
+                                                 ((row[-d] - c) + (row[d] - c)), a);
+            } else {
+                a = fmaf(tp.c[star_y<R>(-d)], col[i + R - d] - c, a);
+                a = fmaf(tp.c[star_y<R>(d)], col[i + R + d] - c, a);
+                a = fmaf(tp.c[star_x<R>(-d)], row[-d] - c, a);
+                a = fmaf(tp.c[star_x<R>(d)], row[d] - c, a);
+            }
+        }
+        p[i] = a;
+    }
+}
+
 // In-plane contribution of an isotropic star (one weight per distance, equal
 // on every arm): c0 u + sum_d w_d (u(x-d) + u(x+d) + u(y-d) + u(y+d)).
 // Taps: c[0] = centre, c[star_x<R>(d)] = w_d.

@@ -1,0 +1,67 @@
+"""GPU tests of the autotuner: it only adopts candidates that pass the
+parity check against the plain single-step configuration, a planted
+wrong-but-faster candidate family is rejected, and the tuned plan still
+matches the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from mathref import rel_l2
+from paper_2609_06694_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def st():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_06694_amd import stencil
+    return stencil
+
+
+def test_autotune_2d_adopts_a_passing_candidate(st):
+    rng = np.random.default_rng(61)
+    c = wl.random_unit_sum_coeffs(rng, 2, wl.BOX, 2)
+    u = wl.small_random_grid(rng, 2, (600, 500), np.float32, 0.0, 1.0)
+    s = st.Stencil((600, 500), "box", 2, c)
+    stats = s.autotune()
+    d = s.describe()
+    print("2D tuned:", d, stats)
+    assert stats["tried"] >= 8 and stats["rejected"] == 0 and d["variant"] == "tb2d"
+    got = s.apply(torch.from_numpy(u).cuda(), 9).cpu().numpy()
+    assert rel_l2(got, oracle.sweep(u, c, wl.BOX, 2, wl.PERIODIC, 9)) <= 1e-5
+
+
+def test_autotune_rejects_planted_wrong_candidates(st, monkeypatch):
+    """With the fault switch, every fused-step candidate computes with a
+    perturbed centre weight; all of them must be rejected before timing."""
+    monkeypatch.setenv("STENCIL_TUNE_FAULT", "1")
+    rng = np.random.default_rng(62)
+    c = wl.random_unit_sum_coeffs(rng, 2, wl.STAR, 3)
+    u = wl.small_random_grid(rng, 2, (700, 300), np.float32, 0.0, 1.0)
+    s = st.Stencil((700, 300), "star", 3, c, boundary="zero")
+    stats = s.autotune()
+    d = s.describe()
+    print("faulted 2D tuned:", d, stats)
+    assert stats["rejected"] > 0 and d["tsteps"] == 1
+    got = s.apply(torch.from_numpy(u).cuda(), 6).cpu().numpy()
+    assert rel_l2(got, oracle.sweep(u, c, wl.STAR, 3, wl.ZERO, 6)) <= 1e-5
+
+
+def test_autotune_3d_and_wave(st, monkeypatch):
+    monkeypatch.setenv("STENCIL_TUNE_FAULT", "1")
+    rng = np.random.default_rng(63)
+    c = wl.random_unit_sum_coeffs(rng, 3, wl.BOX, 1)
+    u = wl.small_random_grid(rng, 3, (130, 70, 90), np.float16, 0.0, 1.0)
+    s = st.Stencil((130, 70, 90), "box", 1, c, dtype="f16")
+    stats = s.autotune()
+    print("3D tuned:", s.describe(), stats)
+    assert stats["rejected"] > 0 and s.describe()["tile_y"] != 32
+    got = s.apply(torch.from_numpy(u).cuda(), 3).cpu().numpy()
+    assert rel_l2(got.astype(np.float64), oracle.sweep(u, c, wl.BOX, 1, wl.PERIODIC, 3)) <= 2e-3
+    m = st.WaveModel((96, 64, 80))
+    stats = m.autotune()
+    print("wave tuned:", m.describe(), stats)
+    assert stats["rejected"] > 0 and m.describe()["tile_y"] != 32

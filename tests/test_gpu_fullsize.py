@@ -1,0 +1,160 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times, on sampled output blocks.
+
+The oracle computes a sampled block of the final state from a sub-box that
+extends R*T cells beyond it (T steps of a radius-R stencil move information
+at most R cells per step), taken with wrap-around for periodic boundaries and
+clipped to the grid for the zero boundary (where clipping reproduces the
+zero frame exactly).  Inside the block the sub-box result equals the
+full-grid result.  Tolerances as in the small parity tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from mathref import rel_l2
+from paper_2609_06694_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def st():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_06694_amd import stencil
+    return stencil
+
+
+def _extract(a, lo, hi, periodic):
+    """a[lo:hi] per axis (array axis order), wrapping if periodic."""
+    idx = [np.arange(l, h) for l, h in zip(lo, hi)]
+    if periodic:
+        idx = [i % n for i, n in zip(idx, a.shape)]
+    return a[np.ix_(*idx)]
+
+
+def _sample_linear(case, got, starts, block):
+    """Check sampled blocks of a linear sweep's output against the oracle."""
+    per = case.boundary == wl.PERIODIC
+    m = case.radius * case.steps
+    errs = []
+    for s0 in starts:
+        if per:
+            lo = [s - m for s in s0]
+            hi = [s + b + m for s, b in zip(s0, block)]
+            sub = _extract(case.u0, lo, hi, True)
+            ref = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps)
+            ref = ref[tuple(slice(m, m + b) for b in block)]
+        else:
+            lo = [max(0, s - m) for s in s0]
+            hi = [min(n, s + b + m) for s, b, n in zip(s0, block, case.u0.shape)]
+            sub = case.u0[tuple(slice(l, h) for l, h in zip(lo, hi))]
+            ref = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps)
+            ref = ref[tuple(slice(s - l, s - l + b) for s, l, b in zip(s0, lo, block))]
+        g = got[tuple(slice(s, s + b) for s, b in zip(s0, block))]
+        errs.append(rel_l2(g.astype(np.float64), ref))
+    return max(errs)
+
+
+def test_fullsize_jacobi2d(st):
+    case = wl.jacobi2d()
+    s = st.Stencil(case.n[:2], "star", 1, case.coeffs)
+    got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
+    ref = oracle.sweep(case.u0, case.coeffs, wl.STAR, 1, wl.PERIODIC, case.steps)
+    assert rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
+def test_fullsize_box3d(st, dtype):
+    case = wl.box3d(dtype=dtype)
+    dt = "f16" if dtype == wl.F16 else "f32"
+    s = st.Stencil(case.n, "box", 1, case.coeffs, dtype=dt)
+    got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
+    starts = [(0, 0, 0), (507, 250, 480)]   # [z, y, x]: a corner (wraps) and a far face
+    e = _sample_linear(case, got, starts, (5, 8, 8))
+    print(f"box3d {dt} 512^3 x50 sampled rel-L2 {e:.2e}")
+    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
+def test_fullsize_box2d(st, dtype):
+    case = wl.box2d(dtype=dtype)
+    dt = "f16" if dtype == wl.F16 else "f32"
+    s = st.Stencil(case.n[:2], "box", 2, case.coeffs, dtype=dt)
+    got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
+    starts = [(0, 0), (2000, 3001), (4080, 4080), (1234, 0)]
+    e = _sample_linear(case, got, starts, (16, 16))
+    print(f"box2d {dt} 4096^2 x100 sampled rel-L2 {e:.2e}")
+    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+
+
+def test_fullsize_wave3d(st):
+    case = wl.wave3d(n=512, steps=20)
+    m = st.WaveModel(case.n, radius=4, boundary="zero")
+    out, prev, _ = m.forward(torch.from_numpy(case.u0).cuda(), torch.from_numpy(case.u_prev).cuda(),
+                             torch.from_numpy(case.kappa).cuda(), case.steps)
+    got, gotp = out.cpu().numpy(), prev.cpu().numpy()
+    R, T = 4, case.steps
+    mg = R * T
+    errs = []
+    # [z, y, x]: the pulse centre, an off-centre block inside the pulse, and a
+    # corner block the pulse never reaches (must stay exactly zero)
+    for s0 in [(252, 250, 249), (270, 236, 262), (0, 0, 0)]:
+        block = (4, 4, 8)
+        lo = [max(0, s - mg) for s in s0]
+        hi = [min(512, s + b + mg) for s, b in zip(s0, block)]
+        sl = tuple(slice(l, h) for l, h in zip(lo, hi))
+        ra, rb, _ = oracle.wave_forward(case.u_prev[sl], case.u0[sl], case.kappa[sl], T)
+        inner = tuple(slice(s - l, s - l + b) for s, l, b in zip(s0, lo, block))
+        blk = tuple(slice(s, s + b) for s, b in zip(s0, block))
+        if np.linalg.norm(rb[inner]) > 0:
+            errs.append(rel_l2(got[blk], rb[inner]))
+            errs.append(rel_l2(gotp[blk], ra[inner]))
+        else:   # a block the pulse never reaches must be exactly zero
+            assert not np.any(got[blk]) and not np.any(gotp[blk])
+    print(f"wave 512^3 x20 sampled rel-L2 {max(errs):.2e}")
+    assert errs and max(errs) <= 1e-5
+
+
+def test_fullsize_batch64_separate_launches(st):
+    cases = wl.batch2d()
+    errs = []
+    for c in cases:
+        s = st.Stencil(c.n[:2], wl.SHAPE_NAMES[c.shape], c.radius, c.coeffs)
+        got = s.apply(torch.from_numpy(c.u0).cuda(), c.steps).cpu().numpy()
+        ny, nx = c.u0.shape
+        errs.append(_sample_linear(c, got, [(0, 0), (ny - 8, nx // 3)], (8, 8)))
+    print(f"64 grids x32 sampled rel-L2 max {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+
+
+def test_fullsize_wave_gradient_checkpointing(st):
+    """At the full gradient size (256^3, 200 steps), checkpointing every 20
+    steps gives exactly the gradient of keeping every state, the loss is the
+    trace misfit, and the gradient is finite and nonzero."""
+    case = wl.wavegrad3d()
+    n = case.n
+    dev = torch.device("cuda")
+    kap = torch.from_numpy(case.kappa).to(dev)
+    zeros = torch.zeros(n[::-1], dtype=torch.float32, device=dev)
+    wav = torch.from_numpy(case.wavelet).to(dev)
+    fwd = st.WaveModel(n)
+    _, _, target = fwd.forward(zeros, zeros, torch.from_numpy(case.kappa_true).to(dev), case.steps,
+                               src=case.src, wavelet=wav, rec_z=case.rec_z, record=True)
+    target = target.contiguous()
+    res = []
+    for K in (20, 200):
+        m = st.WaveModel(n, ckpt_every=K)
+        dk, loss = m.gradient(zeros, zeros, kap, case.steps, case.src, wav, case.rec_z, target)
+        res.append((dk.cpu().numpy(), float(loss.item())))
+        del m
+        torch.cuda.empty_cache()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
+    _, _, tr = fwd.forward(zeros, zeros, kap, case.steps, src=case.src, wavelet=wav, rec_z=case.rec_z,
+                           record=True)
+    J = 0.5 * float(((tr.double() - target.double()) ** 2).sum().item())
+    assert abs(J - res[0][1]) <= 1e-9 * abs(J)
+    g = res[0][0]
+    assert np.isfinite(g).all() and np.abs(g).max() > 0

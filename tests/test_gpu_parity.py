@@ -179,7 +179,7 @@ def test_wave_two_step_fused_vs_oracle(st, bc, n, ty, zc, steps):
     wav = wl.ricker(steps, 3.0)
     rec = n[2] // 3
     bcode = wl.ZERO if bc == "zero" else wl.PERIODIC
-    m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc, tsteps=2)
+    m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc, tsteps=2, variant=3)
     assert m.describe()["tsteps"] == 2
     uT, uT1, tr = m.forward(_dev(u0), _dev(up), _dev(kappa), steps, src=src, wavelet=_dev(wav), rec_z=rec,
                             record=True)
@@ -192,7 +192,7 @@ def test_wave_two_step_inplace_output(st):
     rng = np.random.default_rng(29)
     n = (70, 30, 26)
     kappa, u0, up = _wave_inputs(rng, n)
-    m = st.WaveModel(n, tsteps=2)
+    m = st.WaveModel(n, tsteps=2, variant=3)
     for steps in (4, 5, 6):
         d = _dev(u0)
         p = _dev(up)
