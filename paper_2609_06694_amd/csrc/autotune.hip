@@ -79,13 +79,20 @@ hipError_t fill(void* p, const st_problem& pr, size_t cells, uint32_t seed, floa
 std::vector<LaunchCfg> candidates(const st_problem& p) {
     std::vector<LaunchCfg> out;
     if (p.update == ST_WAVE || p.ndim == 3) {
-        const int var = p.update == ST_WAVE ? ST_VARIANT_WAVE3D : ST_VARIANT_ZM3D;
-        for (int ty : {8, 16, 32})
-            for (int zc : {32, 64, 128, 0}) {
-                if (zc != 0 && zc >= p.n[2]) continue;
-                LaunchCfg c{var, 0, ty, 1, zc};
-                out.push_back(c);
-            }
+        std::vector<int> vars;
+        // Forward wave candidates come from the difference-form (LDS ring)
+        // family only: the direct weighted sum is faster by a few percent
+        // but its f32 cancellation error, invisible over the short parity
+        // probe, exceeds the 1e-5 gate after tens of steps.
+        if (p.update == ST_WAVE) vars = {ST_VARIANT_WAVE3D_LDS};
+        else vars = {ST_VARIANT_ZM3D};
+        for (int var : vars)
+            for (int ty : {8, 16, 32})
+                for (int zc : {32, 64, 128, 256, 0}) {
+                    if (zc != 0 && zc >= p.n[2]) continue;
+                    LaunchCfg c{var, 0, ty, 1, zc};
+                    if (cfg_legal(p, c)) out.push_back(c);
+                }
         return out;
     }
     for (int tx : {64, 128, 256})
@@ -103,7 +110,7 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
 hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, const Taps& taps,
                    const void* in, void* out, void* tmp, const float* kappa, int steps,
                    hipStream_t s) {
-    Geom g = geom_of(p);
+    Geom g = plan_geom(pl);
     if (p.update == ST_WAVE) {
         const float* prev = (const float*)tmp;
         const float* cur = (const float*)in;
@@ -116,7 +123,8 @@ hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, c
             w.cur = cur;
             w.next = ((steps - t - 1) % 2 == 0) ? (float*)out : (float*)tmp;
             w.kappa = kappa;
-            hipError_t e = launch_wave3d(g, c, taps, pl->taps, kWaveFwd, w, s);
+            hipError_t e = c.variant == ST_VARIANT_WAVE3D_LDS ? launch_wave3d_ring(g, c, taps, w, s)
+                                                              : launch_wave3d(g, c, taps, pl->taps, kWaveFwd, w, s);
             if (e != hipSuccess) return e;
             prev = cur;
             cur = w.next;
@@ -143,7 +151,7 @@ bool faulty(const st_problem& p, const LaunchCfg& c) {
     const char* f = getenv("STENCIL_TUNE_FAULT");
     if (!f || f[0] != '1') return false;
     if (p.ndim == 2 && p.update == ST_LINEAR) return c.tsteps > 1;
-    return c.tile_y == 32;
+    return c.tile_y == 16;
 }
 
 st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, TuneStats& st) {

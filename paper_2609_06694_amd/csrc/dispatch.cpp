@@ -6,6 +6,8 @@
 // defaults cover every legal case; the autotuner overwrites cells in process
 // and, when STENCIL_TUNE_CACHE names a file, appends them there so later
 // processes start from the tuned entries.
+#include <dlfcn.h>
+
 #include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
@@ -116,11 +118,7 @@ static bool g_cache_loaded = false;
 
 // Cache file format, one entry per line (later lines win):
 //   ndim shape r dtype boundary update size_class slab variant tile_x tile_y tsteps zchunk
-static void load_cache_locked() {
-    if (g_cache_loaded) return;
-    g_cache_loaded = true;
-    const char* path = getenv("STENCIL_TUNE_CACHE");
-    if (!path || !*path) return;
+static void read_map_file(const char* path) {
     FILE* f = fopen(path, "r");
     if (!f) return;
     char line[256];
@@ -135,6 +133,24 @@ static void load_cache_locked() {
     }
     fclose(f);
 }
+
+// The measured map shipped next to the library (written by the autotuner on
+// an MI355X), then the caller's tuning cache on top of it.
+static void load_cache_locked() {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    Dl_info info;
+    if (dladdr((void*)&read_map_file, &info) && info.dli_fname) {
+        std::string dir(info.dli_fname);
+        const size_t slash = dir.find_last_of('/');
+        dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+        read_map_file((dir + "/dispatch_mi355x.txt").c_str());
+    }
+    const char* path = getenv("STENCIL_TUNE_CACHE");
+    if (path && *path) read_map_file(path);
+}
+
+LaunchCfg default_dispatch(const CaseKey& k) { return default_cfg(k); }
 
 LaunchCfg dispatch_lookup(const CaseKey& k) {
     std::lock_guard<std::mutex> lk(g_map_mu);
@@ -159,12 +175,12 @@ void dispatch_store(const CaseKey& k, const LaunchCfg& c, bool persist) {
     fclose(f);
 }
 
-// Plane chunk giving about 512 workgroups: enough to fill 256 CUs twice
-// while keeping the z-halo re-read (2R planes per chunk) small.
+// Plane chunk giving about 1024 workgroups (four per CU) while keeping the
+// z-halo re-read (2R planes per chunk) small; the measured map overrides it.
 int auto_zchunk(const st_problem& p, const LaunchCfg& c) {
     const int rows = c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8);
     const int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
-    int64_t zc = p.n[2] * tiles / 512;
+    int64_t zc = p.n[2] * tiles / 1024;
     zc = zc < 16 ? 16 : zc;
     zc = (zc + 7) / 8 * 8;
     return zc >= p.n[2] ? 0 : (int)zc;

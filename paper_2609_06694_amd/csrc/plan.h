@@ -42,6 +42,7 @@ std::string key_string(const CaseKey& k);
 // Default entry for a case (compiled in), then the tuning cache file and the
 // in-process table written by the autotuner override it.
 LaunchCfg dispatch_lookup(const CaseKey& k);
+LaunchCfg default_dispatch(const CaseKey& k);
 void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
 bool cfg_legal(const st_problem& p, const LaunchCfg& c);
 constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk from the grid

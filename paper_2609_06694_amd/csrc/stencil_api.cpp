@@ -169,6 +169,11 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
     }
     pl->cfg = dispatch_lookup(classify(*p));
     if (pl->cfg.zchunk == kAutoChunk) pl->cfg.zchunk = auto_zchunk(*p, pl->cfg);
+    if (!cfg_legal(pl->prob, pl->cfg)) {   // a stale map entry falls back to the default
+        LaunchCfg d = default_dispatch(classify(*p));
+        if (d.zchunk == kAutoChunk) d.zchunk = auto_zchunk(*p, d);
+        pl->cfg = d;
+    }
     pl->ckpt_every = 20;
     pl->batched = false;
     if (opts) {

@@ -1,0 +1,49 @@
+"""Regenerate the shipped dispatch map (dispatch_mi355x.txt next to the
+library) by running the autotuner on the benchmark workloads' cases.
+
+Usage (on the GPU machine): python -m paper_2609_06694_amd.tune_defaults OUT
+Each tuned case key is appended to OUT; copy OUT to the package directory as
+dispatch_mi355x.txt to make it the default map.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+
+
+def main(out: str) -> None:
+    os.environ["STENCIL_TUNE_CACHE"] = out
+    os.environ.pop("STENCIL_TUNE_FAULT", None)
+    import torch  # noqa: F401  (device memory for the scratch buffers)
+    from . import stencil as st, workloads as wl
+    open(out, "w").write("# ndim shape r dtype boundary update size_class slab variant tile_x tile_y tsteps zchunk\n")
+    plans = []
+    c = wl.jacobi2d()
+    plans.append(("jacobi2d 512^2", st.Stencil(c.n[:2], "star", 1, c.coeffs)))
+    for dt in ("f16", "f32"):
+        c = wl.box3d(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
+        plans.append((f"box3d 512^3 {dt}", st.Stencil((512, 512, 512), "box", 1, c.coeffs, dtype=dt)))
+        c = wl.box2d(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
+        plans.append((f"box2d 4096^2 {dt}", st.Stencil((4096, 4096), "box", 2, c.coeffs, dtype=dt)))
+    plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))
+    plans.append(("wave 256^3", st.WaveModel((256, 256, 256))))
+    # One representative grid per case key of the 64-grid workload.
+    seen = set()
+    for g in wl.batch2d():
+        cells = g.n[0] * g.n[1]
+        size_class = 0 if cells <= 1 << 20 else (1 if cells <= 1 << 24 else 2)
+        slab = max(g.n[:2]) >= 4 * min(g.n[:2])
+        key = (g.shape, g.radius, size_class, slab)
+        if key in seen:
+            continue
+        seen.add(key)
+        plans.append((g.name, st.Stencil(g.n[:2], wl.SHAPE_NAMES[g.shape], g.radius, g.coeffs)))
+    for name, p in plans:
+        stats = p.autotune()
+        print(f"{name}: {p.describe()} {stats}", flush=True)
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "dispatch_tuned.txt")
