@@ -201,7 +201,12 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     for (const LaunchCfg& c : candidates(p)) {
         ++st.tried;
         Taps taps = pl->taps;
-        if (faulty(p, c)) taps.c[0] += 0.25f;
+        // A planted fault shifts the centre weight; the difference-form
+        // kernels read the weight sum in its place, so shift both.
+        if (faulty(p, c)) {
+            taps.c[0] += 0.25f;
+            taps.sum += 0.25f;
+        }
         // Parity: same inputs (tmp is the wave's u_{-1}; refill it each time).
         T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
         T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
