@@ -89,9 +89,18 @@ WAVE_SOURCES = ["paper_2609_06694_amd/csrc/kernels_wave_ring.hip", "paper_2609_0
 TRAFFIC_PROFILE = "profiles/wave3d_fwd_r4_512cube_pmc_traffic.md"
 
 
-def measured_traffic():
+def ring_kernel_name(disp):
+    """Instantiation of the LDS-ring leapfrog kernel a dispatch selects: two
+    rows per thread, tile_y / 2 waves per workgroup."""
+    if disp.get("variant") != "wave3d_lds":
+        return disp.get("variant")
+    return f"wave3d_ring_kernel<R=4,zero,RY=2,NW={disp['tile_y'] // 2},D=2,iso>"
+
+
+def measured_traffic(kernel):
     """HBM bytes per launch of the leapfrog kernel from the committed PMC
-    summary, or None when the kernel sources changed since it was taken."""
+    summary, or None when the kernel sources or the instantiation the
+    dispatch selects changed since it was taken."""
     import hashlib
     try:
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in WAVE_SOURCES)
@@ -99,7 +108,7 @@ def measured_traffic():
         for line in open(os.path.join(ROOT, TRAFFIC_PROFILE)):
             if line.startswith("traffic_json:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec.get("source_hash") == h:
+                if rec.get("source_hash") == h and rec.get("kernel") == kernel:
                     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
@@ -269,7 +278,7 @@ def main():
     cells = case.cells
     value = gcells(cells, case.steps, ms_pass)
     achieved = WAVE_BYTES_PER_CELL * cells / (launch_ms * 1e-3) / 1e9
-    tbytes = measured_traffic()
+    tbytes = measured_traffic(ring_kernel_name(disp))
     traffic = None if tbytes is None else round(tbytes / (launch_ms * 1e-3) / 1e9, 1)
     line = {
         "metric": "GCells/s", "value": round(value, 2), "unit": "GCells/s", "n_gpus": 1,
@@ -281,7 +290,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_bytes_per_launch": tbytes, "traffic_source": TRAFFIC_PROFILE,
-                     "kernel": "wave3d_ring_kernel<R=4,zero,RY=2,D=2,iso>", "bytes_per_cell": WAVE_BYTES_PER_CELL,
+                     "kernel": ring_kernel_name(disp), "bytes_per_cell": WAVE_BYTES_PER_CELL,
                      "cells_per_launch": cells, "launch_ms": round(launch_ms, 5)},
     }
     extras = {}

@@ -83,7 +83,7 @@ static LaunchCfg default_cfg(const CaseKey& k) {
     LaunchCfg c{};
     if (k.update == ST_WAVE) {
         c.variant = ST_VARIANT_WAVE3D_LDS;
-        c.tile_y = 8;
+        c.tile_y = 32;
         c.tsteps = 1;
         c.zchunk = kAutoChunk;
         return c;
@@ -177,10 +177,36 @@ void dispatch_store(const CaseKey& k, const LaunchCfg& c, bool persist) {
 
 // Plane chunk giving about 1024 workgroups (four per CU) while keeping the
 // z-halo re-read (2R planes per chunk) small; the measured map overrides it.
+// Workgroups of a configuration that fit on one CU at once (register and
+// LDS limits of the compiled kernels): the LDS-ring wave kernel runs 4-, 8-
+// and 16-wave workgroups for 8-, 16- and 32-row tiles; the direct-form wave
+// kernels (adjoint, gradient) hold about two waves per SIMD; the linear
+// z-march runs four 4-wave workgroups.
+static int resident_wgs(const st_problem& p, const LaunchCfg& c) {
+    if (p.update == ST_WAVE && c.variant == ST_VARIANT_WAVE3D_LDS)
+        return c.tile_y >= 32 ? 1 : (c.tile_y >= 16 ? 2 : 3);
+    if (p.update == ST_WAVE) return c.tile_y >= 32 ? 1 : 2;   // adjoint/gradient: ~2 waves per SIMD
+    return 4;
+}
+
+static int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
+}
+
+// Plane chunk for a z-march: split z so that the grid fills every CU about
+// once (one round of workgroups; a partial second round costs a whole
+// round's time), with chunks of at least 16 planes.
 int auto_zchunk(const st_problem& p, const LaunchCfg& c) {
     const int rows = c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8);
     const int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
-    int64_t zc = p.n[2] * tiles / 1024;
+    const int64_t target = (int64_t)device_cus() * resident_wgs(p, c);
+    const int64_t nch = (target + tiles - 1) / tiles;
+    if (nch <= 1) return 0;
+    int64_t zc = (p.n[2] + nch - 1) / nch;
     zc = zc < 16 ? 16 : zc;
     zc = (zc + 7) / 8 * 8;
     return zc >= p.n[2] ? 0 : (int)zc;
@@ -190,7 +216,7 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
     if (p.update == ST_WAVE) {
         if (c.tsteps == 2 && !wave3d_tb2_supported(p.radius)) return false;
         if (c.variant == ST_VARIANT_WAVE3D_LDS)
-            return (c.tile_y == 8 || c.tile_y == 16) && c.zchunk >= 0 && c.tsteps <= 1;
+            return (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1;
         return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }

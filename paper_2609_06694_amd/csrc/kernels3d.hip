@@ -6,12 +6,12 @@ namespace stk {
 
 // D planes are kept in flight per workgroup: the register slot of plane zp
 // is refilled with plane zp + D as soon as zp has been staged in LDS.
-template <int R, int SHAPE, typename T, int BC, int RY, int D>
-__global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in,
-                                                        T* __restrict__ out, int nx, int ny,
-                                                        int nz, int zc, int tiles_x, int tiles_y,
-                                                        Taps tp) {
-    using G = PlaneGeom<R, RY>;
+template <int R, int SHAPE, typename T, int BC, int RY, int NW, int D>
+__global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ in,
+                                                          T* __restrict__ out, int nx, int ny,
+                                                          int nz, int zc, int tiles_x, int tiles_y,
+                                                          Taps tp) {
+    using G = PlaneGeom<R, RY, NW>;
     __shared__ float tile[2][G::H * G::W];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int txi = b % tiles_x;
@@ -30,27 +30,34 @@ __global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in
 #pragma unroll
         for (int i = 0; i < RY; ++i) acc[q][i] = 0.f;
 
-    float vin[D][RY], vhalo[D][G::HT];
+    // In-flight planes stay in storage precision until staged.  Plane
+    // indices past the end of the march are clamped to its last plane (a
+    // cache hit), keeping every load unconditional.
+    T vin[D][RY], vhalo[D][G::HT];
+    uint32_t vm[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        if (zbeg + d < zend) load_plane<R, RY, BC>(in, nx, ny, nz, zbeg + d, x0, y0, vin[d], vhalo[d]);
+        vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), x0, y0, vin[d], vhalo[d]);
 
     for (int zb = zbeg; zb < zend; zb += D) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int zp = zb + d;
-            if (zp >= zend) break;
+            // The march runs in whole groups of D planes: up to D-1 planes
+            // past zend are clamped loads that emit no output.  (A uniform
+            // early exit here would let the compiler assume fewer loads in
+            // flight at the loop head and wait for all of them.)
             float* t = tile[zp & 1];
-            store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
+            store_plane<R, RY, BC, T, NW>(t, vin[d], vhalo[d], vm[d]);
             float cen[RY];
 #pragma unroll
-            for (int i = 0; i < RY; ++i) cen[i] = vin[d][i];
-            if (zp + D < zend) load_plane<R, RY, BC>(in, nx, ny, nz, zp + D, x0, y0, vin[d], vhalo[d]);
+            for (int i = 0; i < RY; ++i) cen[i] = masked<BC>(vin[d][i], vm[d], i);
+            vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), x0, y0, vin[d], vhalo[d]);
             __syncthreads();
 
             if constexpr (SHAPE == kStar) {
                 float p[RY];
-                star_plane<R, RY>(t, tp, p);
+                star_plane<R, RY, NW>(t, tp, p);
                 // plane zp feeds output zo = zp - dz with weight c_z(dz); slot R - dz
 #pragma unroll
                 for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
@@ -82,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void zm3d_kernel(const T* __restrict__ in
 
             // Output plane zp - R has received all 2R+1 planes.
             const int zo = zp - R;
-            if (zo >= z0 && gx < nx) {
+            if (zo >= z0 && zo < z1 && gx < nx) {
                 T* o = out + (size_t)zo * nx * ny;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
@@ -114,15 +121,15 @@ constexpr int zm3d_depth() {
     return RY >= 8 ? 1 : (RY >= 4 ? 2 : (R >= 3 ? 3 : 4));
 }
 
-template <int R, int SHAPE, typename T, int BC, int RY>
+template <int R, int SHAPE, typename T, int BC, int RY, int NW>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const void* in, void* out,
                      hipStream_t s) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = zm3d_depth<R, RY>();
-    hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY, D>), dim3(tiles_x * tiles_y * nchunks),
-                       dim3(kThreads), 0, s, (const T*)in, (T*)out, g.nx, g.ny, g.nz, zc, tiles_x,
+    hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks),
+                       dim3(G::NT), 0, s, (const T*)in, (T*)out, g.nx, g.ny, g.nz, zc, tiles_x,
                        tiles_y, tp);
     return hipGetLastError();
 }
@@ -132,9 +139,9 @@ static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const
                         void* out, hipStream_t s) {
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
     switch (zm3d_rows(c)) {
-        case 8: return go<R, SHAPE, T, BC, 2>(g, zc, tp, in, out, s);
-        case 16: return go<R, SHAPE, T, BC, 4>(g, zc, tp, in, out, s);
-        default: return go<R, SHAPE, T, BC, 8>(g, zc, tp, in, out, s);
+        case 8: return go<R, SHAPE, T, BC, 2, 4>(g, zc, tp, in, out, s);
+        case 16: return go<R, SHAPE, T, BC, 4, 4>(g, zc, tp, in, out, s);
+        default: return go<R, SHAPE, T, BC, 8, 4>(g, zc, tp, in, out, s);
     }
 }
 

@@ -19,11 +19,11 @@ namespace stk {
 // with plane zp + D as soon as it has been staged in LDS, and the pointwise
 // operands of output plane zo are issued D planes before zo is emitted, so
 // D HBM round trips overlap instead of one per plane.
-template <int MODE, int R, int BC, int RY, int D>
-__global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, int ny, int nz,
-                                                          int zc, int tiles_x, int tiles_y,
-                                                          Taps tp, Taps tp2) {
-    using G = PlaneGeom<R, RY>;
+template <int MODE, int R, int BC, int RY, int NW, int D>
+__global__ __launch_bounds__(NW * kWave) void wave3d_kernel(WaveLaunch w, int nx, int ny, int nz,
+                                                            int zc, int tiles_x, int tiles_y,
+                                                            Taps tp, Taps tp2) {
+    using G = PlaneGeom<R, RY, NW>;
     constexpr bool TWO = (MODE == kWaveGrad);       // second stencil field u_t
     constexpr bool SCALE = (MODE != kWaveFwd);      // first field is kappa (.) lambda
     __shared__ float tile[TWO ? 4 : 2][G::H * G::W];
@@ -62,24 +62,32 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
     float vin[D][RY], vhalo[D][G::HT];
     float kin[SCALE ? D : 1][RY], khalo[SCALE ? D : 1][G::HT];
     float uin[TWO ? D : 1][RY], uhalo[TWO ? D : 1][G::HT];
+    uint32_t vm[D];   // validity mask of the planes (same cells for all fields)
     float pq[D][RY], kq[MODE == kWaveFwd ? D : 1][RY], gq[TWO ? D : 1][RY];
+    // Read once, up front: a load inside the per-cell branch would make the
+    // wave wait for every load in flight.
+    const float amp = (MODE == kWaveFwd && w.src_x >= 0) ? *w.src_amp : 0.f;
 
+    // All loads are unconditional; plane indices past the end of the march
+    // are clamped to its last plane (see load_plane).
     auto issue_plane = [&](int slot, int zp) {
-        load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp, x0, y0, vin[slot], vhalo[slot]);
-        if constexpr (SCALE) load_plane<R, RY, BC>(w.kappa, nx, ny, nz, zp, x0, y0, kin[slot], khalo[slot]);
-        if constexpr (TWO) load_plane<R, RY, BC>(w.u, nx, ny, nz, zp, x0, y0, uin[slot], uhalo[slot]);
+        zp = min(zp, zend - 1);
+        vm[slot] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, zp, x0, y0, vin[slot], vhalo[slot]);
+        if constexpr (SCALE) load_plane<R, RY, BC, float, NW>(w.kappa, nx, ny, nz, zp, x0, y0, kin[slot], khalo[slot]);
+        if constexpr (TWO) load_plane<R, RY, BC, float, NW>(w.u, nx, ny, nz, zp, x0, y0, uin[slot], uhalo[slot]);
     };
-    // Pointwise operands of output plane zo (read by the thread that writes it).
+    // Pointwise operands of output plane zo (read by the thread that writes
+    // it), clamped to the chunk and the grid; clamped values are never used.
     auto issue_point = [&](int slot, int zo) {
-        if (zo < z0 || zo >= z1 || gx >= nx) return;
-        const size_t zoff = (size_t)zo * plane_sz;
+        const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
         const float* pp = w.prev + zoff;
         const float* kp = w.kappa + zoff;
         const float* gp = w.grad + zoff;
+        const int gxc = min(gx, nx - 1);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            const int gy = y0 + ty * RY + i;
-            const uint32_t o = (uint32_t)((gy < ny ? gy : 0) * nx + gx);
+            const int gy = min(y0 + ty * RY + i, ny - 1);
+            const uint32_t o = (uint32_t)(gy * nx + gxc);
             pq[slot][i] = __builtin_nontemporal_load(&pp[o]);
             if constexpr (MODE == kWaveFwd) kq[slot][i] = __builtin_nontemporal_load(&kp[o]);
             if constexpr (TWO) gq[slot][i] = __builtin_nontemporal_load(&gp[o]);
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
 
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        if (zbeg + d < zend) issue_plane(d, zbeg + d);
+        issue_plane(d, zbeg + d);
         issue_point(d, zbeg + d - R);
     }
 
@@ -96,7 +104,10 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int zp = zb + d;
-            if (zp >= zend) break;
+            // The march runs in whole groups of D planes: up to D-1 planes
+            // past zend are clamped loads that emit no output.  (A uniform
+            // early exit here would let the compiler assume fewer loads in
+            // flight at the loop head and wait for all of them.)
             float* t;
             float* t2 = nullptr;
             if constexpr (TWO) {
@@ -105,23 +116,24 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
             } else {
                 t = tile[zp & 1];
             }
-            if constexpr (SCALE) store_plane<R, RY, true>(t, vin[d], vhalo[d], kin[d], khalo[d]);
-            else store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
-            if constexpr (TWO) store_plane<R, RY, false>(t2, uin[d], uhalo[d], uin[d], uhalo[d]);
+            if constexpr (SCALE) store_plane<R, RY, BC, true, float, NW>(t, vin[d], vhalo[d], vm[d], kin[d], khalo[d]);
+            else store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
+            if constexpr (TWO) store_plane<R, RY, BC, float, NW>(t2, uin[d], uhalo[d], vm[d]);
             float cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
-                cq[R][i] = vin[d][i];
-                if constexpr (SCALE) cen[i] = vin[d][i] * kin[d][i];
-                else cen[i] = vin[d][i];
-                if constexpr (TWO) cq2[R][i] = uin[d][i];
+                const float v = masked<BC>(vin[d][i], vm[d], i);
+                cq[R][i] = v;
+                if constexpr (SCALE) cen[i] = v * kin[d][i];
+                else cen[i] = v;
+                if constexpr (TWO) cq2[R][i] = masked<BC>(uin[d][i], vm[d], i);
             }
-            if (zp + D < zend) issue_plane(d, zp + D);
+            issue_plane(d, zp + D);
             __syncthreads();
 
             {
                 float p[RY];
-                star_plane<R, RY>(t, tp, p);
+                star_plane<R, RY, NW>(t, tp, p);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) acc[R][i] += p[i];
 #pragma unroll
@@ -134,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
             }
             if constexpr (TWO) {
                 float p[RY];
-                star_plane<R, RY>(t2, tp2, p);
+                star_plane<R, RY, NW>(t2, tp2, p);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) acc2[R][i] += p[i];
 #pragma unroll
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
 
             // Output plane zo = zp - R has received all 2R+1 planes.
             const int zo = zp - R;
-            if (zo >= z0 && gx < nx) {
+            if (zo >= z0 && zo < z1 && gx < nx) {
                 const size_t zoff = (size_t)zo * plane_sz;
                 float* np_ = w.next + zoff;
                 float* gp = w.grad + zoff;
@@ -160,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
                     float v;
                     if constexpr (MODE == kWaveFwd) {
                         v = 2.f * cq[0][i] - pq[d][i] + kq[d][i] * acc[0][i];
-                        if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
+                        if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += amp;
                         if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
                     } else if constexpr (MODE == kWaveAdj) {
                         v = 2.f * cq[0][i] - w.prev_sign * pq[d][i] + acc[0][i];
@@ -198,6 +210,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_kernel(WaveLaunch w, int nx, 
 
 bool wave3d_supported(int r) { return r >= 1 && r <= 4; }
 
+
 // Planes in flight per workgroup: deeper for thin tiles (few registers per
 // plane), shallower for the two-field gradient step.
 template <int MODE, int RY>
@@ -205,15 +218,15 @@ constexpr int wave_depth() {
     return MODE == kWaveGrad ? (RY >= 4 ? 1 : 2) : (RY >= 8 ? 1 : (RY >= 4 ? 2 : 4));
 }
 
-template <int MODE, int R, int BC, int RY>
+template <int MODE, int R, int BC, int RY, int NW>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const Taps& tp2, const WaveLaunch& w,
                      hipStream_t s) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = wave_depth<MODE, RY>();
-    hipLaunchKernelGGL((wave3d_kernel<MODE, R, BC, RY, D>), dim3(tiles_x * tiles_y * nchunks),
-                       dim3(kThreads), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+    hipLaunchKernelGGL((wave3d_kernel<MODE, R, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks),
+                       dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
     return hipGetLastError();
 }
 
@@ -222,9 +235,9 @@ static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const
                         const WaveLaunch& w, hipStream_t s) {
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
     switch (zm3d_rows(c)) {
-        case 8: return go<MODE, R, BC, 2>(g, zc, tp, tp2, w, s);
-        case 16: return go<MODE, R, BC, 4>(g, zc, tp, tp2, w, s);
-        default: return go<MODE, R, BC, 8>(g, zc, tp, tp2, w, s);
+        case 8: return go<MODE, R, BC, 2, 4>(g, zc, tp, tp2, w, s);
+        case 16: return go<MODE, R, BC, 4, 4>(g, zc, tp, tp2, w, s);
+        default: return go<MODE, R, BC, 4, 8>(g, zc, tp, tp2, w, s);
     }
 }
 

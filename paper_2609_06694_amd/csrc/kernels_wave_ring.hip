@@ -17,11 +17,11 @@
 
 namespace stk {
 
-template <int R, int BC, int RY, int D, bool ISO>
-__global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
-                                                               int zc, int tiles_x, int tiles_y,
-                                                               Taps tp) {
-    using G = PlaneGeom<R, RY>;
+template <int R, int BC, int RY, int NW, int D, bool ISO>
+__global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
+                                                                 int zc, int tiles_x, int tiles_y,
+                                                                 Taps tp) {
+    using G = PlaneGeom<R, RY, NW>;
     constexpr int NR = 2 * R + 2;          // ring depth: one spare slot separates writers and readers
     constexpr int IP = G::BX * G::BY;      // interior cells per plane
     __shared__ float tile[2][G::H * G::W];
@@ -39,28 +39,34 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
 
     float pq[R + 1][RY];                   // in-plane partials of planes zp-R..zp
     float vin[D][RY], vhalo[D][G::HT];
+    uint32_t vm[D];
     float pv[D][RY], kv[D][RY];            // u_{t-1}, kappa of the output plane
+    // The source amplitude is read once, up front: a load inside the
+    // per-cell branch would make the wave wait for every load in flight.
+    const float amp = w.src_x >= 0 ? *w.src_amp : 0.f;
 #pragma unroll
     for (int q = 0; q <= R; ++q)
 #pragma unroll
         for (int i = 0; i < RY; ++i) pq[q][i] = 0.f;
 
+    // Unconditional loads (clamped to the chunk and the grid; values at
+    // clamped cells are never used), for the reason given at load_plane.
     auto issue_point = [&](int slot, int zo) {
-        if (zo < z0 || zo >= z1 || gx >= nx) return;
-        const size_t zoff = (size_t)zo * plane_sz;
+        const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
         const float* pp = w.prev + zoff;
         const float* kp = w.kappa + zoff;
+        const int gxc = min(gx, nx - 1);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            const int gy = y0 + ty * RY + i;
-            const uint32_t o = (uint32_t)((gy < ny ? gy : 0) * nx + gx);
+            const int gy = min(y0 + ty * RY + i, ny - 1);
+            const uint32_t o = (uint32_t)(gy * nx + gxc);
             pv[slot][i] = __builtin_nontemporal_load(&pp[o]);
             kv[slot][i] = __builtin_nontemporal_load(&kp[o]);
         }
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        if (zbeg + d < zend) load_plane<R, RY, BC>(w.cur, nx, ny, nz, zbeg + d, x0, y0, vin[d], vhalo[d]);
+        vm[d] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), x0, y0, vin[d], vhalo[d]);
         issue_point(d, zbeg + d - R);
     }
 
@@ -69,21 +75,24 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int zp = zs + d;
-            if (zp >= zend) break;
+            // The march runs in whole groups of D planes: up to D-1 planes
+            // past zend are clamped loads that emit no output.  (A uniform
+            // early exit here would let the compiler assume fewer loads in
+            // flight at the loop head and wait for all of them.)
             float* t = tile[zp & 1];
-            store_plane<R, RY, false>(t, vin[d], vhalo[d], vin[d], vhalo[d]);
+            store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
 #pragma unroll
-            for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = vin[d][i];
-            if (zp + D < zend) load_plane<R, RY, BC>(w.cur, nx, ny, nz, zp + D, x0, y0, vin[d], vhalo[d]);
+            for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
+            vm[d] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zp + D, zend - 1), x0, y0, vin[d], vhalo[d]);
             __syncthreads();
 
             float p[RY], uc[RY];
-            star_plane_diff<R, RY, ISO>(t, tp, p, uc);
+            star_plane_diff<R, RY, ISO, NW>(t, tp, p, uc);
 #pragma unroll
             for (int i = 0; i < RY; ++i) pq[R][i] = p[i];
 
             const int zo = zp - R;
-            if (zo >= z0 && gx < nx) {
+            if (zo >= z0 && zo < z1 && gx < nx) {
                 const size_t zoff = (size_t)zo * plane_sz;
                 float* np_ = w.next + zoff;
                 // ring slots of planes zo-R .. zo+R: slot(zp - 2R + j), j = 0..2R
@@ -112,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
                     if (gy >= ny) continue;
                     const uint32_t o = (uint32_t)(gy * nx + gx);
                     float v = 2.f * uo - pv[d][i] + kv[d][i] * a;
-                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += *w.src_amp;
+                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += amp;
                     if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
                     __builtin_nontemporal_store(v, &np_[o]);
                 }
@@ -129,19 +138,19 @@ __global__ __launch_bounds__(kThreads) void wave3d_ring_kernel(WaveLaunch w, int
 
 bool wave3d_ring_supported(int r) { return r >= 1 && r <= 4; }
 
-template <int R, int BC, int RY>
+template <int R, int BC, int RY, int NW>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     constexpr int D = 2;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
-    const dim3 grid(tiles_x * tiles_y * nchunks), block(kThreads);
+    const dim3 grid(tiles_x * tiles_y * nchunks), block(G::NT);
     if (g.iso)
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, D, true>), grid, block, 0, s, w, g.nx, g.ny,
-                           g.nz, zc, tiles_x, tiles_y, tp);
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true>), grid, block, 0, s, w, g.nx,
+                           g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     else
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, D, false>), grid, block, 0, s, w, g.nx, g.ny,
-                           g.nz, zc, tiles_x, tiles_y, tp);
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false>), grid, block, 0, s, w, g.nx,
+                           g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     return hipGetLastError();
 }
 
@@ -149,8 +158,12 @@ template <int R, int BC>
 static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const WaveLaunch& w,
                         hipStream_t s) {
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
-    if (c.tile_y >= 16) return go<R, BC, 4>(g, zc, tp, w, s);
-    return go<R, BC, 2>(g, zc, tp, w, s);
+    // Two rows per thread at every tile height: taller tiles add waves (up
+    // to 16, a 1024-thread workgroup) rather than registers, so occupancy
+    // stays at four waves per SIMD while the halo share of each plane falls.
+    if (c.tile_y >= 32) return go<R, BC, 2, 16>(g, zc, tp, w, s);
+    if (c.tile_y >= 16) return go<R, BC, 2, 8>(g, zc, tp, w, s);
+    return go<R, BC, 2, 4>(g, zc, tp, w, s);
 }
 
 template <int R>

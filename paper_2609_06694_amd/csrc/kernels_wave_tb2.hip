@@ -64,6 +64,7 @@ __global__ __launch_bounds__(kThreads, 2) void wave3d_tb2_kernel(WaveTB2 w, int 
     }
 
     float vin[D][RYA], vhalo[D][GA::HT];
+    uint32_t vm[D];
     float pA[D][RYA], kA[D][RYA];    // u_{t-1}, kappa at stage-A cells of plane za
     float uB[D][RYB], kB[D][RYB];    // u_t, kappa at stage-B cells of plane zb
 
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kThreads, 2) void wave3d_tb2_kernel(WaveTB2 w, int 
 
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        if (zbeg + d < zend) load_plane<R, RYA, BC>(w.cur, nx, ny, nz, zbeg + d, ex0, ey0, vin[d], vhalo[d]);
+        vm[d] = load_plane<R, RYA, BC>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), ex0, ey0, vin[d], vhalo[d]);
         issue_a(d, zbeg + d - R);
         issue_b(d, zbeg + d - 2 * R);
     }
@@ -109,14 +110,14 @@ __global__ __launch_bounds__(kThreads, 2) void wave3d_tb2_kernel(WaveTB2 w, int 
             if (zp >= zend) break;
             // ---- stage A: accumulate u_t plane zp into u_{t+1} partial sums
             float* ta = tA[zp & 1];
-            store_plane<R, RYA, false>(ta, vin[d], vhalo[d], vin[d], vhalo[d]);
+            store_plane<R, RYA, BC>(ta, vin[d], vhalo[d], vm[d]);
             float cen[RYA];
 #pragma unroll
             for (int i = 0; i < RYA; ++i) {
-                cen[i] = vin[d][i];
-                cqA[R][i] = vin[d][i];
+                cen[i] = masked<BC>(vin[d][i], vm[d], i);
+                cqA[R][i] = cen[i];
             }
-            if (zp + D < zend) load_plane<R, RYA, BC>(w.cur, nx, ny, nz, zp + D, ex0, ey0, vin[d], vhalo[d]);
+            vm[d] = load_plane<R, RYA, BC>(w.cur, nx, ny, nz, min(zp + D, zend - 1), ex0, ey0, vin[d], vhalo[d]);
             __syncthreads();
             {
                 float p[RYA];

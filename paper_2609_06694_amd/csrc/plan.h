@@ -13,6 +13,7 @@ struct st_plan {
     stk::Taps taps;                 // compact forward taps
     stk::Taps taps_t;               // compact transposed taps (offsets negated)
     stk::LaunchCfg cfg;
+    stk::LaunchCfg adj_cfg;         // wave adjoint and gradient steps (direct-form kernel)
     int ckpt_every;
     bool iso;                       // isotropic star: one weight per distance
     bool batched;

@@ -13,20 +13,21 @@
 
 namespace stk {
 
-template <int R, int RY>
+template <int R, int RY, int NW = 4>
 struct PlaneGeom {
+    static constexpr int NT = NW * kWave;                      // threads per workgroup
     static constexpr int BX = kWave;
-    static constexpr int BY = 4 * RY;
+    static constexpr int BY = NW * RY;
     static constexpr int W = BX + 2 * R;
     static constexpr int H = BY + 2 * R;
     static constexpr int NH = W * H - BX * BY;                 // halo cells per plane
-    static constexpr int HT = (NH + kThreads - 1) / kThreads;  // halo cells per thread
+    static constexpr int HT = (NH + NT - 1) / NT;              // halo cells per thread
 };
 
 // LDS coordinates of halo cell h (0 <= h < NH).
-template <int R, int RY>
+template <int R, int RY, int NW = 4>
 __device__ __forceinline__ void halo_coord(int h, int& ly, int& lx) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     if (h < 2 * R * G::W) {
         const int row = h / G::W;
         lx = h - row * G::W;
@@ -49,65 +50,122 @@ __device__ __forceinline__ bool map_coord(int& i, int n) {
     return i >= 0 && i < n;
 }
 
-// Loads one plane of `f` (interior RY values and this thread's halo share)
-// into registers, converted to f32.  Out-of-domain cells read as zero.  The
-// loads are predicated rather than followed by a select: a select would
-// consume each value as soon as it is loaded and force a wait right there,
-// while predicated loads stay in flight until the plane is staged in LDS.
-template <int R, int RY, int BC, typename T>
-__device__ __forceinline__ void load_plane(const T* __restrict__ f, int nx, int ny, int nz, int zp,
-                                           int x0, int y0, float (&in)[RY],
-                                           float (&halo)[PlaneGeom<R, RY>::HT]) {
-    using G = PlaneGeom<R, RY>;
+// Moves a grid coordinate onto a cell whose address is always valid:
+// periodic boundaries wrap; the zero frame clamps into the grid and reports
+// whether the cell was inside (an outside cell is loaded from the clamped
+// address and zeroed when the value is consumed).
+template <int BC>
+__device__ __forceinline__ bool fix_coord(int& i, int n) {
+    if (BC == kPeriodic) {
+        if (n >= kMaxRadius) {
+            // Uniform branch.  Needed coordinates lie within R <= n of the
+            // grid, so one period suffices; the clamp only keeps cells past
+            // every neighbourhood (tile overhang of tiny grids) addressable.
+            i = i < 0 ? i + n : (i >= n ? i - n : i);
+            i = min(i, n - 1);
+        } else {
+            i = wrap_index(i, n);
+        }
+        return true;
+    }
+    const bool ok = (unsigned)i < (unsigned)n;
+    i = min(max(i, 0), n - 1);
+    return ok;
+}
+
+// A loaded value as f32, or zero if mask bit `bit` says its cell lies
+// outside the domain (zero frame only).
+template <int BC, typename T>
+__device__ __forceinline__ float masked(T v, uint32_t m, int bit) {
+    const float f = to_f32(v);
+    if (BC == kPeriodic) return f;
+    return ((m >> bit) & 1u) ? f : 0.f;
+}
+
+// Issues the loads of one plane of `f` (this thread's RY interior values and
+// its halo share) into registers, in storage precision, and returns the
+// validity mask (bit i: interior value i, bit RY + j: halo value j).
+// Every lane loads from a valid address and no load sits under a branch:
+// the compiler can then count the loads still in flight and wait for exactly
+// the plane it consumes, so D planes really are in flight at once; a load
+// under a divergent branch (or a select right after it) makes it wait for
+// every outstanding load instead.
+template <int R, int RY, int BC, typename T, int NW = 4>
+__device__ __forceinline__ uint32_t load_plane(const T* __restrict__ f, int nx, int ny, int nz, int zp,
+                                               int x0, int y0, T (&in)[RY],
+                                               T (&halo)[PlaneGeom<R, RY, NW>::HT]) {
+    using G = PlaneGeom<R, RY, NW>;
+    static_assert(RY + G::HT <= 32, "validity mask holds 32 cells");
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     int gz = zp;
-    const bool zin = map_coord<BC>(gz, nz);
+    const bool zin = fix_coord<BC>(gz, nz);
     const T* plane = f + (size_t)gz * nx * ny;
     const bool inner = x0 - R >= 0 && y0 - R >= 0 && x0 + G::BX + R <= nx && y0 + G::BY + R <= ny;
+    uint32_t m = 0;
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
         int gx = x0 + tx, gy = y0 + ty * RY + i;
         bool ok = zin;
-        if (!inner) ok = ok && map_coord<BC>(gx, nx) && map_coord<BC>(gy, ny);
-        in[i] = ok ? to_f32(plane[(uint32_t)(gy * nx + gx)]) : 0.f;
+        if (!inner) {
+            const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
+            ok = ok && okx && oky;
+        }
+        in[i] = plane[(uint32_t)(gy * nx + gx)];
+        m |= (uint32_t)ok << i;
     }
 #pragma unroll
     for (int j = 0; j < G::HT; ++j) {
-        const int h = threadIdx.x + j * kThreads;
-        float v = 0.f;
+        const int h = threadIdx.x + j * G::NT;
+        const bool hv = h < G::NH;   // the last round of halo cells is partial
+        int ly, lx;
+        halo_coord<R, RY, NW>(hv ? h : 0, ly, lx);
+        int gx = x0 - R + lx, gy = y0 - R + ly;
+        bool ok = zin && hv;
+        if (!inner) {
+            const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
+            ok = ok && okx && oky;
+        }
+        halo[j] = plane[(uint32_t)(gy * nx + gx)];
+        m |= (uint32_t)ok << (RY + j);
+    }
+    return m;
+}
+
+// Writes a loaded plane (mask m from load_plane) into an LDS tile of H x W
+// floats, multiplying by `scale_in[i]` / `scale_halo[j]` when SCALED (used
+// for kappa (.) lambda; the scale is read at the same cells, so the mask of
+// the plane also covers it).
+template <int R, int RY, int BC, bool SCALED, typename T, int NW = 4>
+__device__ __forceinline__ void store_plane(float* __restrict__ tile, const T (&in)[RY],
+                                            const T (&halo)[PlaneGeom<R, RY, NW>::HT], uint32_t m,
+                                            const float (&scale_in)[RY],
+                                            const float (&scale_halo)[PlaneGeom<R, RY, NW>::HT]) {
+    using G = PlaneGeom<R, RY, NW>;
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const float v = masked<BC>(in[i], m, i);
+        tile[(R + ty * RY + i) * G::W + R + tx] = SCALED ? v * scale_in[i] : v;
+    }
+#pragma unroll
+    for (int j = 0; j < G::HT; ++j) {
+        const int h = threadIdx.x + j * G::NT;
         if (h < G::NH) {
             int ly, lx;
-            halo_coord<R, RY>(h, ly, lx);
-            int gx = x0 - R + lx, gy = y0 - R + ly;
-            bool ok = zin;
-            if (!inner) ok = ok && map_coord<BC>(gx, nx) && map_coord<BC>(gy, ny);
-            if (ok) v = to_f32(plane[(uint32_t)(gy * nx + gx)]);
+            halo_coord<R, RY, NW>(h, ly, lx);
+            const float v = masked<BC>(halo[j], m, RY + j);
+            tile[ly * G::W + lx] = SCALED ? v * scale_halo[j] : v;
         }
-        halo[j] = v;
     }
 }
 
-// Writes a loaded plane into an LDS tile of H x W floats, scaling the values
-// by `scale_in[i]` / `scale_halo[j]` when SCALED (used for kappa (.) lambda).
-template <int R, int RY, bool SCALED>
-__device__ __forceinline__ void store_plane(float* __restrict__ tile, const float (&in)[RY],
-                                            const float (&halo)[PlaneGeom<R, RY>::HT],
-                                            const float (&scale_in)[RY],
-                                            const float (&scale_halo)[PlaneGeom<R, RY>::HT]) {
-    using G = PlaneGeom<R, RY>;
-    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < RY; ++i)
-        tile[(R + ty * RY + i) * G::W + R + tx] = SCALED ? in[i] * scale_in[i] : in[i];
-#pragma unroll
-    for (int j = 0; j < G::HT; ++j) {
-        const int h = threadIdx.x + j * kThreads;
-        if (h < G::NH) {
-            int ly, lx;
-            halo_coord<R, RY>(h, ly, lx);
-            tile[ly * G::W + lx] = SCALED ? halo[j] * scale_halo[j] : halo[j];
-        }
-    }
+// Unscaled form of store_plane.
+template <int R, int RY, int BC, typename T, int NW = 4>
+__device__ __forceinline__ void store_plane(float* __restrict__ tile, const T (&in)[RY],
+                                            const T (&halo)[PlaneGeom<R, RY, NW>::HT], uint32_t m) {
+    const float one[RY] = {};
+    const float oneh[PlaneGeom<R, RY, NW>::HT] = {};
+    store_plane<R, RY, BC, false, T, NW>(tile, in, halo, m, one, oneh);
 }
 
 // In-plane arms of a star in difference form, sum over the x and y arms of
@@ -116,10 +174,10 @@ __device__ __forceinline__ void store_plane(float* __restrict__ tile, const floa
 // arithmetic, while each difference of nearby values is formed with little
 // rounding: a high-order Laplacian otherwise cancels terms of size ~8|u| to a
 // result much smaller than u.
-template <int R, int RY, bool ISO>
+template <int R, int RY, bool ISO, int NW = 4>
 __device__ __forceinline__ void star_plane_diff(const float* __restrict__ tile, const Taps& tp,
                                                 float (&p)[RY], float (&u0)[RY]) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const float* base = tile + (ty * RY) * G::W + R + tx;
     float col[RY + 2 * R];
@@ -150,10 +208,10 @@ __device__ __forceinline__ void star_plane_diff(const float* __restrict__ tile, 
 // In-plane contribution of an isotropic star (one weight per distance, equal
 // on every arm): c0 u + sum_d w_d (u(x-d) + u(x+d) + u(y-d) + u(y+d)).
 // Taps: c[0] = centre, c[star_x<R>(d)] = w_d.
-template <int R, int RY>
+template <int R, int RY, int NW = 4>
 __device__ __forceinline__ void star_plane_iso(const float* __restrict__ tile, const Taps& tp,
                                                float (&p)[RY]) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const float* base = tile + (ty * RY) * G::W + R + tx;
     float col[RY + 2 * R];
@@ -171,10 +229,10 @@ __device__ __forceinline__ void star_plane_iso(const float* __restrict__ tile, c
 }
 
 // In-plane star contribution (centre, x and y arms) for this thread's RY rows.
-template <int R, int RY>
+template <int R, int RY, int NW = 4>
 __device__ __forceinline__ void star_plane(const float* __restrict__ tile, const Taps& tp,
                                            float (&p)[RY]) {
-    using G = PlaneGeom<R, RY>;
+    using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const float* base = tile + (ty * RY) * G::W + R + tx;   // row ty*RY - R + R, column tx
     float col[RY + 2 * R];
