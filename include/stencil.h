@@ -71,7 +71,8 @@ typedef enum {
     ST_VARIANT_TB2D = 1,  /* 2D LDS tile, k fused time steps per launch */
     ST_VARIANT_ZM3D = 2,  /* 3D plane-streaming (z-march) with register queues */
     ST_VARIANT_WAVE3D = 3, /* 3D leapfrog z-march, fused source/receiver */
-    ST_VARIANT_WAVE3D_LDS = 4 /* 3D leapfrog forward with z-neighbours in an LDS ring */
+    ST_VARIANT_WAVE3D_LDS = 4, /* 3D leapfrog forward with z-neighbours in an LDS ring */
+    ST_VARIANT_YM2D = 5   /* 2D row march, k fused time steps held in LDS row rings */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */
@@ -92,9 +93,11 @@ typedef struct {
 /* Per-plan overrides.  Zero fields mean "dispatch map decides". */
 typedef struct {
     int32_t variant;       /* st_variant */
-    int32_t tile_x;        /* TB2D: output tile width (multiple of 64) */
-    int32_t tile_y;        /* TB2D: output tile height; ZM3D/WAVE3D: rows per workgroup */
-    int32_t tsteps;        /* TB2D: time steps fused per launch (1..16);
+    int32_t tile_x;        /* TB2D: output tile width (multiple of 64);
+                              YM2D: window width = threads per workgroup (256 or 512) */
+    int32_t tile_y;        /* TB2D: output tile height; YM2D: rows per chunk (0 = automatic);
+                              ZM3D/WAVE3D: rows per workgroup */
+    int32_t tsteps;        /* TB2D/YM2D: time steps fused per launch (1..16);
                               WAVE3D: 1, or 2 = two fused leapfrog steps (radius 2 or 4) */
     int32_t zchunk;        /* ZM3D/WAVE3D: planes per workgroup (0 = whole depth) */
     int32_t ckpt_every;    /* wave gradient checkpoint interval (0 = 20) */

@@ -102,6 +102,14 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                 LaunchCfg c{ST_VARIANT_TB2D, tx, ty, k, 0};
                 if (cfg_legal(p, c)) out.push_back(c);
             }
+    // Row march: window width, fused depth, rows per chunk (0 = automatic).
+    for (int nt : {256, 512})
+        for (int k : {1, 2, 4, 8})
+            for (int ych : {0, 32, 64, 128}) {
+                if (nt > 2 * p.n[0] + 256 || (ych != 0 && ych >= p.n[1])) continue;
+                LaunchCfg c{ST_VARIANT_YM2D, nt, ych, k, 0};
+                if (cfg_legal(p, c)) out.push_back(c);
+            }
     return out;
 }
 
@@ -138,7 +146,7 @@ hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, c
     for (int j = 1; j <= L; ++j) {
         const int kj = std::min(k, steps - done);
         void* dst = ((L - j) % 2 == 0) ? out : tmp;
-        hipError_t e = p.ndim == 2 ? launch_tb2d(g, c, taps, cur, dst, kj, s)
+        hipError_t e = p.ndim == 2 ? launch_linear2d(g, c, taps, cur, dst, kj, s)
                                    : launch_zm3d(g, c, taps, cur, dst, s);
         if (e != hipSuccess) return e;
         cur = dst;

@@ -61,7 +61,7 @@ CaseKey classify(const st_problem& p) {
     k.boundary = p.boundary;
     k.update = p.update;
     const double cells = (double)p.n[0] * (double)p.n[1] * (double)p.n[2];
-    k.size_class = cells <= (double)(1 << 20) ? 0 : (cells <= (double)(1 << 24) ? 1 : 2);
+    k.size_class = cells <= (double)(1 << 20) ? 0 : cells <= (double)(1 << 22) ? 1 : cells <= (double)(1 << 25) ? 2 : 3;
     int64_t lo = p.n[0], hi = p.n[0];
     for (int a = 1; a < p.ndim; ++a) {
         lo = p.n[a] < lo ? p.n[a] : lo;
@@ -94,13 +94,39 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.zchunk = kAutoChunk;
         return c;
     }
-    c.variant = ST_VARIANT_TB2D;
-    c.tile_x = 64;
-    c.tile_y = 32;
-    // Deeper fusion for small grids (launch-bound), shallower for wide stencils.
-    if (k.size_class == 0) c.tsteps = k.r == 1 ? 8 : (k.r == 2 ? 4 : 2);
-    else c.tsteps = k.r <= 2 ? 4 : 2;
-    if (k.shape == kBox && k.r == 2 && k.size_class > 0) c.tsteps = 2;
+    if (k.size_class == 0) {
+        // Small grids: square LDS tiles give enough workgroups; deeper
+        // fusion for narrow stencils (these launches are short).
+        c.variant = ST_VARIANT_TB2D;
+        c.tile_x = 64;
+        c.tile_y = 32;
+        c.tsteps = k.r == 1 ? 8 : (k.r == 2 ? 4 : 2);
+        return c;
+    }
+    // Larger grids: the row march (redundant halo work in x only).
+    c.variant = ST_VARIANT_YM2D;
+    c.tile_x = 256;
+    c.tile_y = 0;
+    c.tsteps = k.r <= 2 ? 4 : 2;
+    return c;
+}
+
+// Starting configuration when a plan option forces a kernel family other
+// than the map's: that family's own defaults (the other option fields then
+// override them).
+LaunchCfg variant_default(const st_problem& p, int variant) {
+    const CaseKey k = classify(p);
+    LaunchCfg c = default_cfg(k);
+    if (variant == c.variant) return c;
+    c = LaunchCfg{variant, 0, 0, 1, 0};
+    switch (variant) {
+        case ST_VARIANT_TB2D: c.tile_x = 64; c.tile_y = 32; c.tsteps = default_cfg(k).tsteps; break;
+        case ST_VARIANT_YM2D: c.tile_x = 256; c.tile_y = 0; c.tsteps = default_cfg(k).tsteps; break;
+        case ST_VARIANT_ZM3D: c.tile_y = 16; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_WAVE3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_WAVE3D_LDS: c.tile_y = 32; c.zchunk = kAutoChunk; break;
+        default: break;
+    }
     return c;
 }
 
@@ -223,6 +249,12 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
     if (p.ndim == 3) {
         return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0;
+    }
+    if (c.variant == ST_VARIANT_YM2D) {
+        if (c.tile_x != 256 && c.tile_x != 512) return false;
+        if (c.tile_y < 0 || c.tsteps < 1 || c.tsteps > 16) return false;
+        if (c.tile_x - 2 * c.tsteps * p.radius < kWave) return false;
+        return ym2d_lds_bytes(c.tile_x, c.tsteps, p.radius) <= ym2d_max_lds_bytes();
     }
     if (c.variant != ST_VARIANT_TB2D) return false;
     if (c.tile_x < kWave || c.tile_x % kWave || c.tile_x > 512) return false;

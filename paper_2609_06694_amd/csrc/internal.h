@@ -62,6 +62,8 @@ struct WaveTB2 {
 // Launchers (return the launch status; asynchronous on `stream`).
 hipError_t launch_tb2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, int k, hipStream_t stream);
+hipError_t launch_ym2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                       void* out, int k, hipStream_t stream);
 hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, hipStream_t stream);
 hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
@@ -87,6 +89,19 @@ bool wave3d_supported(int r);
 int zm3d_rows(const LaunchCfg& cfg);    // rows per workgroup actually used
 int tb2d_max_lds_bytes();
 int tb2d_lds_floats_host(int BX, int BY, int k, int R);
+bool ym2d_supported(int r, int shape);
+int ym2d_rows(int nt, int k, int R);            // input rows per march iteration
+int ym2d_lds_bytes(int nt, int k, int R);
+int ym2d_max_lds_bytes();
+int ym2d_auto_chunk(int nx, int ny, int nt, int k, int R);
+
+// One launch of a 2D linear sweep (k fused steps) through the kernel family
+// the configuration names.
+inline hipError_t launch_linear2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                                  const void* in, void* out, int k, hipStream_t stream) {
+    if (cfg.variant == 5) return launch_ym2d(g, cfg, taps, in, out, k, stream);
+    return launch_tb2d(g, cfg, taps, in, out, k, stream);
+}
 
 
 }  // namespace stk

@@ -33,7 +33,7 @@ namespace stk {
 // shape and precision; a cell names the kernel structure that won there).
 struct CaseKey {
     int ndim, shape, r, dtype, boundary, update;
-    int size_class;   // 0: <= 2^20 cells, 1: <= 2^24, 2: larger
+    int size_class;   // 0: <= 2^20 cells, 1: <= 2^22, 2: <= 2^25, 3: larger
     int slab;         // 1 if the longest side is >= 4x the shortest
 };
 
@@ -44,6 +44,7 @@ std::string key_string(const CaseKey& k);
 // in-process table written by the autotuner override it.
 LaunchCfg dispatch_lookup(const CaseKey& k);
 LaunchCfg default_dispatch(const CaseKey& k);
+LaunchCfg variant_default(const st_problem& p, int variant);
 void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
 bool cfg_legal(const st_problem& p, const LaunchCfg& c);
 constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk from the grid

@@ -188,7 +188,10 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
         }
         if (opts->ckpt_every > 0) pl->ckpt_every = opts->ckpt_every;
         LaunchCfg c = pl->cfg;
-        if (opts->variant != ST_VARIANT_AUTO) c.variant = opts->variant;
+        if (opts->variant != ST_VARIANT_AUTO && opts->variant != c.variant) {
+            c = variant_default(*p, opts->variant);
+            if (c.zchunk == kAutoChunk) c.zchunk = auto_zchunk(*p, c);
+        }
         if (opts->tile_x > 0) c.tile_x = opts->tile_x;
         if (opts->tile_y > 0) c.tile_y = opts->tile_y;
         if (opts->tsteps > 0) c.tsteps = opts->tsteps;
@@ -221,7 +224,7 @@ hipError_t wave_forward_launch(const st_plan* pl, const WaveLaunch& w, hipStream
 hipError_t linear_launch(const st_plan* pl, const Taps& taps, const void* in, void* out, int k,
                          hipStream_t s) {
     const Geom g = geom_of(pl->prob);
-    if (pl->prob.ndim == 2) return launch_tb2d(g, pl->cfg, taps, in, out, k, s);
+    if (pl->prob.ndim == 2) return launch_linear2d(g, pl->cfg, taps, in, out, k, s);
     return launch_zm3d(g, pl->cfg, taps, in, out, s);
 }
 

@@ -32,7 +32,7 @@ def main(out: str) -> None:
     seen = set()
     for g in wl.batch2d():
         cells = g.n[0] * g.n[1]
-        size_class = 0 if cells <= 1 << 20 else (1 if cells <= 1 << 24 else 2)
+        size_class = 0 if cells <= 1 << 20 else (1 if cells <= 1 << 22 else (2 if cells <= 1 << 25 else 3))
         slab = max(g.n[:2]) >= 4 * min(g.n[:2])
         key = (g.shape, g.radius, size_class, slab)
         if key in seen:
@@ -43,6 +43,11 @@ def main(out: str) -> None:
         stats = p.autotune()
         print(f"{name}: {p.describe()} {stats}", flush=True)
         torch.cuda.empty_cache()
+    # Two tuned workloads that share a case key overwrite each other's entry.
+    keys = [tuple(line.split()[:8]) for line in open(out) if line.strip() and not line.startswith("#")]
+    dup = sorted({k for k in keys if keys.count(k) > 1})
+    if dup:
+        print(f"warning: case keys tuned more than once (the last entry wins): {dup}", flush=True)
 
 
 if __name__ == "__main__":

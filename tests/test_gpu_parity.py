@@ -65,6 +65,29 @@ def test_2d_sweep_vs_oracle(st, shape, r, dtype, bc):
         assert e <= TOL[dtype], (nx, ny, tx, ty, k, steps, e)
 
 
+@pytest.mark.parametrize("shape,r", CASES_2D)
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_2d_rowmarch_vs_oracle(st, shape, r, dtype, bc):
+    """Row-march kernel: window widths 256/512, fused depths 1..8, automatic
+    and explicit chunks (several chunks and strips, ragged tails, grids
+    smaller than one window and than the radius)."""
+    rng = np.random.default_rng(700 + 100 * r + shape)
+    npdt = np.float32 if dtype == "f32" else np.float16
+    c = wl.random_unit_sum_coeffs(rng, 2, shape, r)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    for (nx, ny), (nt, k, ych), steps in [((197, 131), (256, 1, 0), 3), ((197, 131), (256, 4, 0), 9),
+                                          ((600, 45), (512, 2, 20), 5), ((70, 300), (256, 8, 37), 8),
+                                          ((5, 7), (256, 2, 0), 5), ((3, 300), (512, 3, 64), 7)]:
+        u = wl.small_random_grid(rng, 2, (nx, ny), npdt, 0.0, 1.0)
+        s = st.Stencil((nx, ny), shape, r, c, dtype=dtype, boundary=bc, variant=5, tile_x=nt, tile_y=ych,
+                       tsteps=k)
+        got = _host(s.apply(_dev(u), steps)).astype(np.float64)
+        ref = oracle.sweep(u, c, shape, r, bcode, steps)
+        e = rel_l2(got, ref)
+        assert e <= TOL[dtype], (nx, ny, nt, k, ych, steps, e)
+
+
 CASES_3D = [(wl.STAR, r) for r in (1, 2, 3, 4)] + [(wl.BOX, 1)]
 
 
