@@ -211,9 +211,13 @@ def bench_batch(dev, st, wl, torch):
 
     ms = timed(run, 3, 1, torch.cuda.synchronize)
     g = gcells(cells, 32, ms)
-    return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms_separate_launches": ms,
-            "gcells_s_separate": g, "eff_gbs": g * 8, "hbm_frac": g * 8 / HBM_PEAK_GBS,
-            "persistent_batched": "disabled (launch did not complete on the GPU; see DESIGN.md)"}
+    bs = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
+                            for c in cases])
+    bms = timed(lambda: bs.apply(ins, 32, outs=outs), 5, 2, torch.cuda.synchronize)
+    bg = gcells(cells, 32, bms)
+    return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms": bms, "gcells_s": bg,
+            "launches": "one per time block for all 64 grids", "eff_gbs": bg * 8,
+            "ms_separate_launches": ms, "gcells_s_separate": g}
 
 
 def bench_grad(dev, st, wl, torch):

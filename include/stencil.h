@@ -175,21 +175,18 @@ st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wa
 st_status stencil_plan_batched(const st_problem *problems, int32_t count,
                                const st_plan_opts *opts, st_plan **out);
 
-/* All members advanced `steps` steps in ONE persistent launch: a device work
- * queue of (member, tile, time block) items, each waiting only on the
- * previous time block of its own member.  u_in / u_out are HOST arrays of
+/* All members advanced `steps` steps, one launch per time block for the
+ * whole batch: each launch runs one block (the member's own fused depth k)
+ * of every member that still has blocks left, so the number of launches is
+ * ceil(steps / k) of the shallowest member instead of a sum over members.
+ * Workgroups never wait on each other.  u_in / u_out are HOST arrays of
  * `count` device pointers (u_in[i] == u_out[i] allowed).  Workspace from
- * stencil_workspace_bytes(batched_plan, steps, 0). */
+ * stencil_workspace_bytes(batched_plan, steps, 0): a partner grid per
+ * member plus the member table.  Asynchronous on `stream`; ST_EHIP if a
+ * launch fails. */
 st_status stencil_apply_batched(const st_plan *plan, const void *const *u_in,
                                 void *const *u_out, int32_t steps, void *workspace,
                                 size_t ws_bytes, void *stream);
-
-/* Outcome of the last stencil_apply_batched on this plan, valid once its
- * stream has synchronised: ST_OK, or ST_EHIP if a dependency wait exceeded
- * its bound (STENCIL_BATCH_WAIT_MS, default 2000 ms) and the launch stopped
- * early with incomplete outputs.  *items_done (nullable) receives the number
- * of queue items pulled. */
-st_status stencil_batched_status(const st_plan *plan, int32_t *items_done);
 
 /* Autotune: for every distinct case of the plan (one, or each batch
  * member), time the legal candidates (tile shape, fused time steps, rows per

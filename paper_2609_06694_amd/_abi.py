@@ -28,7 +28,7 @@ VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",
             "stencil_plan_describe", "stencil_apply", "stencil_apply_adjoint",
             "stencil_wave_gradient", "stencil_plan_batched", "stencil_apply_batched",
-            "stencil_batched_status", "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version"]
+            "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version"]
 
 
 class StProblem(ctypes.Structure):
@@ -88,8 +88,6 @@ def lib():
     L.stencil_plan_batched.restype = ctypes.c_int
     L.stencil_apply_batched.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), i32, P, sz, P]
     L.stencil_apply_batched.restype = ctypes.c_int
-    L.stencil_batched_status.argtypes = [P, ip]
-    L.stencil_batched_status.restype = ctypes.c_int
     L.stencil_autotune.argtypes = [P, P, sz, P]
     L.stencil_autotune.restype = ctypes.c_int
     L.stencil_autotune_stats.argtypes = [P, ip, ip]

@@ -1,15 +1,19 @@
-// Persistent batched launch over many independent 2D grids.
+// Batched launch over many independent 2D grids.
 //
-// One kernel launch advances every member grid by `steps` time steps.  The
-// work is a device queue of items (member, time block, tile), ordered so that
-// every item of a member's time block p-1 precedes every item of its block
-// p.  Resident workgroups pull items in order with one atomic counter; an item
-// waits (bounded spin) until all tiles of its member's previous block are
-// published, then runs that member's own specialised tile routine (its
-// shape, radius, tile and fused depth come from the dispatch map).  Because
-// an item only waits on items earlier in the queue, and an item is pulled only
-// by a running workgroup, the oldest unfinished item can always proceed: no
-// co-residency is required and there is no grid-wide barrier.
+// All members advance one time block (k_g fused steps of member g) per
+// launch: a launch covers every member's row-march workgroups, so one kernel
+// fills the device with the work of many small grids instead of one launch
+// per grid and block.  The blocks of a member are ordered by the launches
+// themselves (one stream), so no workgroup ever waits on another.  A member
+// with fewer blocks than the longest one has its workgroups exit at once in
+// the remaining launches.  Each workgroup finds its member by a binary search
+// over the members' first workgroup indices in a device table (member
+// geometry, buffers and coefficients), written from pinned host staging.
+//
+// Members keep their own stencil (shape, radius, coefficients), extent and
+// fused depth; they share storage type and boundary rule.  Blocks ping-pong
+// between the caller's output and a workspace partner so that the last
+// block of every member lands in its output.
 #include <stdlib.h>
 #include <string.h>
 
@@ -18,138 +22,86 @@
 #include <vector>
 
 #include "plan.h"
-#include "tb2d_tile.h"
+#include "ym2d_run.h"
 
 namespace stk {
 
-struct BMember {
-    const void* in;      // initial input (u_in, or the workspace copy)
-    void* out;           // caller output
-    void* ws;            // ping-pong partner
-    int nx, ny, BX, BY, k, L, steps, tiles_x, ntiles, shape, r;
-    int done_base;       // index of this member's first block counter
+constexpr int kGroupThreads = 256;
+
+struct GMember {
+    const void* in;   // source of block 1 (u_in, or its workspace copy)
+    void* out;        // caller output: receives the last block
+    void* ws;         // ping-pong partner
+    int nx, ny;
+    int k;            // fused steps per block (window geometry)
+    int L;            // blocks: ceil(steps / k)
+    int ow, ych, strips;
+    int first;        // first workgroup of this member in every launch
+    int shape, r;
     Taps taps;
 };
 
-// One time block of one member: `tiles` consecutive queue items starting at
-// `first`.  The queue index of an item is found by binary search over these.
-struct BLevel {
-    int member, block, tiles, first;
-};
-
-
-template <int R, int SHAPE, typename T>
-__device__ void run_item(const BMember& m, int block, int tile, int bc, float* lds) {
-    // Block j (1-based) writes out if (L - j) is even, else ws; block 1 reads in.
-    const int j = block + 1;
-    void* dst = ((m.L - j) % 2 == 0) ? m.out : m.ws;
-    const void* src = j == 1 ? m.in : (((m.L - (j - 1)) % 2 == 0) ? m.out : m.ws);
-    const int kj = min(m.k, m.steps - block * m.k);
-    const int tyi = tile / m.tiles_x, txi = tile - tyi * m.tiles_x;
-    if (bc == kPeriodic)
-        tb2d_tile<R, SHAPE, T, kPeriodic>((const T*)src, (T*)dst, m.nx, m.ny, txi * m.BX, tyi * m.BY,
-                                          m.BX, m.BY, kj, m.taps, lds);
-    else
-        tb2d_tile<R, SHAPE, T, kZero>((const T*)src, (T*)dst, m.nx, m.ny, txi * m.BX, tyi * m.BY,
-                                      m.BX, m.BY, kj, m.taps, lds);
+template <typename T, int BC, int RY, int R, int SHAPE>
+__device__ void grouped_member(const GMember& m, int round, int steps, int local, float* lds) {
+    const int kl = min(m.k, steps - round * m.k);
+    // Block j = round + 1 writes out if (L - j) is even, else the partner.
+    const int j = round + 1;
+    T* dst = (T*)(((m.L - j) % 2 == 0) ? m.out : m.ws);
+    const T* src = (const T*)(j == 1 ? m.in : (((m.L - j + 1) % 2 == 0) ? m.out : m.ws));
+    ym2d_run<R, SHAPE, T, BC, kGroupThreads, RY, 2>(src, dst, m.nx, m.ny, m.k, kl, m.ow, m.ych,
+                                                    m.strips, local, m.taps, lds);
 }
 
-template <typename T>
-__device__ void dispatch_item(const BMember& m, int block, int tile, int bc, float* lds) {
+template <typename T, int BC, int RY>
+__global__ __launch_bounds__(kGroupThreads) void grouped_kernel(const GMember* __restrict__ ms, int nm,
+                                                                int round, int steps) {
+    extern __shared__ float lds[];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nm - 1;   // last member whose first workgroup is <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ms[mid].first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GMember& m = ms[lo];
+    if (round >= m.L) return;   // uniform: this member has finished
+    const int local = b - m.first;
     if (m.shape == kStar) {
         switch (m.r) {
-            case 1: run_item<1, kStar, T>(m, block, tile, bc, lds); break;
-            case 2: run_item<2, kStar, T>(m, block, tile, bc, lds); break;
-            case 3: run_item<3, kStar, T>(m, block, tile, bc, lds); break;
-            case 4: run_item<4, kStar, T>(m, block, tile, bc, lds); break;
+            case 1: grouped_member<T, BC, RY, 1, kStar>(m, round, steps, local, lds); break;
+            case 2: grouped_member<T, BC, RY, 2, kStar>(m, round, steps, local, lds); break;
+            case 3: grouped_member<T, BC, RY, 3, kStar>(m, round, steps, local, lds); break;
+            case 4: grouped_member<T, BC, RY, 4, kStar>(m, round, steps, local, lds); break;
         }
     } else {
         switch (m.r) {
-            case 1: run_item<1, kBox, T>(m, block, tile, bc, lds); break;
-            case 2: run_item<2, kBox, T>(m, block, tile, bc, lds); break;
+            case 1: grouped_member<T, BC, RY, 1, kBox>(m, round, steps, local, lds); break;
+            case 2: grouped_member<T, BC, RY, 2, kBox>(m, round, steps, local, lds); break;
         }
     }
 }
 
-// ctl[0] = next item, ctl[1] = abort flag (set when a wait exceeds its bound).
-__device__ __forceinline__ int find_level(const BLevel* __restrict__ lv, int nlev, int item) {
-    int lo = 0, hi = nlev - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (lv[mid].first <= item) lo = mid;
-        else hi = mid - 1;
+template <typename T, int BC, int RY>
+static hipError_t launch_round(const GMember* d_members, int nm, int round, int steps, int grid,
+                               size_t lds, hipStream_t s) {
+    auto kern = grouped_kernel<T, BC, RY>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
     }
-    return lo;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), lds, s, d_members, nm, round, steps);
+    return hipGetLastError();
 }
 
-// A dependency wait polls with relaxed (non-invalidating) loads and ends
-// after `wait_ticks` of the constant-rate wall clock; the acquire side is one
-// fence after the wait.  On timeout ctl[1] is set, every workgroup stops
-// pulling items, and the host reads the flag through stencil_batched_status.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void batched_kernel(const BMember* __restrict__ members,
-                                                           const BLevel* __restrict__ levels,
-                                                           int nlev, int nitems, int bc, int* ctl,
-                                                           int* done, unsigned long long wait_ticks) {
-    extern __shared__ float lds[];
-    __shared__ int s_item;
-    __shared__ int s_abort;
-    __shared__ int s_member, s_block, s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int it = -1;
-            if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                it = atomicAdd(&ctl[0], 1);
-            s_item = it < nitems ? it : -1;
-            s_abort = 0;
-            if (s_item >= 0) {
-                const BLevel lv = levels[find_level(levels, nlev, s_item)];
-                s_member = lv.member;
-                s_block = lv.block;
-                s_tile = s_item - lv.first;
-                if (lv.block > 0) {
-                    const BMember& m = members[lv.member];
-                    const int* cnt = &done[m.done_base + lv.block - 1];
-                    const int need = m.ntiles;
-                    const unsigned long long t0 = wall_clock64();
-                    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        __builtin_amdgcn_s_sleep(8);
-                        if (wall_clock64() - t0 > wait_ticks ||
-                            __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            s_abort = 1;
-                            break;
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
-            }
-        }
-        __syncthreads();
-        const int it = s_item;
-        if (it < 0 || s_abort) return;
-        __threadfence();   // acquire side for every wave before reading the grid
-        const int member = s_member, block = s_block, tile = s_tile;
-        const BMember& m = members[member];
-        dispatch_item<T>(m, block, tile, bc, lds);
-        __threadfence();   // publish this wave's stores before the count below
-        __syncthreads();   // also keeps s_* intact until every wave has read them
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&done[m.done_base + block], 1, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-__global__ void zero_ints(int* p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
-// Copies the abort flag and the item counter to host-visible memory.
-__global__ void publish_status(const int* ctl, int* host_status) {
-    if (threadIdx.x == 0) {
-        host_status[0] = ctl[1];
-        host_status[1] = ctl[0];
-    }
+static hipError_t launch_round_t(int bc, int ry, const GMember* d, int nm, int round, int steps,
+                                 int grid, size_t lds, hipStream_t s) {
+    if (bc == kPeriodic)
+        return ry == 8 ? launch_round<T, kPeriodic, 8>(d, nm, round, steps, grid, lds, s)
+                       : launch_round<T, kPeriodic, 4>(d, nm, round, steps, grid, lds, s);
+    return ry == 8 ? launch_round<T, kZero, 8>(d, nm, round, steps, grid, lds, s)
+                   : launch_round<T, kZero, 4>(d, nm, round, steps, grid, lds, s);
 }
 
 }  // namespace stk
@@ -164,57 +116,70 @@ size_t member_grid_bytes(const st_plan* m) {
     return (size_t)m->prob.n[0] * m->prob.n[1] * (m->prob.dtype == ST_F16 ? 2 : 4);
 }
 
-struct BatchSched {
-    std::vector<BLevel> levels;
-    std::vector<int> L, done_base;
-    int ncount = 0;
-    int nitems = 0;
+// Fused depth of member m in a grouped launch: its own depth, within the
+// limits of a 256-column window (at least 64 output columns) and of LDS.
+int member_depth(const st_plan* m) {
+    const int r = m->prob.radius;
+    int k = std::min(8, std::max(1, m->cfg.tsteps));
+    while (k > 1 && (kGroupThreads - 2 * k * r < kWave ||
+                     (int)sizeof(float) * k * (4 + 2 * r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
+        --k;
+    return k;
+}
+
+struct Layout {
+    std::vector<GMember> members;   // pointers filled at apply time
+    int rounds = 0, grid = 0, ry = 8;
+    size_t lds = 0;
 };
 
-// Queue order: earliest simulated time first (a block of a member with k
-// fused steps starting at step b*k), larger members first at equal time.
-BatchSched schedule(const st_plan* plan, int steps) {
-    BatchSched s;
+// Geometry of one grouped launch: chunks sized so that every member gets
+// workgroups in proportion to its cells, about four per CU in total.
+Layout layout(const st_plan* plan, int steps, int cus) {
+    Layout lay;
     const int nm = (int)plan->members.size();
-    s.L.resize(nm);
-    s.done_base.resize(nm);
-    struct Key {
-        int t0, member, block, tiles;
-    };
-    std::vector<Key> keys;
-    int base = 0;
+    double total = 0;
+    for (const st_plan* m : plan->members) total += (double)m->prob.n[0] * m->prob.n[1];
+    const double target = 4.0 * cus;
+    int need8 = 0;
     for (int g = 0; g < nm; ++g) {
         const st_plan* m = plan->members[g];
-        const int k = std::max(1, m->cfg.tsteps);
-        s.L[g] = steps > 0 ? (steps + k - 1) / k : 0;
-        s.done_base[g] = base;
-        base += s.L[g];
-        const int tx = (int)((m->prob.n[0] + m->cfg.tile_x - 1) / m->cfg.tile_x);
-        const int ty = (int)((m->prob.n[1] + m->cfg.tile_y - 1) / m->cfg.tile_y);
-        for (int b = 0; b < s.L[g]; ++b) keys.push_back({b * k, g, b, tx * ty});
+        GMember b;
+        memset(&b, 0, sizeof b);
+        b.nx = (int)m->prob.n[0];
+        b.ny = (int)m->prob.n[1];
+        b.r = m->prob.radius;
+        b.shape = m->prob.shape;
+        b.k = member_depth(m);
+        b.L = steps > 0 ? (steps + b.k - 1) / b.k : 0;
+        b.ow = kGroupThreads - 2 * b.k * b.r;
+        b.strips = (b.nx + b.ow - 1) / b.ow;
+        const double share = target * ((double)b.nx * b.ny / std::max(1.0, total));
+        const int chunks = std::max(1, (int)(share / b.strips + 0.5));
+        int ych = (b.ny + chunks - 1) / chunks;
+        ych = std::max(ych, std::max(16, 4 * b.k * b.r));
+        b.ych = std::min(ych, b.ny);
+        b.first = lay.grid;
+        lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
+        b.taps = m->taps;
+        lay.rounds = std::max(lay.rounds, b.L);
+        if ((int)sizeof(float) * b.k * (8 + 2 * b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
+        lay.members.push_back(b);
     }
-    s.ncount = base;
-    std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
-        if (a.t0 != b.t0) return a.t0 < b.t0;
-        return a.tiles > b.tiles;
-    });
-    int first = 0;
-    for (const Key& k : keys) {
-        s.levels.push_back({k.member, k.block, k.tiles, first});
-        first += k.tiles;
-    }
-    s.nitems = first;
-    return s;
+    // Eight input rows per iteration unless a member's rings would outgrow
+    // 64 KiB; the launch reserves the largest member's rings.
+    lay.ry = need8 ? 4 : 8;
+    for (const GMember& b : lay.members)
+        lay.lds = std::max(lay.lds, sizeof(float) * (size_t)b.k * (lay.ry + 2 * b.r) * (kGroupThreads + 2 * b.r));
+    return lay;
 }
 
 }  // namespace
 
 namespace stk {
 
-size_t batched_meta_bytes(const st_plan* plan, int steps) {
-    BatchSched s = schedule(plan, std::max(0, steps));
-    return align256(sizeof(BMember) * plan->members.size()) + align256(sizeof(BLevel) * s.levels.size()) +
-           align256(sizeof(int) * (size_t)(s.ncount + 2));
+size_t batched_meta_bytes(const st_plan* plan, int /*steps*/) {
+    return align256(sizeof(GMember) * plan->members.size());
 }
 
 }  // namespace stk
@@ -286,115 +251,56 @@ st_status stencil_apply_batched(const st_plan* plan, const void* const* u_in, vo
     }
     const size_t need = stencil_workspace_bytes(plan, steps, 0);
     if (!workspace || ws_bytes < need) B_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", need);
-    // The persistent launch did not complete on the GPU (the device sync after
-    // it never returned) and its cause is not yet shown; the launch stays
-    // disabled until it is.  Members can still be advanced one by one with
-    // stencil_apply.
-    B_FAIL(ST_EUNSUPPORTED, "the persistent batched launch is disabled (it did not complete on the GPU)");
 
-    BatchSched sc = schedule(plan, steps);
+    int dev = 0, cus = 0;
+    B_HIP(hipGetDevice(&dev));
+    B_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    Layout lay = layout(plan, steps, std::max(1, cus));
+    if (lay.lds > (size_t)ym2d_max_lds_bytes()) B_FAIL(ST_EUNSUPPORTED, "member rings exceed LDS");
+
     char* ws = (char*)workspace;
     size_t off = 0;
-    std::vector<BMember> hm(nm);
-    int max_lds = 0;
     for (int g = 0; g < nm; ++g) {
         const st_plan* m = plan->members[g];
+        GMember& b = lay.members[g];
         void* partner = ws + off;
         off += align256(member_grid_bytes(m));
-        BMember& b = hm[g];
-        memset(&b, 0, sizeof b);
+        b.in = u_in[g];
         b.out = u_out[g];
         b.ws = partner;
-        b.in = u_in[g];
-        b.nx = (int)m->prob.n[0];
-        b.ny = (int)m->prob.n[1];
-        b.BX = m->cfg.tile_x;
-        b.BY = m->cfg.tile_y;
-        b.k = std::max(1, m->cfg.tsteps);
-        b.L = sc.L[g];
-        b.steps = steps;
-        b.tiles_x = (b.nx + b.BX - 1) / b.BX;
-        b.ntiles = b.tiles_x * ((b.ny + b.BY - 1) / b.BY);
-        b.shape = m->prob.shape;
-        b.r = m->prob.radius;
-        b.done_base = sc.done_base[g];
-        b.taps = m->taps;
+        // In place with an odd block count: block 1 would write the grid it
+        // reads, so it reads a copy in the partner instead (block 2 writes
+        // the partner only after block 1's launch has completed).
         if (u_in[g] == u_out[g] && (b.L % 2) == 1) {
             B_HIP(hipMemcpyAsync(partner, u_in[g], member_grid_bytes(m), hipMemcpyDeviceToDevice, s));
-            b.in = partner;   // block 1 then writes out, block 2 writes the partner back
+            b.in = partner;
         }
-        max_lds = std::max(max_lds, (int)sizeof(float) * tb2d_lds_floats_host(b.BX, b.BY, b.k, b.r));
     }
-    // The workspace copy of an in-place member is read by block 1 and
-    // overwritten by block 2 only after block 1 has fully completed.
-    BMember* d_members = (BMember*)(ws + off);
-    off += align256(sizeof(BMember) * nm);
-    BLevel* d_levels = (BLevel*)(ws + off);
-    off += align256(sizeof(BLevel) * sc.levels.size());
-    int* d_ctl = (int*)(ws + off);
-    int* d_done = d_ctl + 2;
-    const int nitems = sc.nitems;
-    const int nlev = (int)sc.levels.size();
-    if (nitems == 0) return ST_OK;
+    GMember* d_members = (GMember*)(ws + off);
 
-    // Upload the tables from plan-owned pinned staging; the previous upload
-    // must have left the staging before it is rewritten.
-    const size_t mb = sizeof(BMember) * nm, lb = sizeof(BLevel) * sc.levels.size();
+    // Upload the member table from plan-owned pinned staging; the previous
+    // upload must have left the staging before it is rewritten.
+    const size_t mb = sizeof(GMember) * nm;
     if (!plan->stage_event) B_HIP(hipEventCreateWithFlags(&plan->stage_event, hipEventDisableTiming));
     else B_HIP(hipEventSynchronize(plan->stage_event));
-    if (plan->stage_cap < mb + lb) {
+    if (plan->stage_cap < mb) {
         if (plan->stage) B_HIP(hipHostFree(plan->stage));
         plan->stage = nullptr;
         plan->stage_cap = 0;
-        B_HIP(hipHostMalloc(&plan->stage, mb + lb, hipHostMallocDefault));
-        plan->stage_cap = mb + lb;
+        B_HIP(hipHostMalloc(&plan->stage, mb, hipHostMallocDefault));
+        plan->stage_cap = mb;
     }
-    memcpy(plan->stage, hm.data(), mb);
-    memcpy((char*)plan->stage + mb, sc.levels.data(), lb);
+    memcpy(plan->stage, lay.members.data(), mb);
     B_HIP(hipMemcpyAsync(d_members, plan->stage, mb, hipMemcpyHostToDevice, s));
-    B_HIP(hipMemcpyAsync(d_levels, (char*)plan->stage + mb, lb, hipMemcpyHostToDevice, s));
     B_HIP(hipEventRecord(plan->stage_event, s));
-    hipLaunchKernelGGL(stk::zero_ints, dim3(64), dim3(256), 0, s, d_ctl, sc.ncount + 2);
-    B_HIP(hipGetLastError());
 
-    int dev = 0, cus = 0, per_cu = 0, clock_khz = 0;
-    B_HIP(hipGetDevice(&dev));
-    B_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    B_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
-    double wait_ms = 2000.0;
-    if (const char* e = getenv("STENCIL_BATCH_WAIT_MS")) wait_ms = atof(e);
-    const unsigned long long wait_ticks =
-        (unsigned long long)(std::max(0.0, wait_ms) * (double)std::max(clock_khz, 1));
-    if (!plan->status) {
-        B_HIP(hipHostMalloc((void**)&plan->status, 2 * sizeof(int), hipHostMallocDefault));
-        plan->status[0] = plan->status[1] = 0;
-    }
     const int bc = plan->prob.boundary;
-    if (plan->prob.dtype == ST_F16) {
-        B_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stk::batched_kernel<_Float16>,
-                                                           stk::kThreads, max_lds));
-        const int grid = std::max(1, std::min(nitems, std::max(1, per_cu) * cus));
-        hipLaunchKernelGGL(stk::batched_kernel<_Float16>, dim3(grid), dim3(stk::kThreads), max_lds, s,
-                           d_members, d_levels, nlev, nitems, bc, d_ctl, d_done, wait_ticks);
-    } else {
-        B_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stk::batched_kernel<float>,
-                                                           stk::kThreads, max_lds));
-        const int grid = std::max(1, std::min(nitems, std::max(1, per_cu) * cus));
-        hipLaunchKernelGGL(stk::batched_kernel<float>, dim3(grid), dim3(stk::kThreads), max_lds, s,
-                           d_members, d_levels, nlev, nitems, bc, d_ctl, d_done, wait_ticks);
+    for (int round = 0; round < lay.rounds; ++round) {
+        hipError_t e = plan->prob.dtype == ST_F16
+                           ? launch_round_t<_Float16>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
+                           : launch_round_t<float>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s);
+        if (e != hipSuccess) B_FAIL(ST_EHIP, "batched launch %d failed: %s", round, hipGetErrorString(e));
     }
-    B_HIP(hipGetLastError());
-    hipLaunchKernelGGL(stk::publish_status, dim3(1), dim3(64), 0, s, d_ctl, plan->status);
-    B_HIP(hipGetLastError());
-    return ST_OK;
-}
-
-st_status stencil_batched_status(const st_plan* plan, int32_t* items_done) {
-    stk::set_error("%s", "");
-    if (!plan || !plan->batched) B_FAIL(ST_EINVAL, "not a batched plan");
-    if (!plan->status) return ST_OK;
-    if (items_done) *items_done = plan->status[1];
-    if (plan->status[0]) B_FAIL(ST_EHIP, "a batched dependency wait timed out; outputs are incomplete");
     return ST_OK;
 }
 

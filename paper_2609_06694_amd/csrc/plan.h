@@ -18,12 +18,11 @@ struct st_plan {
     bool iso;                       // isotropic star: one weight per distance
     bool batched;
     std::vector<st_plan*> members;  // batched plans own their members
-    // Batched launch: pinned host staging for the device work tables, and
+    // Batched launch: pinned host staging for the device member table, and
     // the event of the last upload (the staging is rewritten only after it).
     mutable void* stage = nullptr;
     mutable size_t stage_cap = 0;
     mutable hipEvent_t stage_event = nullptr;
-    mutable int* status = nullptr;             // pinned: [abort flag, items pulled]
     int tune_tried = 0, tune_rejected = 0;   // last autotune: candidates, parity rejects
 };
 

@@ -444,7 +444,6 @@ void stencil_plan_destroy(st_plan* plan) {
         (void)hipEventDestroy(plan->stage_event);
     }
     if (plan->stage) (void)hipHostFree(plan->stage);
-    if (plan->status) (void)hipHostFree(plan->status);
     delete plan;
 }
 

@@ -261,7 +261,8 @@ def wave_misfit(kappa, model: WaveModel, u0, u_prev, steps, src, wavelet, rec_z,
 
 
 class BatchedStencil(_Plan):
-    """Many independent 2D linear sweeps advanced in one persistent launch."""
+    """Many independent 2D linear sweeps advanced together: one launch per
+    time block for the whole batch."""
 
     def __init__(self, cases: List[dict], **opts):
         super().__init__()
@@ -297,9 +298,3 @@ class BatchedStencil(_Plan):
         check(lib().stencil_apply_batched(self._h, ins, ots, int(steps), ws, nb, _stream_ptr(stream)))
         return outs
 
-    def status(self) -> int:
-        """Items pulled by the last launch; raises if a dependency wait timed
-        out (call after synchronising the stream)."""
-        n = ctypes.c_int32()
-        check(lib().stencil_batched_status(self._h, ctypes.byref(n)))
-        return n.value

@@ -205,23 +205,3 @@ def test_dispatch_cache_file_overrides_default(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=ROOT)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "128", "16", "3"]
-
-
-def test_batched_launch_is_switched_off(L):
-    """The persistent batched launch is disabled: it must refuse with
-    ST_EUNSUPPORTED after its host checks, before touching the device."""
-    cases = wl.batch2d(count=3, lo=64, hi=100, steps=2)
-    keep = []
-    arr = (_abi.StProblem * len(cases))()
-    for i, c in enumerate(cases):
-        cc = np.ascontiguousarray(c.coeffs)
-        keep.append(cc)
-        arr[i] = _abi.StProblem(2, (ctypes.c_int64 * 3)(*c.n), c.shape, c.radius,
-                                cc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0, 0, 0)
-    h = ctypes.c_void_p()
-    assert L.stencil_plan_batched(arr, len(cases), None, ctypes.byref(h)) == _abi.ST_OK
-    need = L.stencil_workspace_bytes(h, 2, 0)
-    fake = (ctypes.c_void_p * len(cases))(*([0x1000] * len(cases)))
-    assert L.stencil_apply_batched(h, fake, fake, 2, ctypes.c_void_p(0x1000), need, None) == _abi.ST_EUNSUPPORTED
-    assert b"disabled" in L.stencil_last_error()
-    L.stencil_plan_destroy(h)
