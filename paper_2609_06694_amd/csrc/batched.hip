@@ -122,7 +122,7 @@ int member_depth(const st_plan* m) {
     const int r = m->prob.radius;
     int k = std::min(8, std::max(1, m->cfg.tsteps));
     while (k > 1 && (kGroupThreads - 2 * k * r < kWave ||
-                     (int)sizeof(float) * k * (4 + 2 * r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
+                     (int)sizeof(float) * k * ym2d_ring_rows(4, r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
         --k;
     return k;
 }
@@ -163,14 +163,14 @@ Layout layout(const st_plan* plan, int steps, int cus) {
         lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
         b.taps = m->taps;
         lay.rounds = std::max(lay.rounds, b.L);
-        if ((int)sizeof(float) * b.k * (8 + 2 * b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
+        if ((int)sizeof(float) * b.k * ym2d_ring_rows(8, b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
         lay.members.push_back(b);
     }
     // Eight input rows per iteration unless a member's rings would outgrow
     // 64 KiB; the launch reserves the largest member's rings.
     lay.ry = need8 ? 4 : 8;
     for (const GMember& b : lay.members)
-        lay.lds = std::max(lay.lds, sizeof(float) * (size_t)b.k * (lay.ry + 2 * b.r) * (kGroupThreads + 2 * b.r));
+        lay.lds = std::max(lay.lds, sizeof(float) * (size_t)b.k * ym2d_ring_rows(lay.ry, b.r) * (kGroupThreads + 2 * b.r));
     return lay;
 }
 

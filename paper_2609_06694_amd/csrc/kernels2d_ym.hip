@@ -18,12 +18,12 @@ __global__ __launch_bounds__(NT) void ym2d_kernel(const T* __restrict__ in, T* _
 
 int ym2d_lds_bytes(int nt, int k, int R) {
     const int RY = ym2d_rows(nt, k, R);
-    return (int)sizeof(float) * k * (RY + 2 * R) * (nt + 2 * R);
+    return (int)sizeof(float) * k * ym2d_ring_rows(RY, R) * (nt + 2 * R);
 }
 
 int ym2d_rows(int nt, int k, int R) {
     // Eight rows per iteration unless the rings would outgrow 64 KiB.
-    return (int)sizeof(float) * k * (8 + 2 * R) * (nt + 2 * R) <= 64 * 1024 ? 8 : 4;
+    return (int)sizeof(float) * k * ym2d_ring_rows(8, R) * (nt + 2 * R) <= 64 * 1024 ? 8 : 4;
 }
 
 int ym2d_max_lds_bytes() { return 160 * 1024; }
@@ -59,7 +59,7 @@ static hipError_t go(const Geom& g, int k, int ych, const Taps& tp, const void* 
     const int ow = NT - 2 * k * R;
     const int strips = (g.nx + ow - 1) / ow;
     const int chunks = (g.ny + ych - 1) / ych;
-    const size_t lds = sizeof(float) * (size_t)k * (RY + 2 * R) * (NT + 2 * R);
+    const size_t lds = sizeof(float) * (size_t)k * ym2d_ring_rows(RY, R) * (NT + 2 * R);
     auto kern = ym2d_kernel<R, SHAPE, T, BC, NT, RY, D>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -12,10 +12,13 @@
 // NT - 2kR middle columns are the workgroup's outputs.  A chunk of rows
 // re-reads and recomputes kR rows above and below it.
 //
-// Each level's ring holds C = RY + 2R rows: stage s+1 reads exactly the C
-// newest rows of level s, and the next iteration overwrites the RY oldest
-// ones only after the barrier that follows stage s+1 (for k = 1 an extra
-// barrier closes every iteration).  Rows of a level above its first valid
+// Each level's ring holds C rows, C = RY * 2^m >= RY + 2R: stage s+1 reads
+// the RY + 2R newest rows of level s, and the next iteration overwrites the
+// RY oldest ones only after the barrier that follows stage s+1 (for k = 1 an
+// extra barrier closes every iteration).  Because C is a multiple of RY, the
+// ring position of an iteration repeats every C / RY iterations; the march
+// is unrolled by that period, so every ring slot is a compile-time constant
+// and each LDS access is a fixed offset from one per-thread address.  Rows of a level above its first valid
 // row (Y + sR) are computed from rows not yet loaded; they feed only other
 // such rows and are never written out.
 //
@@ -30,6 +33,13 @@
 #include "common.h"
 
 namespace stk {
+
+// Ring rows per level: the smallest RY * 2^m that holds RY + 2R rows.
+__host__ __device__ constexpr int ym2d_ring_rows(int RY, int R) {
+    int c = RY;
+    while (c < RY + 2 * R) c *= 2;
+    return c;
+}
 
 template <int BC>
 __device__ __forceinline__ bool ym_fix(int& i, int n) {
@@ -46,12 +56,16 @@ __device__ __forceinline__ bool ym_fix(int& i, int n) {
 // The window geometry (output width ow = NT - 2 kgeo R, halo rows) is laid
 // out for kgeo fused steps; klev <= kgeo levels are computed (a final,
 // shorter time block keeps the geometry of the others).  `lds` holds
-// klev rings of (RY + 2R) x (NT + 2R) floats.  Called by all NT threads.
+// klev rings of ym2d_ring_rows(RY, R) x (NT + 2R) floats.  Called by all NT
+// threads.
 template <int R, int SHAPE, typename T, int BC, int NT, int RY, int D>
 __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int kgeo,
                          int klev, int ow, int ych, int strips, int b, const Taps& tp,
                          float* __restrict__ lds) {
-    constexpr int C = RY + 2 * R;       // ring rows per level
+    constexpr int C = ym2d_ring_rows(RY, R);   // ring rows per level
+    constexpr int U = C / RY;                  // iterations per ring period
+    constexpr int NRD = RY + 2 * R;            // rows a stage reads from the level below
+    static_assert(U % D == 0, "the prefetch slots must repeat with the ring");
     constexpr int RW = NT + 2 * R;      // ring row width: R pad columns on each side
     const int k = klev;
     const int si = b % strips, ci = b / strips;
@@ -84,14 +98,16 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
 #pragma unroll
     for (int d = 0; d < D; ++d) issue(d, d);
 
-    for (int i0 = 0; i0 < iters; i0 += D) {
+    for (int i0 = 0;; i0 += U) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int i = i0 + d;   // iterations past `iters` compute rows no one reads
-            // Uniform ring offset of this iteration: stage s+1 reads level-s
-            // slots base+0 .. base+C-1 (mod C); stage s writes base+2R+j.
-            int base = (i * RY - 2 * R) % C;
-            base = base < 0 ? base + C : base;
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            if (i >= iters) return;   // uniform: the whole workgroup leaves together
+            const int d = u % D;
+            // Ring offset of this iteration (a constant: i0 is a multiple of
+            // the period U): stage s+1 reads level-s slots base+2R-(RY+2R)
+            // .. base+2R+RY-1, stage s writes base+2R+j (all mod C).
+            const int base = ((u * RY - 2 * R) % C + C) % C;
 
             // Stage 0: stage the input rows of this iteration in ring 0.
             {
@@ -115,9 +131,9 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                     for (int j = 0; j < RY; ++j) acc[j] = 0.f;
 #pragma unroll
                     for (int dx = -R; dx <= R; ++dx) {
-                        float col[C];
+                        float col[NRD];
 #pragma unroll
-                        for (int j = 0; j < C; ++j) {
+                        for (int j = 0; j < NRD; ++j) {
                             int q = base + j;
                             q = q >= C ? q - C : q;
                             col[j] = src[q * RW + R + x + dx];
@@ -129,9 +145,9 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                                 acc[j] = fmaf(tp.c[box2<R>(dy, dx)], col[j + R + dy], acc[j]);
                     }
                 } else {
-                    float col[C];
+                    float col[NRD];
 #pragma unroll
-                    for (int j = 0; j < C; ++j) {
+                    for (int j = 0; j < NRD; ++j) {
                         int q = base + j;
                         q = q >= C ? q - C : q;
                         col[j] = src[q * RW + R + x];
