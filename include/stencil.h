@@ -72,7 +72,8 @@ typedef enum {
     ST_VARIANT_ZM3D = 2,  /* 3D plane-streaming (z-march) with register queues */
     ST_VARIANT_WAVE3D = 3, /* 3D leapfrog z-march, fused source/receiver */
     ST_VARIANT_WAVE3D_LDS = 4, /* 3D leapfrog forward with z-neighbours in an LDS ring */
-    ST_VARIANT_YM2D = 5   /* 2D row march, k fused time steps held in LDS row rings */
+    ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
+    ST_VARIANT_ZM3D_MFMA = 6 /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */

@@ -22,7 +22,8 @@ ST_STAR, ST_BOX = 0, 1
 ST_LINEAR, ST_WAVE = 0, 1
 ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D, ST_VARIANT_WAVE3D_LDS = 0, 1, 2, 3, 4
 ST_VARIANT_YM2D = 5
-VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d"}
+ST_VARIANT_ZM3D_MFMA = 6
+VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",

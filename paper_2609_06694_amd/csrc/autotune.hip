@@ -93,6 +93,12 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                     LaunchCfg c{var, 0, ty, 1, zc};
                     if (cfg_legal(p, c)) out.push_back(c);
                 }
+        // Matrix-core form of the fp16 27-point box (64 x 64 tiles).
+        for (int zc : {16, 32, 64, 128, 0}) {
+            if (zc != 0 && zc >= p.n[2]) continue;
+            LaunchCfg c{ST_VARIANT_ZM3D_MFMA, 0, 64, 1, zc};
+            if (cfg_legal(p, c)) out.push_back(c);
+        }
         return out;
     }
     for (int tx : {64, 128, 256})
@@ -147,7 +153,7 @@ hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, c
         const int kj = std::min(k, steps - done);
         void* dst = ((L - j) % 2 == 0) ? out : tmp;
         hipError_t e = p.ndim == 2 ? launch_linear2d(g, c, taps, cur, dst, kj, s)
-                                   : launch_zm3d(g, c, taps, cur, dst, s);
+                                   : launch_linear3d(g, c, taps, cur, dst, s);
         if (e != hipSuccess) return e;
         cur = dst;
         done += kj;

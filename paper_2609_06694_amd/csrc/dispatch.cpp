@@ -123,6 +123,7 @@ LaunchCfg variant_default(const st_problem& p, int variant) {
         case ST_VARIANT_TB2D: c.tile_x = 64; c.tile_y = 32; c.tsteps = default_cfg(k).tsteps; break;
         case ST_VARIANT_YM2D: c.tile_x = 256; c.tile_y = 0; c.tsteps = default_cfg(k).tsteps; break;
         case ST_VARIANT_ZM3D: c.tile_y = 16; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_ZM3D_MFMA: c.tile_y = 64; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D_LDS: c.tile_y = 32; c.zchunk = kAutoChunk; break;
         default: break;
@@ -212,6 +213,7 @@ static int resident_wgs(const st_problem& p, const LaunchCfg& c) {
     if (p.update == ST_WAVE && c.variant == ST_VARIANT_WAVE3D_LDS)
         return c.tile_y >= 32 ? 1 : (c.tile_y >= 16 ? 2 : 3);
     if (p.update == ST_WAVE) return c.tile_y >= 32 ? 1 : 2;   // adjoint/gradient: ~2 waves per SIMD
+    if (c.variant == ST_VARIANT_ZM3D_MFMA) return 2;
     return 4;
 }
 
@@ -227,7 +229,7 @@ static int device_cus() {
 // once (one round of workgroups; a partial second round costs a whole
 // round's time), with chunks of at least 16 planes.
 int auto_zchunk(const st_problem& p, const LaunchCfg& c) {
-    const int rows = c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8);
+    const int rows = c.tile_y >= 64 ? 64 : (c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8));
     const int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
     const int64_t target = (int64_t)device_cus() * resident_wgs(p, c);
     const int64_t nch = (target + tiles - 1) / tiles;
@@ -247,6 +249,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }
     if (p.ndim == 3) {
+        if (c.variant == ST_VARIANT_ZM3D_MFMA)
+            return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 8 == 0 &&
+                   c.tile_y == 64 && c.zchunk >= 0;
         return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0;
     }

@@ -66,6 +66,17 @@ hipError_t launch_ym2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
                        void* out, int k, hipStream_t stream);
 hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, hipStream_t stream);
+hipError_t launch_zm3d_mfma(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                            void* out, hipStream_t stream);
+bool zm3d_mfma_supported(const Geom& g);
+
+// One launch of a 3D linear sweep through the kernel family the
+// configuration names.
+inline hipError_t launch_linear3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                                  const void* in, void* out, hipStream_t stream) {
+    if (cfg.variant == 6) return launch_zm3d_mfma(g, cfg, taps, in, out, stream);
+    return launch_zm3d(g, cfg, taps, in, out, stream);
+}
 hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
                          const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
                          hipStream_t stream);

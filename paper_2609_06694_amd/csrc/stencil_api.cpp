@@ -225,7 +225,7 @@ hipError_t linear_launch(const st_plan* pl, const Taps& taps, const void* in, vo
                          hipStream_t s) {
     const Geom g = geom_of(pl->prob);
     if (pl->prob.ndim == 2) return launch_linear2d(g, pl->cfg, taps, in, out, k, s);
-    return launch_zm3d(g, pl->cfg, taps, in, out, s);
+    return launch_linear3d(g, pl->cfg, taps, in, out, s);
 }
 
 // Runs `steps` linear steps from u_in into u_out, rotating through the
