@@ -171,20 +171,21 @@ st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wa
                                 void *workspace, size_t ws_bytes, void *stream);
 
 /* Batched plan over `count` independent 2D ST_LINEAR problems of one storage
- * type (shapes, radii, extents and coefficients may differ).  Each member
- * is dispatched through the map like a single plan.  *out owns the plan. */
+ * type and boundary rule (shapes, radii, extents and coefficients may
+ * differ).  opts->tsteps (0 = 2) is the fused depth of the batch, the same
+ * for every member (clamped per member to what its radius allows); the other
+ * option fields apply to each member's own plan.  *out owns the plan. */
 st_status stencil_plan_batched(const st_problem *problems, int32_t count,
                                const st_plan_opts *opts, st_plan **out);
 
 /* All members advanced `steps` steps, one launch per time block for the
- * whole batch: each launch runs one block (the member's own fused depth k)
- * of every member that still has blocks left, so the number of launches is
- * ceil(steps / k) of the shallowest member instead of a sum over members.
- * Workgroups never wait on each other.  u_in / u_out are HOST arrays of
- * `count` device pointers (u_in[i] == u_out[i] allowed).  Workspace from
- * stencil_workspace_bytes(batched_plan, steps, 0): a partner grid per
- * member plus the member table.  Asynchronous on `stream`; ST_EHIP if a
- * launch fails. */
+ * whole batch: each launch runs one block of k fused steps (the batch
+ * depth) of every member, ceil(steps / k) launches in all instead of one
+ * series per member.  Workgroups never wait on each other.  u_in / u_out are
+ * HOST arrays of `count` device pointers (u_in[i] == u_out[i] allowed).
+ * Workspace from stencil_workspace_bytes(batched_plan, steps, 0): a partner
+ * grid per member plus the member table.  Asynchronous on `stream`; ST_EHIP
+ * if a launch fails. */
 st_status stencil_apply_batched(const st_plan *plan, const void *const *u_in,
                                 void *const *u_out, int32_t steps, void *workspace,
                                 size_t ws_bytes, void *stream);

@@ -66,6 +66,8 @@ struct TuneStats {
 
 size_t esize(int dtype) { return dtype == ST_F16 ? 2 : 4; }
 
+size_t grid_bytes_of(const st_problem& p) { return (size_t)p.n[0] * p.n[1] * p.n[2] * esize(p.dtype); }
+
 hipError_t fill(void* p, const st_problem& pr, size_t cells, uint32_t seed, float lo, float hi,
                 hipStream_t s) {
     const unsigned blocks = (unsigned)std::min<size_t>(8192, (cells + 255) / 256);
@@ -275,7 +277,122 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     return ST_OK;
 }
 
+// Steps of the grouped-launch probe: a multiple of every candidate depth
+// but 8, so most candidates run whole blocks.
+constexpr int kBatchProbeSteps = 12;
+
+
+// Fused depth of the grouped batched launch, measured on the member grids:
+// each candidate depth runs the whole batch, every member's output is
+// checked against depth 1, and the fastest passing depth (median of five)
+// becomes the plan's batch depth.
+st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream_t s, TuneStats& st) {
+    const size_t need = batch_tune_bytes(plan);
+    if (bytes < need) {
+        set_error("autotune scratch of %zu bytes needed", need);
+        return ST_EWORKSPACE;
+    }
+#define B_TRY(e)                                                                         \
+    do {                                                                                 \
+        hipError_t e_ = (e);                                                             \
+        if (e_ != hipSuccess) {                                                          \
+            set_error("autotune: %s: %s", #e, hipGetErrorString(e_));                    \
+            return ST_EHIP;                                                              \
+        }                                                                                \
+    } while (0)
+    const int nm = (int)plan->members.size();
+    std::vector<void*> in(nm), out(nm), ref(nm);
+    std::vector<size_t> cells(nm);
+    char* p = scratch;
+    for (int g = 0; g < nm; ++g) {
+        const st_problem& pr = plan->members[g]->prob;
+        cells[g] = (size_t)pr.n[0] * pr.n[1];
+        const size_t gb = (grid_bytes_of(pr) + 255) / 256 * 256;
+        in[g] = p;
+        out[g] = p + gb;
+        ref[g] = p + 2 * gb;
+        p += 3 * gb;
+        B_TRY(fill(in[g], pr, cells[g], 11u + g, 0.f, 1.f, s));
+    }
+    const size_t wsb = stencil_workspace_bytes(plan, kBatchProbeSteps, 0);
+    void* ws = p;
+    unsigned* cnt = (unsigned*)(p + (wsb + 255) / 256 * 256);
+    const int keep = plan->cfg.tsteps;
+    plan->cfg.tsteps = 1;
+    st_status r = stencil_apply_batched(plan, in.data(), ref.data(), kBatchProbeSteps, ws, wsb, s);
+    if (r != ST_OK) {
+        plan->cfg.tsteps = keep;
+        return r;
+    }
+    hipEvent_t e0, e1;
+    B_TRY(hipEventCreate(&e0));
+    B_TRY(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    int best = keep;
+    for (int k : {1, 2, 3, 4, 6, 8}) {
+        ++st.tried;
+        plan->cfg.tsteps = k;
+        r = stencil_apply_batched(plan, in.data(), out.data(), kBatchProbeSteps, ws, wsb, s);
+        if (r != ST_OK) break;
+        bool ok = true;
+        for (int g = 0; g < nm && ok; ++g) {
+            const st_problem& pr = plan->members[g]->prob;
+            unsigned h[2] = {0u, 0u};
+            hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 2);
+            const unsigned blocks = (unsigned)std::min<size_t>(4096, (cells[g] + 255) / 256);
+            if (pr.dtype == ST_F16)
+                hipLaunchKernelGGL(max_diff<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)out[g],
+                                   (const _Float16*)ref[g], cells[g], cnt);
+            else
+                hipLaunchKernelGGL(max_diff<float>, dim3(blocks), dim3(256), 0, s, (const float*)out[g],
+                                   (const float*)ref[g], cells[g], cnt);
+            B_TRY(hipGetLastError());
+            B_TRY(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+            B_TRY(hipStreamSynchronize(s));
+            float dmax, rmax;
+            memcpy(&dmax, &h[0], 4);
+            memcpy(&rmax, &h[1], 4);
+            ok = dmax <= (pr.dtype == ST_F16 ? 2e-3f : 1e-5f) * std::max(rmax, 1e-30f);
+        }
+        if (!ok) {
+            ++st.rejected;
+            continue;
+        }
+        std::vector<float> ms;
+        for (int rep = 0; rep < 6 && r == ST_OK; ++rep) {
+            B_TRY(hipEventRecord(e0, s));
+            r = stencil_apply_batched(plan, in.data(), out.data(), kBatchProbeSteps, ws, wsb, s);
+            B_TRY(hipEventRecord(e1, s));
+            B_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            B_TRY(hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms.push_back(t);
+        }
+        if (r != ST_OK) break;
+        std::sort(ms.begin(), ms.end());
+        if (ms[ms.size() / 2] < best_ms) {
+            best_ms = ms[ms.size() / 2];
+            best = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+#undef B_TRY
+    plan->cfg.tsteps = best;
+    return r;
+}
+
 }  // namespace
+
+namespace stk {
+
+size_t batch_tune_bytes(const st_plan* plan) {
+    size_t g = 0;
+    for (const st_plan* m : plan->members) g += 3 * ((grid_bytes_of(m->prob) + 255) / 256 * 256);
+    return g + stencil_workspace_bytes(plan, kBatchProbeSteps, 0) + 256;
+}
+
+}  // namespace stk
 
 extern "C" {
 
@@ -313,9 +430,11 @@ st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, v
         if (r != ST_OK) return r;
         done.push_back({k, m->cfg});
     }
+    // Then the batch depth of the grouped launch.
+    st_status r = tune_batch_depth(plan, (char*)scratch, scratch_bytes, s, st);
     plan->tune_tried = st.tried;
     plan->tune_rejected = st.rejected;
-    return ST_OK;
+    return r;
 }
 
 st_status stencil_autotune_stats(const st_plan* plan, int32_t* tried, int32_t* rejected) {

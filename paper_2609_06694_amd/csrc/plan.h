@@ -51,6 +51,7 @@ int auto_zchunk(const st_problem& p, const LaunchCfg& c);
 
 void set_error(const char* fmt, ...);
 size_t batched_meta_bytes(const st_plan* plan, int steps);
+size_t batch_tune_bytes(const st_plan* plan);   // autotune scratch for the batch depth
 Geom geom_of(const st_problem& p);
 Geom plan_geom(const st_plan* pl);
 

@@ -450,7 +450,7 @@ void stencil_plan_destroy(st_plan* plan) {
 st_status stencil_plan_describe(const st_plan* plan, int32_t* variant, int32_t* tile_x,
                                 int32_t* tile_y, int32_t* tsteps, int32_t* zchunk) {
     if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
-    const LaunchCfg& c = plan->batched && !plan->members.empty() ? plan->members[0]->cfg : plan->cfg;
+    const LaunchCfg& c = plan->cfg;   // batched: the grouped launch (row march, batch depth)
     if (variant) *variant = c.variant;
     if (tile_x) *tile_x = c.tile_x;
     if (tile_y) *tile_y = c.tile_y;
@@ -549,7 +549,7 @@ extern "C" {
 size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode) {
     if (!plan) return 0;
     if (plan->batched && mode == 2) {
-        size_t m = 0;
+        size_t m = batch_tune_bytes(plan);
         for (const st_plan* x : plan->members) m = std::max(m, stencil_workspace_bytes(x, 0, 2));
         return m;
     }

@@ -66,3 +66,18 @@ def test_autotune_3d_and_wave(st, monkeypatch):
     stats = m.autotune()
     print("wave tuned:", m.describe(), stats)
     assert stats["rejected"] > 0 and m.describe()["tile_y"] != 16
+
+
+def test_autotune_batched_picks_a_batch_depth(st):
+    """Tuning a batched plan tunes every member case and then the depth of
+    the grouped launch itself; the tuned batch still matches the oracle."""
+    cases = wl.batch2d(count=6, lo=96, hi=300, steps=9, seed=5)
+    bs = st.BatchedStencil([dict(n=c.n[:2], shape=c.shape, radius=c.radius, coeffs=c.coeffs) for c in cases])
+    stats = bs.autotune()
+    d = bs.describe()
+    print("batch tuned:", d, stats)
+    assert d["variant"] == "ym2d" and d["tsteps"] in (1, 2, 3, 4, 6, 8)
+    assert stats["tried"] >= 6 and stats["rejected"] == 0
+    outs = bs.apply([torch.from_numpy(c.u0).cuda() for c in cases], 9)
+    for c, o in zip(cases, outs):
+        assert rel_l2(o.cpu().numpy(), oracle.sweep(c.u0, c.coeffs, c.shape, c.radius, wl.PERIODIC, 9)) <= 1e-5

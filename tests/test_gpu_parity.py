@@ -166,6 +166,32 @@ def test_3d_box_fp16_mfma_vs_oracle(st, bc):
         assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, 1, bcode, steps, adjoint=True)) <= TOL["f16"]
 
 
+def test_graph_capture_replays_match_eager(st):
+    """A sweep captured in a HIP graph (torch.cuda.graph) replays bitwise
+    equal to the eager call, every replay, with eager work and
+    synchronisation between replays (tile kernel, row march, z-march)."""
+    rng = np.random.default_rng(31)
+    for n, shape, r, kw, steps in [((512, 512), wl.STAR, 1, {}, 10),
+                                   ((700, 300), wl.BOX, 2, dict(variant=5, tile_x=256, tsteps=2), 5),
+                                   ((96, 70, 40), wl.STAR, 4, {}, 3)]:
+        c = wl.random_unit_sum_coeffs(rng, len(n), shape, r)
+        u = _dev(wl.small_random_grid(rng, len(n), n, np.float32, 0.0, 1.0))
+        s = st.Stencil(n, shape, r, c, **kw)
+        eager = _host(s.apply(u, steps))
+        out = torch.empty_like(u)
+        s.apply(u, steps, out=out)   # allocates the workspace before capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.apply(u, steps, out=out)
+        for rep in range(4):
+            out.fill_(float(rep + 1))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(_host(out), eager), (n, rep)
+
+
 def test_autograd_sweep_backward_is_transpose(st):
     rng = np.random.default_rng(8)
     c = wl.random_unit_sum_coeffs(rng, 2, wl.BOX, 2)
