@@ -105,14 +105,14 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
     }
     for (int tx : {64, 128, 256})
         for (int ty : {16, 32, 64})
-            for (int k : {1, 2, 4, 8}) {
+            for (int k : {1, 2, 4, 8, 10, 16}) {
                 if (tx > 2 * p.n[0] + 64 || ty > 2 * p.n[1] + 16) continue;
                 LaunchCfg c{ST_VARIANT_TB2D, tx, ty, k, 0};
                 if (cfg_legal(p, c)) out.push_back(c);
             }
     // Row march: window width, fused depth, rows per chunk (0 = automatic).
     for (int nt : {256, 512})
-        for (int k : {1, 2, 4, 8})
+        for (int k : {1, 2, 4, 8, 10, 16})
             for (int ych : {0, 32, 64, 128}) {
                 if (nt > 2 * p.n[0] + 256 || (ych != 0 && ych >= p.n[1])) continue;
                 LaunchCfg c{ST_VARIANT_YM2D, nt, ych, k, 0};

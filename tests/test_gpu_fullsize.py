@@ -130,6 +130,21 @@ def test_fullsize_batch64_separate_launches(st):
     assert max(errs) <= 1e-5
 
 
+def test_fullsize_batch64_grouped_launch(st):
+    """The 64-grid workload through the grouped batched launch, as the
+    benchmark runs it, on sampled blocks of every member."""
+    cases = wl.batch2d()
+    bs = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
+                            for c in cases])
+    outs = bs.apply([torch.from_numpy(c.u0).cuda() for c in cases], 32)
+    errs = []
+    for c, o in zip(cases, outs):
+        ny, nx = c.u0.shape
+        errs.append(_sample_linear(c, o.cpu().numpy(), [(0, 0), (ny // 2, nx - 8)], (8, 8)))
+    print(f"64 grids x32 grouped, sampled rel-L2 max {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+
+
 def test_fullsize_wave_gradient_checkpointing(st):
     """At the full gradient size (256^3, 200 steps), checkpointing every 20
     steps gives exactly the gradient of keeping every state, the loss is the
