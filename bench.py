@@ -274,7 +274,7 @@ def cpu_baseline(wl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the stencil library runs on one GPU; run with --gpus 1"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -228,10 +228,10 @@ static int device_cus() {
 // Plane chunk for a z-march: split z so that the grid fills every CU about
 // once (one round of workgroups; a partial second round costs a whole
 // round's time), with chunks of at least 16 planes.
-int auto_zchunk(const st_problem& p, const LaunchCfg& c) {
+int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident) {
     const int rows = c.tile_y >= 64 ? 64 : (c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8));
     const int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
-    const int64_t target = (int64_t)device_cus() * resident_wgs(p, c);
+    const int64_t target = (int64_t)device_cus() * (resident > 0 ? resident : resident_wgs(p, c));
     const int64_t nch = (target + tiles - 1) / tiles;
     if (nch <= 1) return 0;
     int64_t zc = (p.n[2] + nch - 1) / nch;

@@ -86,6 +86,18 @@ bool wave3d_tb2_supported(int r);
 hipError_t launch_wave3d_ring(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
                               const WaveLaunch& w, hipStream_t stream);
 bool wave3d_ring_supported(int r);
+hipError_t launch_wave3d_ring_adj(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                                  const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
+                                  hipStream_t stream);
+
+// One adjoint or gradient step through the kernel family the configuration
+// names (the LDS-ring kernel, or the partial-sum queue kernel).
+inline hipError_t launch_wave_adjoint(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                                      const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
+                                      hipStream_t stream) {
+    if (cfg.variant == 4) return launch_wave3d_ring_adj(g, cfg, taps, taps_fwd, mode, w, stream);
+    return launch_wave3d(g, cfg, taps, taps_fwd, mode, w, stream);
+}
 hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hipStream_t stream);
 hipError_t launch_fill(float* dst, float v, size_t n, hipStream_t stream);
 // loss = 1/2 sum (traces - target)^2 in double, two fixed-order passes

@@ -47,7 +47,8 @@ LaunchCfg variant_default(const st_problem& p, int variant);
 void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
 bool cfg_legal(const st_problem& p, const LaunchCfg& c);
 constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk from the grid
-int auto_zchunk(const st_problem& p, const LaunchCfg& c);
+// resident > 0 overrides the workgroups per CU assumed for the configuration.
+int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident = 0);
 
 void set_error(const char* fmt, ...);
 size_t batched_meta_bytes(const st_plan* plan, int steps);

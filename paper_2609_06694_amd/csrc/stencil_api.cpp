@@ -174,11 +174,11 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
         if (d.zchunk == kAutoChunk) d.zchunk = auto_zchunk(*p, d);
         pl->cfg = d;
     }
-    // The adjoint and gradient steps run the direct-form kernel; its own
-    // default is 64 x 32 tiles (4 rows per thread, 8 waves), the fastest
-    // shape for its larger per-thread state.
-    pl->adj_cfg = LaunchCfg{ST_VARIANT_WAVE3D, 0, 32, 1, 0};
-    pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg);
+    // The adjoint and gradient steps have their own configuration: the
+    // LDS-ring kernel with 64 x 16 tiles (8 waves; the gradient stages two
+    // fields, so one workgroup fills a CU's LDS).
+    pl->adj_cfg = LaunchCfg{ST_VARIANT_WAVE3D_LDS, 0, 16, 1, 0};
+    pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg, 1);
     pl->ckpt_every = 20;
     pl->batched = false;
     if (opts) {
@@ -201,10 +201,16 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
             ST_FAIL(ST_EINVAL, "plan options name an illegal variant/tile/depth for this case");
         }
         pl->cfg = c;
-        // An explicit tile height or chunk applies to the adjoint kernel too.
+        // An explicit partial-sum family, tile height or chunk applies to the
+        // adjoint kernel too.
+        if (opts->variant == ST_VARIANT_WAVE3D) {
+            pl->adj_cfg.variant = ST_VARIANT_WAVE3D;
+            pl->adj_cfg.tile_y = 32;
+        }
         if (opts->tile_y > 0) pl->adj_cfg.tile_y = opts->tile_y;
         if (opts->zchunk > 0) pl->adj_cfg.zchunk = opts->zchunk;
-        else if (opts->tile_y > 0) pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg);
+        else if (opts->tile_y > 0 || opts->variant == ST_VARIANT_WAVE3D)
+            pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg, pl->adj_cfg.variant == ST_VARIANT_WAVE3D_LDS ? 1 : 0);
     }
     *out = pl;
     return ST_OK;
@@ -397,7 +403,7 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
             HIP_TRY(wave_forward_launch(pl, w, s));
         } else {
             w.prev_sign = t == 0 ? -1.f : 1.f;
-            HIP_TRY(launch_wave3d(g, pl->adj_cfg, pl->taps_t, pl->taps, kWaveAdj, w, s));
+            HIP_TRY(launch_wave_adjoint(g, pl->adj_cfg, pl->taps_t, pl->taps, kWaveAdj, w, s));
         }
         prev = cur;
         cur = next;
@@ -675,7 +681,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
             w.grad = dkappa;
             w.rec_z = (int)wave->rec_z;
             w.target_t = t >= 1 ? wave->target + (size_t)(t - 1) * plane : nullptr;
-            HIP_TRY(launch_wave3d(g, plan->adj_cfg, plan->taps_t, plan->taps, kWaveGrad, w, s));
+            HIP_TRY(launch_wave_adjoint(g, plan->adj_cfg, plan->taps_t, plan->taps, kWaveGrad, w, s));
             std::swap(l_next, l_next2);
         }
     }
