@@ -419,3 +419,41 @@ def test_batched_zero_steps_and_single_member(st):
     got = _host(bs.apply([u], 4)[0])
     assert rel_l2(got, oracle.sweep(c.u0, c.coeffs, c.shape, c.radius, wl.PERIODIC, 4)) <= 1e-5
 
+
+
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_degenerate_extents(st, bc):
+    """Grids with extent 1 (or a few cells) along one or two axes through
+    every kernel family: the halos wrap many times (periodic) or read only
+    the zero frame, and tiles are almost all overhang."""
+    rng = np.random.default_rng(808)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    cases2 = [((1, 300), wl.STAR, 3, dict(variant=1, tile_x=64, tile_y=16, tsteps=2)),
+              ((300, 1), wl.BOX, 2, dict(variant=1, tile_x=64, tile_y=32, tsteps=2)),
+              ((1, 300), wl.BOX, 1, dict(variant=5, tile_x=256, tsteps=3)),
+              ((700, 1), wl.STAR, 4, dict(variant=5, tile_x=512, tsteps=2)),
+              ((2, 2), wl.STAR, 4, dict(variant=5, tile_x=256, tsteps=4))]
+    for n, shape, r, kw in cases2:
+        c = wl.random_unit_sum_coeffs(rng, 2, shape, r)
+        u = wl.small_random_grid(rng, 2, n, np.float32, 0.0, 1.0)
+        s = st.Stencil(n, shape, r, c, boundary=bc, **kw)
+        got = _host(s.apply(_dev(u), 5)).astype(np.float64)
+        assert rel_l2(got, oracle.sweep(u, c, shape, r, bcode, 5)) <= 1e-5, (n, kw)
+    cases3 = [((1, 1, 70), wl.STAR, 4, {}), ((90, 1, 1), wl.STAR, 2, dict(variant=2, tile_y=8)),
+              ((1, 40, 3), wl.BOX, 1, {}), ((8, 1, 30), wl.BOX, 1, dict(dtype="f16", variant=6, tile_y=64))]
+    for n, shape, r, kw in cases3:
+        dt = kw.get("dtype", "f32")
+        c = wl.random_unit_sum_coeffs(rng, 3, shape, r)
+        u = wl.small_random_grid(rng, 3, n, np.float16 if dt == "f16" else np.float32, 0.0, 1.0)
+        s = st.Stencil(n, shape, r, c, boundary=bc, **kw)
+        got = _host(s.apply(_dev(u), 3)).astype(np.float64)
+        assert rel_l2(got, oracle.sweep(u, c, shape, r, bcode, 3)) <= TOL[dt], (n, kw)
+    for n, kw in [((1, 1, 40), dict(variant=4, tile_y=32)), ((50, 1, 2), dict(variant=4, tile_y=8)),
+                  ((3, 60, 1), dict(variant=3, tile_y=16))]:
+        kappa = (0.05 + 0.1 * rng.random(n[::-1])).astype(np.float32)
+        u0 = wl.small_random_grid(rng, 3, n, np.float32, -1.0, 1.0)
+        up = (u0 * np.float32(0.9)).astype(np.float32)
+        m = st.WaveModel(n, boundary=bc, **kw)
+        uT, uT1, _ = m.forward(_dev(u0), _dev(up), _dev(kappa), 4)
+        ra, rb, _ = oracle.wave_forward(up, u0, kappa, 4, boundary=bcode)
+        assert rel_l2(_host(uT), rb) <= 1e-5 and rel_l2(_host(uT1), ra) <= 1e-5, (n, kw)
