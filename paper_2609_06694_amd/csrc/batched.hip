@@ -87,13 +87,12 @@ __global__ __launch_bounds__(kGroupThreads) void grouped_kernel(const GMember* _
 template <typename T, int BC, int RY>
 static hipError_t launch_round(const GMember* d_members, int nm, int round, int steps, int grid,
                                size_t lds, hipStream_t s) {
-    auto kern = grouped_kernel<T, BC, RY>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+        hipError_t e = allow_large_lds<grouped_kernel<T, BC, RY>>();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), lds, s, d_members, nm, round, steps);
+    hipLaunchKernelGGL((grouped_kernel<T, BC, RY>), dim3(grid), dim3(kGroupThreads), lds, s, d_members, nm,
+                       round, steps);
     return hipGetLastError();
 }
 

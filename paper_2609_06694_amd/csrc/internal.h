@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "common.h"
 
 namespace stk {
@@ -58,6 +60,22 @@ struct WaveTB2 {
     float* trace1;               // plane for u_{t+1}[rec_z] or null
     float* trace2;               // plane for u_{t+2}[rec_z] or null
 };
+
+// Raises kernel KERN's dynamic-LDS ceiling to the 160 KiB of a gfx950 CU,
+// once per device (the first launch on a device that needs more than the
+// default 64 KiB), so later launches skip the runtime call.
+template <auto KERN>
+inline hipError_t allow_large_lds() {
+    static std::atomic<unsigned long long> done{0};   // bit d: set on device d
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned long long bit = 1ull << (dev & 63);
+    if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+    e = hipFuncSetAttribute((const void*)KERN, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 
 // Launchers (return the launch status; asynchronous on `stream`).
 hipError_t launch_tb2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,

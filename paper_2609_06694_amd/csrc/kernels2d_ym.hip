@@ -60,14 +60,12 @@ static hipError_t go(const Geom& g, int k, int ych, const Taps& tp, const void* 
     const int strips = (g.nx + ow - 1) / ow;
     const int chunks = (g.ny + ych - 1) / ych;
     const size_t lds = sizeof(float) * (size_t)k * ym2d_ring_rows(RY, R) * (NT + 2 * R);
-    auto kern = ym2d_kernel<R, SHAPE, T, BC, NT, RY, D>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+        hipError_t e = allow_large_lds<ym2d_kernel<R, SHAPE, T, BC, NT, RY, D>>();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(strips * chunks), dim3(NT), lds, s, (const T*)in, (T*)out, g.nx, g.ny,
-                       k, ow, ych, strips, tp);
+    hipLaunchKernelGGL((ym2d_kernel<R, SHAPE, T, BC, NT, RY, D>), dim3(strips * chunks), dim3(NT), lds, s,
+                       (const T*)in, (T*)out, g.nx, g.ny, k, ow, ych, strips, tp);
     return hipGetLastError();
 }
 
