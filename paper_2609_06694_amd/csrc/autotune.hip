@@ -95,6 +95,13 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                     LaunchCfg c{var, 0, ty, 1, zc};
                     if (cfg_legal(p, c)) out.push_back(c);
                 }
+        // Two fused steps (radius 1: 62 x (tile_y - 2) output tiles).
+        for (int ty : {16, 32})
+            for (int zc : {32, 64, 128, 0}) {
+                if (zc != 0 && zc >= p.n[2]) continue;
+                LaunchCfg c{ST_VARIANT_ZM3D, 0, ty, 2, zc};
+                if (cfg_legal(p, c)) out.push_back(c);
+            }
         // Matrix-core form of the fp16 27-point box (64 x 64 tiles).
         for (int zc : {16, 32, 64, 128, 0}) {
             if (zc != 0 && zc >= p.n[2]) continue;
@@ -147,7 +154,7 @@ hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, c
         }
         return hipSuccess;
     }
-    const int k = p.ndim == 2 ? std::max(1, c.tsteps) : 1;
+    const int k = p.ndim == 2 ? std::max(1, c.tsteps) : (c.tsteps == 2 ? 2 : 1);
     const int L = (steps + k - 1) / k;
     const void* cur = in;
     int done = 0;
@@ -155,7 +162,7 @@ hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, c
         const int kj = std::min(k, steps - done);
         void* dst = ((L - j) % 2 == 0) ? out : tmp;
         hipError_t e = p.ndim == 2 ? launch_linear2d(g, c, taps, cur, dst, kj, s)
-                                   : launch_linear3d(g, c, taps, cur, dst, s);
+                                   : launch_linear3d(g, c, taps, cur, dst, kj, s);
         if (e != hipSuccess) return e;
         cur = dst;
         done += kj;

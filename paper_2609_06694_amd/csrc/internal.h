@@ -87,11 +87,15 @@ hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
 hipError_t launch_zm3d_mfma(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                             void* out, hipStream_t stream);
 bool zm3d_mfma_supported(const Geom& g);
+hipError_t launch_zm3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
+                           void* out, hipStream_t stream);
+bool zm3d_tb2_supported(int r, int shape);
 
-// One launch of a 3D linear sweep through the kernel family the
-// configuration names.
+// One launch of a 3D linear sweep (k = 1 or 2 fused steps) through the
+// kernel family the configuration names.
 inline hipError_t launch_linear3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
-                                  const void* in, void* out, hipStream_t stream) {
+                                  const void* in, void* out, int k, hipStream_t stream) {
+    if (k == 2) return launch_zm3d_tb2(g, cfg, taps, in, out, stream);
     if (cfg.variant == 6) return launch_zm3d_mfma(g, cfg, taps, in, out, stream);
     return launch_zm3d(g, cfg, taps, in, out, stream);
 }

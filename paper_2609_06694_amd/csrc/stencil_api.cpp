@@ -231,7 +231,7 @@ hipError_t linear_launch(const st_plan* pl, const Taps& taps, const void* in, vo
                          hipStream_t s) {
     const Geom g = geom_of(pl->prob);
     if (pl->prob.ndim == 2) return launch_linear2d(g, pl->cfg, taps, in, out, k, s);
-    return launch_linear3d(g, pl->cfg, taps, in, out, s);
+    return launch_linear3d(g, pl->cfg, taps, in, out, k, s);
 }
 
 // Runs `steps` linear steps from u_in into u_out, rotating through the
@@ -245,7 +245,7 @@ st_status run_linear(const st_plan* pl, const Taps& taps, const void* u_in, void
         return ST_OK;
     }
     if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
-    const int k = pl->prob.ndim == 2 ? std::max(1, pl->cfg.tsteps) : 1;
+    const int k = pl->prob.ndim == 2 ? std::max(1, pl->cfg.tsteps) : (pl->cfg.tsteps == 2 ? 2 : 1);
     const int L = (steps + k - 1) / k;
     const void* cur = u_in;
     if (u_in == u_out && (L % 2) == 1) {

@@ -109,6 +109,30 @@ def test_3d_sweep_vs_oracle(st, shape, r, dtype, bc):
         assert e <= TOL[dtype], (nx, ny, nz, ty, zc, steps, e)
 
 
+@pytest.mark.parametrize("shape", [wl.STAR, wl.BOX])
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_3d_two_step_vs_oracle(st, shape, dtype, bc):
+    """Radius-1 3D sweeps with two steps per launch: several 62 x 30 tiles
+    with ragged tails, plane chunks, odd step counts (a final one-step
+    launch), grids smaller than a tile, in place."""
+    rng = np.random.default_rng(3030 + shape)
+    npdt = np.float32 if dtype == "f32" else np.float16
+    c = wl.random_unit_sum_coeffs(rng, 3, shape, 1)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    for (nx, ny, nz), ty, zc, steps in [((130, 70, 23), 32, 0, 4), ((63, 31, 40), 16, 7, 5),
+                                        ((200, 95, 17), 32, 16, 2), ((5, 4, 6), 16, 0, 3)]:
+        u = wl.small_random_grid(rng, 3, (nx, ny, nz), npdt, 0.0, 1.0)
+        s = st.Stencil((nx, ny, nz), shape, 1, c, dtype=dtype, boundary=bc, variant=2, tile_y=ty, tsteps=2,
+                       zchunk=zc)
+        ref = oracle.sweep(u, c, shape, 1, bcode, steps)
+        got = _host(s.apply(_dev(u), steps)).astype(np.float64)
+        assert rel_l2(got, ref) <= TOL[dtype], (nx, ny, nz, zc, steps, rel_l2(got, ref))
+        d = _dev(u)
+        s.apply(d, steps, out=d)
+        assert rel_l2(_host(d).astype(np.float64), ref) <= TOL[dtype], ("in place", nx, ny, nz)
+
+
 def test_inplace_and_zero_steps(st):
     rng = np.random.default_rng(5)
     c = wl.random_unit_sum_coeffs(rng, 2, wl.BOX, 1)
