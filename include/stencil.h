@@ -172,7 +172,7 @@ st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wa
 
 /* Batched plan over `count` independent 2D ST_LINEAR problems of one storage
  * type and boundary rule (shapes, radii, extents and coefficients may
- * differ).  opts->tsteps (0 = 2) is the fused depth of the batch, the same
+ * differ).  opts->tsteps (0 = 3) is the fused depth of the batch, the same
  * for every member (clamped per member to what its radius allows); the other
  * option fields apply to each member's own plan.  *out owns the plan. */
 st_status stencil_plan_batched(const st_problem *problems, int32_t count,

@@ -136,13 +136,14 @@ struct Layout {
 };
 
 // Geometry of one grouped launch: chunks sized so that every member gets
-// workgroups in proportion to its cells, about four per CU in total.
+// workgroups in proportion to its cells, about eight per CU in total (two
+// and four per CU measured 40 % and 5 % slower on the 64-grid workload).
 Layout layout(const st_plan* plan, int steps, int cus) {
     Layout lay;
     const int nm = (int)plan->members.size();
     double total = 0;
     for (const st_plan* m : plan->members) total += (double)m->prob.n[0] * m->prob.n[1];
-    const double target = 4.0 * cus;
+    const double target = 8.0 * cus;
     int need8 = 0;
     for (int g = 0; g < nm; ++g) {
         const st_plan* m = plan->members[g];
@@ -213,9 +214,9 @@ st_status stencil_plan_batched(const st_problem* problems, int32_t count, const 
     memset(&pl->cfg, 0, sizeof pl->cfg);
     pl->cfg.variant = ST_VARIANT_YM2D;
     pl->cfg.tile_x = kGroupThreads;
-    // Two fused steps measured fastest for the 64-grid workload (k = 3, 4,
-    // 6: 3 %, 30 %, 90 % slower, as the rings of wide stencils cut occupancy).
-    pl->cfg.tsteps = (opts && opts->tsteps > 0) ? opts->tsteps : 2;
+    // Three fused steps measured fastest for the 64-grid workload (k = 1, 2,
+    // 4: 47 %, 5 %, 32 % slower; deeper rings of wide stencils cut occupancy).
+    pl->cfg.tsteps = (opts && opts->tsteps > 0) ? opts->tsteps : 3;
     // Member plans carry the stencils; the batch depth is not theirs to check.
     st_plan_opts mopts;
     if (opts) {
