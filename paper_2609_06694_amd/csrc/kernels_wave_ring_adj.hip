@@ -1,0 +1,218 @@
+// Adjoint and gradient steps of the 3D leapfrog in the LDS-ring design (the
+// forward kernel's staging: halo tile for in-plane taps, ring of interior
+// planes for z taps).
+#include "internal.h"
+#include "zmarch.h"
+
+namespace stk {
+
+// Adjoint (MODE = kWaveAdj) and gradient (MODE = kWaveGrad) steps in the
+// ring design:
+//   adjoint : l_t = 2 l_{t+1} - s * l_{t+2} + L^T(kappa (.) l_{t+1})
+//   gradient: the same with s = 1, plus l_t += [z = rec] (u_t - d_t) and
+//             g += l_{t+1} (.) L(u_t).
+// kappa (.) l_{t+1} (and, for the gradient, u_t) is staged once per plane:
+// its halo tile gives the in-plane taps and its interior enters an LDS ring
+// of 2R+2 planes for the z taps, as in the forward kernel.  The unscaled
+// l_{t+1} of the output plane waits R planes in a register queue.  `tp` holds
+// L^T (the flipped star), `tp2` holds L.  Direct weighted sums, as in the
+// queue kernel of the same steps.
+template <int MODE, int R, int BC, int RY, int NW, int D>
+__global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch w, int nx, int ny,
+                                                                     int nz, int zc, int tiles_x,
+                                                                     int tiles_y, Taps tp, Taps tp2) {
+    using G = PlaneGeom<R, RY, NW>;
+    constexpr bool TWO = (MODE == kWaveGrad);
+    constexpr int NR = 2 * R + 2;
+    constexpr int IP = G::BX * G::BY;
+    __shared__ float tile[TWO ? 2 : 1][2][G::H * G::W];
+    __shared__ float ring[TWO ? 2 : 1][NR][IP];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % tiles_x;
+    const int rest = b / tiles_x;
+    const int tyi = rest % tiles_y, zci = rest / tiles_y;
+    const int x0 = txi * G::BX, y0 = tyi * G::BY;
+    const int z0 = zci * zc, z1 = min(z0 + zc, nz);
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const int gx = x0 + tx;
+    const size_t plane_sz = (size_t)nx * ny;
+    const int zbeg = z0 - R, zend = z1 + R;
+
+    float pq[R + 1][RY], pq2[TWO ? R + 1 : 1][RY];   // in-plane partials, planes zp-R..zp
+    float lq[R + 1][RY];                               // l_{t+1} at this thread's cells
+#pragma unroll
+    for (int q = 0; q <= R; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            pq[q][i] = 0.f;
+            lq[q][i] = 0.f;
+            if constexpr (TWO) pq2[q][i] = 0.f;
+        }
+    float vin[D][RY], vhalo[D][G::HT], kin[D][RY], khalo[D][G::HT];
+    float uin[TWO ? D : 1][RY], uhalo[TWO ? D : 1][G::HT];
+    uint32_t vm[D];
+    float p2v[D][RY], gv[TWO ? D : 1][RY];   // l_{t+2}, g of the output plane
+
+    auto issue_plane = [&](int slot, int zp) __attribute__((always_inline)) {
+        zp = min(zp, zend - 1);
+        vm[slot] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, zp, x0, y0, vin[slot], vhalo[slot]);
+        load_plane<R, RY, BC, float, NW>(w.kappa, nx, ny, nz, zp, x0, y0, kin[slot], khalo[slot]);
+        if constexpr (TWO) load_plane<R, RY, BC, float, NW>(w.u, nx, ny, nz, zp, x0, y0, uin[slot], uhalo[slot]);
+    };
+    auto issue_point = [&](int slot, int zo) __attribute__((always_inline)) {
+        const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
+        const int gxc = min(gx, nx - 1);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            const int gy = min(y0 + ty * RY + i, ny - 1);
+            const uint32_t o = (uint32_t)(gy * nx + gxc);
+            p2v[slot][i] = __builtin_nontemporal_load(&w.prev[zoff + o]);
+            if constexpr (TWO) gv[slot][i] = __builtin_nontemporal_load(&w.grad[zoff + o]);
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        issue_plane(d, zbeg + d);
+        issue_point(d, zbeg + d - R);
+    }
+
+    int slot = 0;
+    for (int zs = zbeg; zs < zend; zs += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int zp = zs + d;   // planes past zend: clamped loads, no output
+            float* t1 = tile[0][zp & 1];
+            store_plane<R, RY, BC, true, float, NW>(t1, vin[d], vhalo[d], vm[d], kin[d], khalo[d]);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const float l = masked<BC>(vin[d][i], vm[d], i);
+                lq[R][i] = l;
+                ring[0][slot][(ty * RY + i) * G::BX + tx] = l * kin[d][i];
+            }
+            float* t2 = nullptr;
+            if constexpr (TWO) {
+                t2 = tile[1][zp & 1];
+                store_plane<R, RY, BC, float, NW>(t2, uin[d], uhalo[d], vm[d]);
+#pragma unroll
+                for (int i = 0; i < RY; ++i)
+                    ring[1][slot][(ty * RY + i) * G::BX + tx] = masked<BC>(uin[d][i], vm[d], i);
+            }
+            issue_plane(d, zp + D);
+            __syncthreads();
+
+            {
+                float p[RY];
+                star_plane<R, RY, NW>(t1, tp, p);
+#pragma unroll
+                for (int i = 0; i < RY; ++i) pq[R][i] = p[i];
+                if constexpr (TWO) {
+                    star_plane<R, RY, NW>(t2, tp2, p);
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) pq2[R][i] = p[i];
+                }
+            }
+
+            const int zo = zp - R;
+            if (zo >= z0 && zo < z1 && gx < nx) {
+                int sl[2 * R + 1];
+#pragma unroll
+                for (int j = 0; j <= 2 * R; ++j) {
+                    const int s2 = slot - 2 * R + j;
+                    sl[j] = s2 < 0 ? s2 + NR : s2;
+                }
+                const size_t zoff = (size_t)zo * plane_sz;
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    const int cell = (ty * RY + i) * G::BX + tx;
+                    float a = pq[0][i];
+#pragma unroll
+                    for (int e = 1; e <= R; ++e) {
+                        a = fmaf(tp.c[star_z<R>(-e)], ring[0][sl[R - e]][cell], a);
+                        a = fmaf(tp.c[star_z<R>(e)], ring[0][sl[R + e]][cell], a);
+                    }
+                    const int gy = y0 + ty * RY + i;
+                    if (gy >= ny) continue;
+                    const uint32_t o = (uint32_t)(gy * nx + gx);
+                    float v;
+                    if constexpr (MODE == kWaveAdj) {
+                        v = 2.f * lq[0][i] - w.prev_sign * p2v[d][i] + a;
+                    } else {
+                        float a2 = pq2[0][i];
+#pragma unroll
+                        for (int e = 1; e <= R; ++e) {
+                            a2 = fmaf(tp2.c[star_z<R>(-e)], ring[1][sl[R - e]][cell], a2);
+                            a2 = fmaf(tp2.c[star_z<R>(e)], ring[1][sl[R + e]][cell], a2);
+                        }
+                        v = 2.f * lq[0][i] - p2v[d][i] + a;
+                        if (w.target_t != nullptr && zo == w.rec_z) v += ring[1][sl[R]][cell] - w.target_t[o];
+                        __builtin_nontemporal_store(fmaf(lq[0][i], a2, gv[d][i]), &w.grad[zoff + o]);
+                    }
+                    __builtin_nontemporal_store(v, &w.next[zoff + o]);
+                }
+            }
+            issue_point(d, zp + D - R);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    pq[q][i] = pq[q + 1][i];
+                    lq[q][i] = lq[q + 1][i];
+                    if constexpr (TWO) pq2[q][i] = pq2[q + 1][i];
+                }
+            slot = slot + 1 == NR ? 0 : slot + 1;
+        }
+    }
+}
+
+template <int MODE, int R, int BC, int NW>
+static hipError_t go_adj(const Geom& g, int zc, const Taps& tp, const Taps& tp2, const WaveLaunch& w,
+                         hipStream_t s) {
+    using G = PlaneGeom<R, 2, NW>;
+    const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
+    const int nchunks = (g.nz + zc - 1) / zc;
+    hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, 2>), dim3(tiles_x * tiles_y * nchunks),
+                       dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+    return hipGetLastError();
+}
+
+template <int MODE, int R, int BC>
+static hipError_t go_adj_ty(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                            const WaveLaunch& w, hipStream_t s) {
+    const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
+    // Two staged fields (gradient) need two rings: 32-row tiles would not fit in LDS.
+    if constexpr (MODE == kWaveAdj)
+        if (c.tile_y >= 32) return go_adj<MODE, R, BC, 16>(g, zc, tp, tp2, w, s);
+    if (c.tile_y >= 16) return go_adj<MODE, R, BC, 8>(g, zc, tp, tp2, w, s);
+    return go_adj<MODE, R, BC, 4>(g, zc, tp, tp2, w, s);
+}
+
+template <int MODE, int R>
+static hipError_t go_adj_bc(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                            const WaveLaunch& w, hipStream_t s) {
+    return g.boundary == kPeriodic ? go_adj_ty<MODE, R, kPeriodic>(g, c, tp, tp2, w, s)
+                                   : go_adj_ty<MODE, R, kZero>(g, c, tp, tp2, w, s);
+}
+
+template <int MODE>
+static hipError_t go_adj_r(const Geom& g, const LaunchCfg& c, const Taps& tp, const Taps& tp2,
+                           const WaveLaunch& w, hipStream_t s) {
+    switch (g.r) {
+        case 1: return go_adj_bc<MODE, 1>(g, c, tp, tp2, w, s);
+        case 2: return go_adj_bc<MODE, 2>(g, c, tp, tp2, w, s);
+        case 3: return go_adj_bc<MODE, 3>(g, c, tp, tp2, w, s);
+        case 4: return go_adj_bc<MODE, 4>(g, c, tp, tp2, w, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// `taps` is L^T (applied to kappa (.) lambda), `taps_fwd` is L (applied to
+// u_t in gradient mode).
+hipError_t launch_wave3d_ring_adj(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
+                                  const Taps& taps_fwd, WaveMode mode, const WaveLaunch& w,
+                                  hipStream_t stream) {
+    if (mode == kWaveAdj) return go_adj_r<kWaveAdj>(g, cfg, taps, taps_fwd, w, stream);
+    if (mode == kWaveGrad) return go_adj_r<kWaveGrad>(g, cfg, taps, taps_fwd, w, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stk
