@@ -48,7 +48,7 @@ typedef enum {
     ST_OK = 0,
     ST_EINVAL = 1,        /* null pointer, bad enum, negative steps, bad opts */
     ST_ESHAPE = 2,        /* grid extent too small for the radius, or too large */
-    ST_EUNSUPPORTED = 3,  /* legal but not provided (e.g. 3D box r > 1, fp16 wave) */
+    ST_EUNSUPPORTED = 3,  /* legal but not provided (e.g. box r > 2, fp16 wave) */
     ST_EWORKSPACE = 4,    /* workspace missing or smaller than required */
     ST_EHIP = 5,          /* a HIP runtime call or kernel launch failed */
     ST_ENOMEM = 6,        /* host allocation failed */
@@ -82,7 +82,7 @@ typedef struct {
     int32_t ndim;          /* 2 or 3 */
     int64_t n[3];          /* nx, ny, nz */
     int32_t shape;         /* st_shape */
-    int32_t radius;        /* 1..4; box: r <= 2 in 2D, r == 1 in 3D */
+    int32_t radius;        /* 1..4; box: r <= 2 */
     const float *coeffs;   /* HOST, (2r+1)^ndim dense; for ST_WAVE may be NULL,
                               meaning the central second-difference Laplacian
                               of accuracy order 2r */

@@ -13,7 +13,7 @@ constexpr int kZero = 1;
 constexpr int kThreads = 256;      // every kernel runs 4 waves of 64
 constexpr int kWave = 64;
 constexpr int kXcds = 8;           // MI355X: 8 accelerator dies, 32 CUs each
-constexpr int kMaxTaps = 81;       // 2D box r = 4
+constexpr int kMaxTaps = 125;      // 3D box r = 2
 constexpr int kMaxRadius = 4;
 
 // Compact coefficient list, passed by value as a kernel argument.

@@ -1,4 +1,4 @@
-// 3D linear sweep (star r = 1..4, box r = 1): plane-streaming z-march.
+// 3D linear sweep (star r = 1..4, box r = 1..2): plane-streaming z-march.
 #include "internal.h"
 #include "zmarch.h"
 
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
 
 bool zm3d_supported(int r, int shape) {
     if (shape == kStar) return r >= 1 && r <= 4;
-    return r == 1;
+    return r >= 1 && r <= 2;
 }
 
 int zm3d_rows(const LaunchCfg& cfg) { return cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8); }
@@ -155,7 +155,11 @@ static hipError_t go_bc(const Geom& g, const LaunchCfg& c, const Taps& tp, const
 template <typename T>
 static hipError_t go_t(const Geom& g, const LaunchCfg& c, const Taps& tp, const void* in,
                        void* out, hipStream_t s) {
-    if (g.shape == kBox) return g.r == 1 ? go_bc<1, kBox, T>(g, c, tp, in, out, s) : hipErrorInvalidValue;
+    if (g.shape == kBox) {
+        if (g.r == 1) return go_bc<1, kBox, T>(g, c, tp, in, out, s);
+        if (g.r == 2) return go_bc<2, kBox, T>(g, c, tp, in, out, s);
+        return hipErrorInvalidValue;
+    }
     switch (g.r) {
         case 1: return go_bc<1, kStar, T>(g, c, tp, in, out, s);
         case 2: return go_bc<2, kStar, T>(g, c, tp, in, out, s);

@@ -184,6 +184,17 @@ def box2d(n: int = 4096, steps: int = 100, dtype: int = F16, seed: int = SEED_BO
     return LinearCase(f"box2d_r2_{tag}", 2, (n, n, 1), BOX, 2, c, PERIODIC, steps, u0, dtype)
 
 
+def box3d_r2(n: int = 512, steps: int = 10, dtype: int = F32, seed: int = SEED_BOX + 20) -> LinearCase:
+    """The 125-point 3D box (radius 2), the compute-bound corner of the
+    paper's kernel matrix (Sections 4.3 and 7.2.3): same coefficient and data law as the
+    27-point box."""
+    rng = np.random.default_rng(seed)
+    c = random_unit_sum_coeffs(rng, 3, BOX, 2)
+    u0 = _uniform(rng, 0.0, 1.0, (n, n, n), DTYPE_NP[dtype])
+    tag = "f16" if dtype == F16 else "f32"
+    return LinearCase(f"box3d_r2_{tag}", 3, (n, n, n), BOX, 2, c, PERIODIC, steps, u0, dtype)
+
+
 # --------------------------------------------------------------------------
 # Workload 4: 64 uneven 2D grids with mixed stencils.
 # --------------------------------------------------------------------------

@@ -68,7 +68,7 @@ def _plan(L, p, opts=None):
     (dict(n=(0, 48, 1)), _abi.ST_ESHAPE),
     (dict(n=(1 << 25, 4, 1)), _abi.ST_ESHAPE),
     (dict(shape=1, r=3), _abi.ST_EUNSUPPORTED),
-    (dict(ndim=3, n=(8, 8, 8), shape=1, r=2), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=3, n=(8, 8, 8), shape=1, r=3), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=1), _abi.ST_EUNSUPPORTED),
     (dict(ndim=2, n=(8, 8, 1), update=1, coeffs=None), _abi.ST_EUNSUPPORTED),
 ])

@@ -79,6 +79,19 @@ def test_fullsize_box3d(st, dtype):
 
 
 @pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
+def test_fullsize_box3d_r2(st, dtype):
+    """The 125-point box on 512^3 x 10 steps (the compute-bound case)."""
+    case = wl.box3d_r2(dtype=dtype)
+    dt = "f16" if dtype == wl.F16 else "f32"
+    s = st.Stencil(case.n, "box", 2, case.coeffs, dtype=dt)
+    got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
+    starts = [(0, 0, 0), (505, 250, 478)]
+    e = _sample_linear(case, got, starts, (4, 6, 8))
+    print(f"box3d r2 {dt} 512^3 x10 sampled rel-L2 {e:.2e}")
+    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
 def test_fullsize_box2d(st, dtype):
     case = wl.box2d(dtype=dtype)
     dt = "f16" if dtype == wl.F16 else "f32"

@@ -88,7 +88,7 @@ def test_2d_rowmarch_vs_oracle(st, shape, r, dtype, bc):
         assert e <= TOL[dtype], (nx, ny, nt, k, ych, steps, e)
 
 
-CASES_3D = [(wl.STAR, r) for r in (1, 2, 3, 4)] + [(wl.BOX, 1)]
+CASES_3D = [(wl.STAR, r) for r in (1, 2, 3, 4)] + [(wl.BOX, 1), (wl.BOX, 2)]
 
 
 @pytest.mark.parametrize("shape,r", CASES_3D)
@@ -145,7 +145,8 @@ def test_inplace_and_zero_steps(st):
         assert rel_l2(_host(d), ref) <= 1e-6, steps
 
 
-@pytest.mark.parametrize("ndim,shape,r", [(2, wl.STAR, 3), (2, wl.BOX, 2), (3, wl.STAR, 2), (3, wl.BOX, 1)])
+@pytest.mark.parametrize("ndim,shape,r", [(2, wl.STAR, 3), (2, wl.BOX, 2), (3, wl.STAR, 2), (3, wl.BOX, 1),
+                                         (3, wl.BOX, 2)])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
 def test_linear_adjoint_vs_oracle_and_dot(st, ndim, shape, r, bc):
     rng = np.random.default_rng(7 + r)
@@ -464,7 +465,8 @@ def test_degenerate_extents(st, bc):
         got = _host(s.apply(_dev(u), 5)).astype(np.float64)
         assert rel_l2(got, oracle.sweep(u, c, shape, r, bcode, 5)) <= 1e-5, (n, kw)
     cases3 = [((1, 1, 70), wl.STAR, 4, {}), ((90, 1, 1), wl.STAR, 2, dict(variant=2, tile_y=8)),
-              ((1, 40, 3), wl.BOX, 1, {}), ((8, 1, 30), wl.BOX, 1, dict(dtype="f16", variant=6, tile_y=64))]
+              ((1, 40, 3), wl.BOX, 1, {}), ((8, 1, 30), wl.BOX, 1, dict(dtype="f16", variant=6, tile_y=64)),
+              ((3, 2, 50), wl.BOX, 2, dict(variant=2, tile_y=16)), ((70, 1, 4), wl.BOX, 2, {})]
     for n, shape, r, kw in cases3:
         dt = kw.get("dtype", "f32")
         c = wl.random_unit_sum_coeffs(rng, 3, shape, r)

@@ -32,7 +32,7 @@ def _rand_coeffs(rng, ndim, shape, r):
 BRUTE_CASES = [
     (2, (5, 7), STAR, 1), (2, (6, 5), STAR, 2), (2, (4, 9), STAR, 4), (2, (7, 6), BOX, 1),
     (2, (5, 8), BOX, 2), (2, (3, 3), BOX, 2), (3, (4, 5, 6), STAR, 1), (3, (5, 4, 3), BOX, 1),
-    (3, (3, 4, 9), STAR, 4), (3, (6, 6, 6), STAR, 2),
+    (3, (3, 4, 9), STAR, 4), (3, (6, 6, 6), STAR, 2), (3, (4, 6, 5), BOX, 2),
 ]
 
 
@@ -71,7 +71,8 @@ def test_jacobi_sine_mode_decays_by_symbol(oracle_lib):
 
 
 @pytest.mark.parametrize("ndim,kind,r,n", [(2, BOX, 2, (12, 10)), (3, BOX, 1, (8, 6, 10)),
-                                           (3, STAR, 3, (7, 9, 8)), (2, STAR, 4, (11, 13))])
+                                           (3, STAR, 3, (7, 9, 8)), (2, STAR, 4, (11, 13)),
+                                           (3, BOX, 2, (9, 7, 10))])
 def test_fourier_symbol_general(oracle_lib, ndim, kind, r, n):
     """e^{i k.x} is an eigenvector of a periodic sweep with eigenvalue
     sum_d c_d e^{i k.d}; the real part of lambda^T e^{i k.x} is the result."""
@@ -91,7 +92,7 @@ def test_fourier_symbol_general(oracle_lib, ndim, kind, r, n):
     assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, abs(lam) ** T)
 
 
-@pytest.mark.parametrize("ndim,kind,r", [(2, STAR, 1), (2, BOX, 2), (3, BOX, 1), (3, STAR, 4)])
+@pytest.mark.parametrize("ndim,kind,r", [(2, STAR, 1), (2, BOX, 2), (3, BOX, 1), (3, STAR, 4), (3, BOX, 2)])
 def test_sum_conservation_periodic(oracle_lib, ndim, kind, r):
     """Under periodic boundaries sum(u^T) = s^T sum(u^0), s = sum of coefficients."""
     rng = np.random.default_rng(3)
@@ -104,7 +105,7 @@ def test_sum_conservation_periodic(oracle_lib, ndim, kind, r):
     assert abs(got.sum() - s ** T * u.sum()) < 1e-11 * u.size
 
 
-@pytest.mark.parametrize("ndim,kind,r", [(2, BOX, 2), (3, STAR, 2), (3, BOX, 1)])
+@pytest.mark.parametrize("ndim,kind,r", [(2, BOX, 2), (3, STAR, 2), (3, BOX, 1), (3, BOX, 2)])
 def test_polynomial_moments_zero_boundary(oracle_lib, ndim, kind, r):
     """Away from the edges, sum_d c_d p(x+d) = sum_alpha m_alpha D^alpha p(x)/alpha!
     with m_alpha = sum_d c_d d^alpha; checked for a quadratic p."""
