@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 WAVE_BYTES_PER_CELL = 16     # read u_t, u_{t-1}, kappa; write u_{t+1}
+# FP32 vector peak without packed FP32 (the kernels are built without it):
+# 256 CUs x 64 FMA lanes x 2 flop x 2.4 GHz.  The published 157.3 TFLOP/s
+# counts packed (two-wide) FP32.
+VALU_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -202,9 +206,12 @@ def bench_linear(dev, st, wl, torch, case, reps=3):
     ms = timed(lambda: s.apply(u, case.steps, out=out), reps, 1, torch.cuda.synchronize)
     g = gcells(case.cells, case.steps, ms)
     bpc = 2 * (2 if dt == "f16" else 4)
+    taps = (2 * case.radius + 1) ** case.ndim if case.shape == wl.BOX else 1 + 2 * case.ndim * case.radius
+    fpc = 2 * taps   # one multiply-add per tap, f32 arithmetic for either storage type
     return {"workload": f"{case.name}_{'x'.join(str(v) for v in case.n[:case.ndim])}_{case.steps}steps",
             "ms": ms, "gcells_s": g, "eff_gbs": g * bpc, "hbm_frac": g * bpc / HBM_PEAK_GBS,
-            "bytes_per_cell_update": bpc, "dispatch": s.describe()}
+            "bytes_per_cell_update": bpc, "flop_per_cell_update": fpc, "valu_tflops": g * fpc / 1e3,
+            "valu_frac": g * fpc / 1e3 / VALU_PEAK_TFLOPS, "dispatch": s.describe()}
 
 
 def bench_batch(dev, st, wl, torch):
@@ -313,6 +320,8 @@ def main():
             ("jacobi2d", lambda: bench_jacobi(dev, st, wl, torch)),
             ("box3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F16))),
             ("box3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F32))),
+            ("box3d_r2_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16))),
+            ("box3d_r2_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F32))),
             ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),
             ("box2d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F32))),
             ("batch64", lambda: bench_batch(dev, st, wl, torch)),

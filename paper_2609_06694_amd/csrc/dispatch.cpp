@@ -61,7 +61,11 @@ CaseKey classify(const st_problem& p) {
     k.boundary = p.boundary;
     k.update = p.update;
     const double cells = (double)p.n[0] * (double)p.n[1] * (double)p.n[2];
-    k.size_class = cells <= (double)(1 << 20) ? 0 : cells <= (double)(1 << 22) ? 1 : cells <= (double)(1 << 25) ? 2 : 3;
+    k.size_class = cells <= (double)(1 << 18)   ? 0
+                   : cells <= (double)(1 << 20) ? 1
+                   : cells <= (double)(1 << 22) ? 2
+                   : cells <= (double)(1 << 25) ? 3
+                                                : 4;
     int64_t lo = p.n[0], hi = p.n[0];
     for (int a = 1; a < p.ndim; ++a) {
         lo = p.n[a] < lo ? p.n[a] : lo;
@@ -94,7 +98,7 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.zchunk = kAutoChunk;
         return c;
     }
-    if (k.size_class == 0) {
+    if (k.size_class <= 1) {
         // Small grids: square LDS tiles give enough workgroups; deeper
         // fusion for narrow stencils (these launches are short).
         c.variant = ST_VARIANT_TB2D;

@@ -4,6 +4,8 @@
 
 namespace stk {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // D planes are kept in flight per workgroup: the register slot of plane zp
 // is refilled with plane zp + D as soon as zp has been staged in LDS.
 template <int R, int SHAPE, typename T, int BC, int RY, int NW, int D>
@@ -29,6 +31,22 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int i = 0; i < RY; ++i) acc[q][i] = 0.f;
+
+    // The 125 weights of the radius-2 box do not fit in scalar registers (the
+    // compiler would park them in vector lanes and read each one back before
+    // use).  They are kept in LDS instead, grouped by dx and padded to whole
+    // 4-vectors, and read back as uniform vectors once per plane; the first
+    // barrier of the march publishes them.
+    constexpr bool kLdsTaps = SHAPE == kBox && R >= 2;
+    constexpr int kPerDx = (Q * Q + 3) / 4 * 4;
+    __shared__ f32x4 ctab[kLdsTaps ? Q * kPerDx / 4 : 1];
+    if constexpr (kLdsTaps) {
+        float* cf = reinterpret_cast<float*>(ctab);
+        for (int i = threadIdx.x; i < Q * kPerDx; i += NW * kWave) {
+            const int dxi = i / kPerDx, j = i % kPerDx;   // j = (dz+R)*Q + (dy+R)
+            cf[i] = j < Q * Q ? tp.c[j * Q + dxi] : 0.f;
+        }
+    }
 
     // In-flight planes stay in storage precision until staged.  Plane
     // indices past the end of the march are clamped to its last plane (a
@@ -69,6 +87,45 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                         acc[R + e][i] = fmaf(tp.c[star_z<R>(-e)], cen[i], acc[R + e][i]);
                     }
                 }
+            } else if constexpr (kLdsTaps) {
+                // An offset the compiler cannot see through keeps the weight
+                // reads inside the march (hoisted, they would need 125
+                // registers).
+                int cb = 0;
+                asm volatile("" : "+v"(cb));
+#pragma unroll
+                for (int dx = -R; dx <= R; ++dx) {
+                    float col[RY + 2 * R];
+                    const float* base = t + (ty * RY) * G::W + R + tx + dx;
+#pragma unroll
+                    for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+                    float w[kPerDx];
+#pragma unroll
+                    for (int v = 0; v < kPerDx / 4; ++v) {
+                        const f32x4 q = ctab[cb + (dx + R) * (kPerDx / 4) + v];
+                        w[4 * v] = q.x;
+                        w[4 * v + 1] = q.y;
+                        w[4 * v + 2] = q.z;
+                        w[4 * v + 3] = q.w;
+                    }
+#pragma unroll
+                    for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+                        for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                            for (int i = 0; i < RY; ++i)
+                                acc[R - dz][i] = fmaf(w[(dz + R) * Q + dy + R], col[i + R + dy], acc[R - dz][i]);
+                    // One dx group at a time: the scheduler would otherwise
+                    // issue all weight reads of the plane at once.
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // Pin the sums here: the compiler would otherwise sink the
+                // multiply-adds past the store branches, away from the weight
+                // reads, leaving every weight live at once.
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) asm volatile("" : "+v"(acc[q][i]));
             } else {
 #pragma unroll
                 for (int dx = -R; dx <= R; ++dx) {

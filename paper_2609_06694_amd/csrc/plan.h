@@ -32,7 +32,7 @@ namespace stk {
 // shape and precision; a cell names the kernel structure that won there).
 struct CaseKey {
     int ndim, shape, r, dtype, boundary, update;
-    int size_class;   // 0: <= 2^20 cells, 1: <= 2^22, 2: <= 2^25, 3: larger
+    int size_class;   // 0: <= 2^18 cells, 1: <= 2^20, 2: <= 2^22, 3: <= 2^25, 4: larger
     int slab;         // 1 if the longest side is >= 4x the shortest
 };
 

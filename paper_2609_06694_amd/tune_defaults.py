@@ -24,6 +24,8 @@ def main(out: str) -> None:
     for dt in ("f16", "f32"):
         c = wl.box3d(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
         plans.append((f"box3d 512^3 {dt}", st.Stencil((512, 512, 512), "box", 1, c.coeffs, dtype=dt)))
+        c = wl.box3d_r2(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
+        plans.append((f"box3d r2 512^3 {dt}", st.Stencil((512, 512, 512), "box", 2, c.coeffs, dtype=dt)))
         c = wl.box2d(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
         plans.append((f"box2d 4096^2 {dt}", st.Stencil((4096, 4096), "box", 2, c.coeffs, dtype=dt)))
     plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))
@@ -32,7 +34,7 @@ def main(out: str) -> None:
     seen = set()
     for g in wl.batch2d():
         cells = g.n[0] * g.n[1]
-        size_class = 0 if cells <= 1 << 20 else (1 if cells <= 1 << 22 else (2 if cells <= 1 << 25 else 3))
+        size_class = sum(cells > 1 << b for b in (18, 20, 22, 25))
         slab = max(g.n[:2]) >= 4 * min(g.n[:2])
         key = (g.shape, g.radius, size_class, slab)
         if key in seen:
