@@ -53,9 +53,10 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
     // cache hit), keeping every load unconditional.
     T vin[D][RY], vhalo[D][G::HT];
     uint32_t vm[D];
+    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, T, NW>(nx, ny, x0, y0);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), x0, y0, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
 
     for (int zb = zbeg; zb < zend; zb += D) {
 #pragma unroll
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
             float cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) cen[i] = masked<BC>(vin[d][i], vm[d], i);
-            vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), x0, y0, vin[d], vhalo[d]);
+            vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
             __syncthreads();
 
             if constexpr (SHAPE == kStar) {

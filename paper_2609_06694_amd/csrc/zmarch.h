@@ -131,6 +131,60 @@ __device__ __forceinline__ uint32_t load_plane(const T* __restrict__ f, int nx, 
     return m;
 }
 
+// The in-plane part of load_plane's addressing, which is the same for every
+// plane of a march: byte offsets of this thread's cells within a plane
+// (after the boundary rule) and their x/y validity bits.  Computed once per
+// workgroup, it leaves one scalar plane base and unconditional loads per plane.
+template <int R, int RY, int NW = 4>
+struct PlaneIdx {
+    uint32_t off[RY + PlaneGeom<R, RY, NW>::HT];
+    uint32_t mxy;
+};
+
+template <int R, int RY, int BC, typename T, int NW = 4>
+__device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x0, int y0) {
+    using G = PlaneGeom<R, RY, NW>;
+    static_assert(RY + G::HT <= 32, "validity mask holds 32 cells");
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    PlaneIdx<R, RY, NW> pi;
+    pi.mxy = 0;
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        int gx = x0 + tx, gy = y0 + ty * RY + i;
+        const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
+        pi.off[i] = (uint32_t)(gy * nx + gx) * (uint32_t)sizeof(T);
+        pi.mxy |= (uint32_t)(okx && oky) << i;
+    }
+#pragma unroll
+    for (int j = 0; j < G::HT; ++j) {
+        const int h = threadIdx.x + j * G::NT;
+        const bool hv = h < G::NH;
+        int ly, lx;
+        halo_coord<R, RY, NW>(hv ? h : 0, ly, lx);
+        int gx = x0 - R + lx, gy = y0 - R + ly;
+        const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
+        pi.off[RY + j] = (uint32_t)(gy * nx + gx) * (uint32_t)sizeof(T);
+        pi.mxy |= (uint32_t)(hv && okx && oky) << (RY + j);
+    }
+    return pi;
+}
+
+// load_plane with the in-plane addressing taken from plane_index.
+template <int R, int RY, int BC, typename T, int NW = 4>
+__device__ __forceinline__ uint32_t load_plane_at(const T* __restrict__ f, int nx, int ny, int nz, int zp,
+                                                  const PlaneIdx<R, RY, NW>& pi, T (&in)[RY],
+                                                  T (&halo)[PlaneGeom<R, RY, NW>::HT]) {
+    using G = PlaneGeom<R, RY, NW>;
+    int gz = zp;
+    const bool zin = fix_coord<BC>(gz, nz);
+    const char* plane = reinterpret_cast<const char*>(f + (size_t)gz * nx * ny);
+#pragma unroll
+    for (int i = 0; i < RY; ++i) in[i] = *reinterpret_cast<const T*>(plane + pi.off[i]);
+#pragma unroll
+    for (int j = 0; j < G::HT; ++j) halo[j] = *reinterpret_cast<const T*>(plane + pi.off[RY + j]);
+    return zin ? pi.mxy : 0u;
+}
+
 // Writes a loaded plane (mask m from load_plane) into an LDS tile of H x W
 // floats, multiplying by `scale_in[i]` / `scale_halo[j]` when SCALED (used
 // for kappa (.) lambda; the scale is read at the same cells, so the mask of
