@@ -49,24 +49,25 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
 #pragma unroll
         for (int i = 0; i < RY; ++i) pq[q][i] = 0.f;
 
-    // Unconditional loads (clamped to the chunk and the grid; values at
-    // clamped cells are never used), for the reason given at load_plane.
+    // In-plane addressing, the same for every plane of the march.
+    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, float, NW>(nx, ny, x0, y0);
+
+    // Unconditional loads (clamped to the chunk; the interior offsets of
+    // pidx are valid addresses, and values at cells outside the grid are
+    // never used), for the reason given at load_plane.
     auto issue_point = [&](int slot, int zo) {
         const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
-        const float* pp = w.prev + zoff;
-        const float* kp = w.kappa + zoff;
-        const int gxc = min(gx, nx - 1);
+        const char* pp = reinterpret_cast<const char*>(w.prev + zoff);
+        const char* kp = reinterpret_cast<const char*>(w.kappa + zoff);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            const int gy = min(y0 + ty * RY + i, ny - 1);
-            const uint32_t o = (uint32_t)(gy * nx + gxc);
-            pv[slot][i] = __builtin_nontemporal_load(&pp[o]);
-            kv[slot][i] = __builtin_nontemporal_load(&kp[o]);
+            pv[slot][i] = __builtin_nontemporal_load(reinterpret_cast<const float*>(pp + pidx.off[i]));
+            kv[slot][i] = __builtin_nontemporal_load(reinterpret_cast<const float*>(kp + pidx.off[i]));
         }
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        vm[d] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), x0, y0, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
         issue_point(d, zbeg + d - R);
     }
 
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
             store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
 #pragma unroll
             for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
-            vm[d] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zp + D, zend - 1), x0, y0, vin[d], vhalo[d]);
+            vm[d] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
             __syncthreads();
 
             float p[RY], uc[RY];
