@@ -58,9 +58,10 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_tb2_kernel(const T* __restric
     const int zbeg = z0 - 2 * R, zend = z1e + 2 * R;
     T vin[D][RY], vhalo[D][GA::HT];
     uint32_t vm[D];
+    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, T, NW>(nx, ny, ex0, ey0);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), ex0, ey0, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
 
     for (int zb = zbeg; zb < zend; zb += D) {
 #pragma unroll
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_tb2_kernel(const T* __restric
             float cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) cen[i] = masked<BC>(vin[d][i], vm[d], i);
-            vm[d] = load_plane<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), ex0, ey0, vin[d], vhalo[d]);
+            vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
             __syncthreads();
 
             // ---- stage 1: plane zp of u_t into the u_{t+1} queue

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        vm[d] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
         issue_point(d, zbeg + d - R);
     }
 
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
             store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
 #pragma unroll
             for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
-            vm[d] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
+            vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
             __syncthreads();
 
             float p[RY], uc[RY];

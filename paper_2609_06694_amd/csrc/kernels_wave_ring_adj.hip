@@ -53,21 +53,24 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch 
     uint32_t vm[D];
     float p2v[D][RY], gv[TWO ? D : 1][RY];   // l_{t+2}, g of the output plane
 
+    // In-plane addressing, the same for every plane and field of the march.
+    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, float, NW>(nx, ny, x0, y0);
     auto issue_plane = [&](int slot, int zp) __attribute__((always_inline)) {
         zp = min(zp, zend - 1);
-        vm[slot] = load_plane<R, RY, BC, float, NW>(w.cur, nx, ny, nz, zp, x0, y0, vin[slot], vhalo[slot]);
-        load_plane<R, RY, BC, float, NW>(w.kappa, nx, ny, nz, zp, x0, y0, kin[slot], khalo[slot]);
-        if constexpr (TWO) load_plane<R, RY, BC, float, NW>(w.u, nx, ny, nz, zp, x0, y0, uin[slot], uhalo[slot]);
+        vm[slot] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, zp, pidx, vin[slot], vhalo[slot]);
+        load_plane_at<R, RY, BC, float, NW>(w.kappa, nx, ny, nz, zp, pidx, kin[slot], khalo[slot]);
+        if constexpr (TWO) load_plane_at<R, RY, BC, float, NW>(w.u, nx, ny, nz, zp, pidx, uin[slot], uhalo[slot]);
     };
+    // The interior offsets of pidx are valid addresses; values at cells
+    // outside the grid are never used.
     auto issue_point = [&](int slot, int zo) __attribute__((always_inline)) {
         const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
-        const int gxc = min(gx, nx - 1);
+        const char* pp = reinterpret_cast<const char*>(w.prev + zoff);
+        const char* gp = reinterpret_cast<const char*>(w.grad + zoff);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            const int gy = min(y0 + ty * RY + i, ny - 1);
-            const uint32_t o = (uint32_t)(gy * nx + gxc);
-            p2v[slot][i] = __builtin_nontemporal_load(&w.prev[zoff + o]);
-            if constexpr (TWO) gv[slot][i] = __builtin_nontemporal_load(&w.grad[zoff + o]);
+            p2v[slot][i] = load_at_nt<float>(pp, pidx.off[i]);
+            if constexpr (TWO) gv[slot][i] = load_at_nt<float>(gp, pidx.off[i]);
         }
     };
 #pragma unroll

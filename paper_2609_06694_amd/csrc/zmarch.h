@@ -169,8 +169,26 @@ __device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x
     return pi;
 }
 
+// Value at byte offset `off` from a uniform base.  The offset passes through
+// an empty asm statement at the point of use so that its zero extension stays
+// next to the load: the load then takes the scalar-base + 32-bit-offset form
+// instead of a 64-bit address built per load (and the loop-invariant offset
+// is not kept as a 64-bit register pair).  It costs a register copy per load;
+// PIN = false leaves the choice to the compiler (measured faster for the
+// wave kernel, slower for the linear z-march and the gradient).
+template <typename T, bool PIN = true>
+__device__ __forceinline__ T load_at(const char* base, uint32_t off) {
+    if constexpr (PIN) asm volatile("" : "+v"(off));
+    return *reinterpret_cast<const T*>(base + off);
+}
+template <typename T>
+__device__ __forceinline__ T load_at_nt(const char* base, uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(base + off));
+}
+
 // load_plane with the in-plane addressing taken from plane_index.
-template <int R, int RY, int BC, typename T, int NW = 4>
+template <int R, int RY, int BC, typename T, int NW = 4, bool PIN = true>
 __device__ __forceinline__ uint32_t load_plane_at(const T* __restrict__ f, int nx, int ny, int nz, int zp,
                                                   const PlaneIdx<R, RY, NW>& pi, T (&in)[RY],
                                                   T (&halo)[PlaneGeom<R, RY, NW>::HT]) {
@@ -179,9 +197,9 @@ __device__ __forceinline__ uint32_t load_plane_at(const T* __restrict__ f, int n
     const bool zin = fix_coord<BC>(gz, nz);
     const char* plane = reinterpret_cast<const char*>(f + (size_t)gz * nx * ny);
 #pragma unroll
-    for (int i = 0; i < RY; ++i) in[i] = *reinterpret_cast<const T*>(plane + pi.off[i]);
+    for (int i = 0; i < RY; ++i) in[i] = load_at<T, PIN>(plane, pi.off[i]);
 #pragma unroll
-    for (int j = 0; j < G::HT; ++j) halo[j] = *reinterpret_cast<const T*>(plane + pi.off[RY + j]);
+    for (int j = 0; j < G::HT; ++j) halo[j] = load_at<T, PIN>(plane, pi.off[RY + j]);
     return zin ? pi.mxy : 0u;
 }
 
