@@ -32,6 +32,7 @@ WAVE_BYTES_PER_CELL = 16     # read u_t, u_{t-1}, kappa; write u_{t+1}
 # 256 CUs x 64 FMA lanes x 2 flop x 2.4 GHz.  The published 157.3 TFLOP/s
 # counts packed (two-wide) FP32.
 VALU_PEAK_TFLOPS = 78.6
+VALU_F64_PEAK_TFLOPS = 78.6   # FP64 vector, published
 
 
 def log(msg):
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--pmc-target", action="store_true",
                     help="run only the profiler target: a 512 MiB device copy (counter calibration) "
                          "then one 2-step pass of the headline workload")
+    ap.add_argument("--shapes", action="store_true",
+                    help="also sweep the 7- and 27-point 3D sweeps over cubes and slabs (f16/f32/f64)")
     ap.add_argument("--stream-ceiling", action="store_true",
                     help="also measure plain streaming kernels (copy, read-3/write-1) as the "
                          "practical bandwidth ceiling")
@@ -197,21 +200,58 @@ def bench_jacobi(dev, st, wl, torch):
             "dispatch": s.describe()}
 
 
+ESIZE = {"f16": 2, "f32": 4, "f64": 8}
+
+
 def bench_linear(dev, st, wl, torch, case, reps=3):
-    dt = "f16" if case.dtype == wl.F16 else "f32"
+    dt = wl.DTYPE_TAGS[case.dtype]
     shape = wl.SHAPE_NAMES[case.shape]
     s = st.Stencil(case.n[:case.ndim], shape, case.radius, case.coeffs, dtype=dt)
     u = torch.from_numpy(case.u0).to(dev)
     out = torch.empty_like(u)
     ms = timed(lambda: s.apply(u, case.steps, out=out), reps, 1, torch.cuda.synchronize)
     g = gcells(case.cells, case.steps, ms)
-    bpc = 2 * (2 if dt == "f16" else 4)
+    bpc = 2 * ESIZE[dt]
     taps = (2 * case.radius + 1) ** case.ndim if case.shape == wl.BOX else 1 + 2 * case.ndim * case.radius
-    fpc = 2 * taps   # one multiply-add per tap, f32 arithmetic for either storage type
+    fpc = 2 * taps   # one multiply-add per tap (f32 arithmetic; f64 for f64 storage)
     return {"workload": f"{case.name}_{'x'.join(str(v) for v in case.n[:case.ndim])}_{case.steps}steps",
             "ms": ms, "gcells_s": g, "eff_gbs": g * bpc, "hbm_frac": g * bpc / HBM_PEAK_GBS,
             "bytes_per_cell_update": bpc, "flop_per_cell_update": fpc, "valu_tflops": g * fpc / 1e3,
-            "valu_frac": g * fpc / 1e3 / VALU_PEAK_TFLOPS, "dispatch": s.describe()}
+            "valu_frac": g * fpc / 1e3 / (VALU_F64_PEAK_TFLOPS if dt == "f64" else VALU_PEAK_TFLOPS),
+            "dispatch": s.describe()}
+
+
+# Cubes of the paper's kernel matrix and slab stand-ins (its slab sizes are
+# not given): thin in z, thin in y, and a long narrow column.
+SHAPES = [("cube128", (128, 128, 128)), ("cube256", (256, 256, 256)), ("cube512", (512, 512, 512)),
+          ("cube1024", (1024, 1024, 1024)), ("slab_z", (4096, 4096, 8)), ("slab_y", (4096, 64, 512)),
+          ("column_z", (64, 64, 32768))]
+
+
+def bench_shapes(dev, st, wl, torch):
+    """7- and 27-point 3D sweeps (10 steps) over cubes and slabs in each
+    storage type, with the default dispatch; inputs are seeded device-side
+    uniform draws (timing only: parity is covered by the tests)."""
+    out = {}
+    rng = np.random.default_rng(77)
+    torch.manual_seed(77)
+    for sname, r in (("star", 1), ("box", 1)):
+        c = wl.random_unit_sum_coeffs(rng, 3, wl.STAR if sname == "star" else wl.BOX, r)
+        for dt in ("f16", "f32", "f64"):
+            tdt = {"f16": torch.float16, "f32": torch.float32, "f64": torch.float64}[dt]
+            for tag, n in SHAPES:
+                s = st.Stencil(n, sname, r, c, dtype=dt)
+                u = torch.rand((n[2], n[1], n[0]), device=dev, dtype=tdt)
+                o = torch.empty_like(u)
+                ms = timed(lambda: s.apply(u, 10, out=o), 3, 1, torch.cuda.synchronize)
+                cells = n[0] * n[1] * n[2]
+                g = gcells(cells, 10, ms)
+                out[f"{sname}1_{dt}_{tag}"] = {"grid": list(n), "ms": round(ms, 4), "gcells_s": round(g, 1),
+                                               "hbm_frac": round(g * 2 * ESIZE[dt] / HBM_PEAK_GBS, 3),
+                                               "dispatch": s.describe()}
+                del u, o
+                torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(dev, st, wl, torch):
@@ -320,6 +360,9 @@ def main():
             ("jacobi2d", lambda: bench_jacobi(dev, st, wl, torch)),
             ("box3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F16))),
             ("box3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F32))),
+            ("star3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F16))),
+            ("star3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F32))),
+            ("star3d_f64", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F64))),
             ("box3d_r2_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16))),
             ("box3d_r2_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F32))),
             ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),
@@ -335,6 +378,10 @@ def main():
             log(f"{name}: {json.dumps(extras[name])} ({time.perf_counter() - t0:.1f} s)")
             torch.cuda.empty_cache()
         line["per_config"] = extras
+    if args.shapes:
+        t0 = time.perf_counter()
+        line["shapes"] = bench_shapes(dev, st, wl, torch)
+        log(f"shapes: {json.dumps(line['shapes'])} ({time.perf_counter() - t0:.1f} s)")
     if args.stream_ceiling:
         line["stream_ceiling"] = stream_ceiling(dev, torch)
         log(f"stream ceiling: {line['stream_ceiling']}")

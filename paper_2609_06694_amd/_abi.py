@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("STENCIL_LIBRARY") or os.path.join(HERE, "libstencil.s
 ST_OK, ST_EINVAL, ST_ESHAPE, ST_EUNSUPPORTED, ST_EWORKSPACE, ST_EHIP, ST_ENOMEM, ST_ETUNE = range(8)
 STATUS_NAMES = {0: "ST_OK", 1: "ST_EINVAL", 2: "ST_ESHAPE", 3: "ST_EUNSUPPORTED", 4: "ST_EWORKSPACE",
                 5: "ST_EHIP", 6: "ST_ENOMEM", 7: "ST_ETUNE"}
-ST_F32, ST_F16 = 0, 1
+ST_F32, ST_F16, ST_F64 = 0, 1, 2
 ST_PERIODIC, ST_ZERO = 0, 1
 ST_STAR, ST_BOX = 0, 1
 ST_LINEAR, ST_WAVE = 0, 1

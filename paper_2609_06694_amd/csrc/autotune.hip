@@ -32,23 +32,44 @@ __device__ __forceinline__ float hash_unit(uint32_t i, uint32_t seed) {
 template <typename T>
 __global__ void fill_random(T* p, size_t n, uint32_t seed, float lo, float hi) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = from_f32<T>(lo + (hi - lo) * hash_unit((uint32_t)i, seed));
+        p[i] = from_acc<T>(lo + (hi - lo) * hash_unit((uint32_t)i, seed));
 }
 
-// out[0] = max |a - b|, out[1] = max |b|; values are non-negative floats, so
-// their bit patterns order like unsigned integers.
+// out[0] = max |a - b|, out[1] = max |b|, as f32 bit patterns (non-negative
+// floats order like unsigned integers); differences are formed in the
+// arithmetic type and rounded up to f32 at the end.
 template <typename T>
 __global__ void max_diff(const T* a, const T* b, size_t n, unsigned* out) {
-    float d = 0.f, m = 0.f;
+    using A = acc_t<T>;
+    A d = 0, m = 0;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float x = to_f32(a[i]), y = to_f32(b[i]);
-        const float e = fabsf(x - y);
-        d = (e > d || e != e) ? (e != e ? INFINITY : e) : d;
-        m = fmaxf(m, fabsf(y));
+        const A x = to_acc<T>(a[i]), y = to_acc<T>(b[i]);
+        const A e = x > y ? x - y : y - x;
+        d = (e > d || e != e) ? (e != e ? A(INFINITY) : e) : d;
+        m = fmax(m, y < 0 ? -y : y);
     }
-    atomicMax(&out[0], __float_as_uint(d));
-    atomicMax(&out[1], __float_as_uint(m));
+    float df = (float)d, mf = (float)m;
+    if ((A)df < d) df = nextafterf(df, INFINITY);
+    atomicMax(&out[0], __float_as_uint(df));
+    atomicMax(&out[1], __float_as_uint(mf));
 }
+
+// Per-dtype launch of max_diff.
+void launch_max_diff(int dtype, const void* a, const void* b, size_t n, unsigned* out, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<size_t>(4096, (n + 255) / 256);
+    if (dtype == ST_F16)
+        hipLaunchKernelGGL(max_diff<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)a,
+                           (const _Float16*)b, n, out);
+    else if (dtype == ST_F64)
+        hipLaunchKernelGGL(max_diff<double>, dim3(blocks), dim3(256), 0, s, (const double*)a, (const double*)b,
+                           n, out);
+    else
+        hipLaunchKernelGGL(max_diff<float>, dim3(blocks), dim3(256), 0, s, (const float*)a, (const float*)b, n,
+                           out);
+}
+
+// Relative tolerance of a candidate against the plain kernel, by dtype.
+float parity_tol(int dtype) { return dtype == ST_F16 ? 2e-3f : (dtype == ST_F64 ? 1e-10f : 1e-5f); }
 
 __global__ void zero_u32(unsigned* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
@@ -64,7 +85,7 @@ struct TuneStats {
     int tried = 0, rejected = 0;
 };
 
-size_t esize(int dtype) { return dtype == ST_F16 ? 2 : 4; }
+size_t esize(int dtype) { return dtype == ST_F16 ? 2 : (dtype == ST_F64 ? 8 : 4); }
 
 size_t grid_bytes_of(const st_problem& p) { return (size_t)p.n[0] * p.n[1] * p.n[2] * esize(p.dtype); }
 
@@ -73,6 +94,8 @@ hipError_t fill(void* p, const st_problem& pr, size_t cells, uint32_t seed, floa
     const unsigned blocks = (unsigned)std::min<size_t>(8192, (cells + 255) / 256);
     if (pr.dtype == ST_F16)
         hipLaunchKernelGGL(fill_random<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)p, cells, seed, lo, hi);
+    else if (pr.dtype == ST_F64)
+        hipLaunchKernelGGL(fill_random<double>, dim3(blocks), dim3(256), 0, s, (double*)p, cells, seed, lo, hi);
     else
         hipLaunchKernelGGL(fill_random<float>, dim3(blocks), dim3(256), 0, s, (float*)p, cells, seed, lo, hi);
     return hipGetLastError();
@@ -235,20 +258,14 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
         T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
         unsigned h[2] = {0u, 0u};
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 2);
-        const unsigned blocks = (unsigned)std::min<size_t>(4096, (cells + 255) / 256);
-        if (p.dtype == ST_F16)
-            hipLaunchKernelGGL(max_diff<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)out,
-                               (const _Float16*)ref, cells, cnt);
-        else
-            hipLaunchKernelGGL(max_diff<float>, dim3(blocks), dim3(256), 0, s, (const float*)out,
-                               (const float*)ref, cells, cnt);
+        launch_max_diff(p.dtype, out, ref, cells, cnt, s);
         T_TRY(hipGetLastError());
         T_TRY(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
         T_TRY(hipStreamSynchronize(s));
         float dmax, rmax;
         memcpy(&dmax, &h[0], 4);
         memcpy(&rmax, &h[1], 4);
-        const float tol = (p.dtype == ST_F16 ? 2e-3f : 1e-5f) * std::max(rmax, 1e-30f);
+        const float tol = parity_tol(p.dtype) * std::max(rmax, 1e-30f);
         if (!(dmax <= tol)) {
             ++st.rejected;
             continue;
@@ -346,20 +363,14 @@ st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream
             const st_problem& pr = plan->members[g]->prob;
             unsigned h[2] = {0u, 0u};
             hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 2);
-            const unsigned blocks = (unsigned)std::min<size_t>(4096, (cells[g] + 255) / 256);
-            if (pr.dtype == ST_F16)
-                hipLaunchKernelGGL(max_diff<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)out[g],
-                                   (const _Float16*)ref[g], cells[g], cnt);
-            else
-                hipLaunchKernelGGL(max_diff<float>, dim3(blocks), dim3(256), 0, s, (const float*)out[g],
-                                   (const float*)ref[g], cells[g], cnt);
+            launch_max_diff(pr.dtype, out[g], ref[g], cells[g], cnt, s);
             B_TRY(hipGetLastError());
             B_TRY(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
             B_TRY(hipStreamSynchronize(s));
             float dmax, rmax;
             memcpy(&dmax, &h[0], 4);
             memcpy(&rmax, &h[1], 4);
-            ok = dmax <= (pr.dtype == ST_F16 ? 2e-3f : 1e-5f) * std::max(rmax, 1e-30f);
+            ok = dmax <= parity_tol(pr.dtype) * std::max(rmax, 1e-30f);
         }
         if (!ok) {
             ++st.rejected;

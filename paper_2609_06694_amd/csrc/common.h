@@ -50,6 +50,33 @@ __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float
 template <typename T>
 __device__ __forceinline__ float round_to_storage(float v) { return to_f32(from_f32<T>(v)); }
 
+// Arithmetic type of a storage type: f32 for fp16 and f32 storage, f64 for
+// f64 storage.
+template <typename T>
+struct AccOf {
+    using type = float;
+};
+template <>
+struct AccOf<double> {
+    using type = double;
+};
+template <typename T>
+using acc_t = typename AccOf<T>::type;
+__device__ __forceinline__ double to_f64(double v) { return v; }
+// Stored value -> arithmetic type, and back (rounding to nearest even).
+template <typename T>
+__device__ __forceinline__ acc_t<T> to_acc(T v) {
+    if constexpr (sizeof(acc_t<T>) == 8) return to_f64(v);
+    else return to_f32(v);
+}
+template <typename T>
+__device__ __forceinline__ T from_acc(acc_t<T> v) {
+    if constexpr (sizeof(acc_t<T>) == 8) return v;
+    else return from_f32<T>(v);
+}
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return fma(a, b, c); }
+
 // Workgroups are handed to the XCDs round-robin in launch order.  Renumber
 // them so each XCD receives one contiguous run of logical tiles: neighbouring
 // tiles then share halo rows through the same L2.  Bijective for any count.

@@ -78,7 +78,7 @@ CaseKey classify(const st_problem& p) {
 std::string key_string(const CaseKey& k) {
     char buf[128];
     snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
-             k.r, k.dtype == 0 ? "f32" : "f16", k.boundary == kPeriodic ? "periodic" : "zero",
+             k.r, k.dtype == 0 ? "f32" : (k.dtype == 1 ? "f16" : "f64"), k.boundary == kPeriodic ? "periodic" : "zero",
              k.update == 0 ? "linear" : "wave", k.size_class, k.slab ? " slab" : "");
     return buf;
 }
@@ -94,7 +94,7 @@ static LaunchCfg default_cfg(const CaseKey& k) {
     }
     if (k.ndim == 3) {
         c.variant = ST_VARIANT_ZM3D;
-        c.tile_y = k.dtype == 1 ? 16 : 32;
+        c.tile_y = k.dtype == 0 ? 32 : 16;
         c.zchunk = kAutoChunk;
         return c;
     }
@@ -261,6 +261,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         if (c.variant == ST_VARIANT_ZM3D && c.tsteps == 2 &&
             (!zm3d_tb2_supported(p.radius, p.shape) || (c.tile_y != 16 && c.tile_y != 32)))
             return false;
+        if (p.dtype == ST_F64)   // f64: one step per launch, 8- or 16-row tiles
+            return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16) && c.zchunk >= 0 &&
+                   c.tsteps >= 0 && c.tsteps <= 1;
         return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }

@@ -14,7 +14,8 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                                                           int nz, int zc, int tiles_x, int tiles_y,
                                                           Taps tp) {
     using G = PlaneGeom<R, RY, NW>;
-    __shared__ float tile[2][G::H * G::W];
+    using A = acc_t<T>;   // arithmetic type (f64 for f64 storage, else f32)
+    __shared__ A tile[2][G::H * G::W];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int txi = b % tiles_x;
     const int rest = b / tiles_x;
@@ -26,11 +27,11 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
     const int zbeg = z0 - R, zend = z1 + R;
 
     constexpr int Q = 2 * R + 1;
-    float acc[Q][RY];
+    A acc[Q][RY];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int i = 0; i < RY; ++i) acc[q][i] = 0.f;
+        for (int i = 0; i < RY; ++i) acc[q][i] = A(0);
 
     // The 125 weights of the radius-2 box do not fit in scalar registers (the
     // compiler would park them in vector lanes and read each one back before
@@ -66,16 +67,16 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
             // past zend are clamped loads that emit no output.  (A uniform
             // early exit here would let the compiler assume fewer loads in
             // flight at the loop head and wait for all of them.)
-            float* t = tile[zp & 1];
+            A* t = tile[zp & 1];
             store_plane<R, RY, BC, T, NW>(t, vin[d], vhalo[d], vm[d]);
-            float cen[RY];
+            A cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) cen[i] = masked<BC>(vin[d][i], vm[d], i);
             vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
             __syncthreads();
 
             if constexpr (SHAPE == kStar) {
-                float p[RY];
+                A p[RY];
                 star_plane<R, RY, NW>(t, tp, p);
                 // plane zp feeds output zo = zp - dz with weight c_z(dz); slot R - dz
 #pragma unroll
@@ -84,8 +85,8 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                 for (int e = 1; e <= R; ++e) {
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
-                        acc[R - e][i] = fmaf(tp.c[star_z<R>(e)], cen[i], acc[R - e][i]);
-                        acc[R + e][i] = fmaf(tp.c[star_z<R>(-e)], cen[i], acc[R + e][i]);
+                        acc[R - e][i] = fma_acc(A(tp.c[star_z<R>(e)]), cen[i], acc[R - e][i]);
+                        acc[R + e][i] = fma_acc(A(tp.c[star_z<R>(-e)]), cen[i], acc[R + e][i]);
                     }
                 }
             } else if constexpr (kLdsTaps) {
@@ -96,11 +97,11 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                 asm volatile("" : "+v"(cb));
 #pragma unroll
                 for (int dx = -R; dx <= R; ++dx) {
-                    float col[RY + 2 * R];
-                    const float* base = t + (ty * RY) * G::W + R + tx + dx;
+                    A col[RY + 2 * R];
+                    const A* base = t + (ty * RY) * G::W + R + tx + dx;
 #pragma unroll
                     for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
-                    float w[kPerDx];
+                    A w[kPerDx];
 #pragma unroll
                     for (int v = 0; v < kPerDx / 4; ++v) {
                         const f32x4 q = ctab[cb + (dx + R) * (kPerDx / 4) + v];
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                         for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
                             for (int i = 0; i < RY; ++i)
-                                acc[R - dz][i] = fmaf(w[(dz + R) * Q + dy + R], col[i + R + dy], acc[R - dz][i]);
+                                acc[R - dz][i] = fma_acc(w[(dz + R) * Q + dy + R], col[i + R + dy], acc[R - dz][i]);
                     // One dx group at a time: the scheduler would otherwise
                     // issue all weight reads of the plane at once.
                     __builtin_amdgcn_sched_barrier(0);
@@ -130,8 +131,8 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
             } else {
 #pragma unroll
                 for (int dx = -R; dx <= R; ++dx) {
-                    float col[RY + 2 * R];
-                    const float* base = t + (ty * RY) * G::W + R + tx + dx;
+                    A col[RY + 2 * R];
+                    const A* base = t + (ty * RY) * G::W + R + tx + dx;
 #pragma unroll
                     for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
 #pragma unroll
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
                         for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
                             for (int i = 0; i < RY; ++i)
-                                acc[R - dz][i] = fmaf(tp.c[box3<R>(dz, dy, dx)], col[i + R + dy],
+                                acc[R - dz][i] = fma_acc(A(tp.c[box3<R>(dz, dy, dx)]), col[i + R + dy],
                                                       acc[R - dz][i]);
                 }
             }
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     const int gy = y0 + ty * RY + i;
-                    if (gy < ny) __builtin_nontemporal_store(from_f32<T>(acc[0][i]), &o[(uint32_t)(gy * nx + gx)]);
+                    if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[0][i]), &o[(uint32_t)(gy * nx + gx)]);
                 }
             }
 #pragma unroll
@@ -196,10 +197,17 @@ template <int R, int SHAPE, typename T, int BC>
 static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const void* in,
                         void* out, hipStream_t s) {
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
-    switch (zm3d_rows(c)) {
-        case 8: return go<R, SHAPE, T, BC, 2, 4>(g, zc, tp, in, out, s);
-        case 16: return go<R, SHAPE, T, BC, 4, 4>(g, zc, tp, in, out, s);
-        default: return go<R, SHAPE, T, BC, 8, 4>(g, zc, tp, in, out, s);
+    if constexpr (sizeof(T) == 8) {
+        // f64: partial sums and tiles take twice the registers and LDS; 8- and
+        // 16-row tiles only.
+        if (zm3d_rows(c) == 8) return go<R, SHAPE, T, BC, 2, 4>(g, zc, tp, in, out, s);
+        return go<R, SHAPE, T, BC, 4, 4>(g, zc, tp, in, out, s);
+    } else {
+        switch (zm3d_rows(c)) {
+            case 8: return go<R, SHAPE, T, BC, 2, 4>(g, zc, tp, in, out, s);
+            case 16: return go<R, SHAPE, T, BC, 4, 4>(g, zc, tp, in, out, s);
+            default: return go<R, SHAPE, T, BC, 8, 4>(g, zc, tp, in, out, s);
+        }
     }
 }
 
@@ -230,6 +238,7 @@ static hipError_t go_t(const Geom& g, const LaunchCfg& c, const Taps& tp, const 
 hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, hipStream_t stream) {
     if (g.dtype == 0) return go_t<float>(g, cfg, taps, in, out, stream);
+    if (g.dtype == 2) return go_t<double>(g, cfg, taps, in, out, stream);
     return go_t<_Float16>(g, cfg, taps, in, out, stream);
 }
 

@@ -32,7 +32,7 @@ namespace {
 constexpr int64_t kMaxExtent = int64_t(1) << 24;
 constexpr double kMaxCells = 68719476736.0;   // 2^36
 
-size_t elem_bytes(int dtype) { return dtype == ST_F16 ? 2 : 4; }
+size_t elem_bytes(int dtype) { return dtype == ST_F16 ? 2 : (dtype == ST_F64 ? 8 : 4); }
 
 size_t cells_of(const st_problem& p) { return (size_t)p.n[0] * (size_t)p.n[1] * (size_t)p.n[2]; }
 
@@ -100,7 +100,8 @@ st_status validate(const st_problem* p) {
     if (!p) ST_FAIL(ST_EINVAL, "problem is NULL");
     if (p->ndim != 2 && p->ndim != 3) ST_FAIL(ST_EINVAL, "ndim must be 2 or 3 (got %d)", p->ndim);
     if (p->shape != ST_STAR && p->shape != ST_BOX) ST_FAIL(ST_EINVAL, "unknown shape %d", p->shape);
-    if (p->dtype != ST_F32 && p->dtype != ST_F16) ST_FAIL(ST_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->dtype != ST_F32 && p->dtype != ST_F16 && p->dtype != ST_F64)
+        ST_FAIL(ST_EINVAL, "unknown dtype %d", p->dtype);
     if (p->boundary != ST_PERIODIC && p->boundary != ST_ZERO)
         ST_FAIL(ST_EINVAL, "unknown boundary %d", p->boundary);
     if (p->update != ST_LINEAR && p->update != ST_WAVE) ST_FAIL(ST_EINVAL, "unknown update %d", p->update);
@@ -119,6 +120,7 @@ st_status validate(const st_problem* p) {
         if (p->dtype != ST_F32) ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 storage");
     } else {
         if (!p->coeffs) ST_FAIL(ST_EINVAL, "coefficients are NULL");
+        if (p->dtype == ST_F64 && p->ndim != 3) ST_FAIL(ST_EUNSUPPORTED, "f64 storage is provided for 3D sweeps");
         if (p->ndim == 2 && !tb2d_supported(p->radius, p->shape))
             ST_FAIL(ST_EUNSUPPORTED, "2D %s r=%d is not provided", p->shape == ST_STAR ? "star" : "box",
                     p->radius);

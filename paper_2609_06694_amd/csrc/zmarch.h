@@ -73,13 +73,13 @@ __device__ __forceinline__ bool fix_coord(int& i, int n) {
     return ok;
 }
 
-// A loaded value as f32, or zero if mask bit `bit` says its cell lies
-// outside the domain (zero frame only).
+// A loaded value in its arithmetic type, or zero if mask bit `bit` says its
+// cell lies outside the domain (zero frame only).
 template <int BC, typename T>
-__device__ __forceinline__ float masked(T v, uint32_t m, int bit) {
-    const float f = to_f32(v);
+__device__ __forceinline__ acc_t<T> masked(T v, uint32_t m, int bit) {
+    const acc_t<T> f = to_acc<T>(v);
     if (BC == kPeriodic) return f;
-    return ((m >> bit) & 1u) ? f : 0.f;
+    return ((m >> bit) & 1u) ? f : acc_t<T>(0);
 }
 
 // Issues the loads of one plane of `f` (this thread's RY interior values and
@@ -207,16 +207,16 @@ __device__ __forceinline__ uint32_t load_plane_at(const T* __restrict__ f, int n
 // floats, multiplying by `scale_in[i]` / `scale_halo[j]` when SCALED (used
 // for kappa (.) lambda; the scale is read at the same cells, so the mask of
 // the plane also covers it).
-template <int R, int RY, int BC, bool SCALED, typename T, int NW = 4>
-__device__ __forceinline__ void store_plane(float* __restrict__ tile, const T (&in)[RY],
+template <int R, int RY, int BC, bool SCALED, typename T, int NW = 4, typename A = float>
+__device__ __forceinline__ void store_plane(A* __restrict__ tile, const T (&in)[RY],
                                             const T (&halo)[PlaneGeom<R, RY, NW>::HT], uint32_t m,
-                                            const float (&scale_in)[RY],
-                                            const float (&scale_halo)[PlaneGeom<R, RY, NW>::HT]) {
+                                            const A (&scale_in)[RY],
+                                            const A (&scale_halo)[PlaneGeom<R, RY, NW>::HT]) {
     using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-        const float v = masked<BC>(in[i], m, i);
+        const A v = masked<BC>(in[i], m, i);
         tile[(R + ty * RY + i) * G::W + R + tx] = SCALED ? v * scale_in[i] : v;
     }
 #pragma unroll
@@ -225,19 +225,19 @@ __device__ __forceinline__ void store_plane(float* __restrict__ tile, const T (&
         if (h < G::NH) {
             int ly, lx;
             halo_coord<R, RY, NW>(h, ly, lx);
-            const float v = masked<BC>(halo[j], m, RY + j);
+            const A v = masked<BC>(halo[j], m, RY + j);
             tile[ly * G::W + lx] = SCALED ? v * scale_halo[j] : v;
         }
     }
 }
 
 // Unscaled form of store_plane.
-template <int R, int RY, int BC, typename T, int NW = 4>
-__device__ __forceinline__ void store_plane(float* __restrict__ tile, const T (&in)[RY],
+template <int R, int RY, int BC, typename T, int NW = 4, typename A = float>
+__device__ __forceinline__ void store_plane(A* __restrict__ tile, const T (&in)[RY],
                                             const T (&halo)[PlaneGeom<R, RY, NW>::HT], uint32_t m) {
-    const float one[RY] = {};
-    const float oneh[PlaneGeom<R, RY, NW>::HT] = {};
-    store_plane<R, RY, BC, false, T, NW>(tile, in, halo, m, one, oneh);
+    const A one[RY] = {};
+    const A oneh[PlaneGeom<R, RY, NW>::HT] = {};
+    store_plane<R, RY, BC, false, T, NW, A>(tile, in, halo, m, one, oneh);
 }
 
 // In-plane arms of a star in difference form, sum over the x and y arms of
@@ -301,22 +301,21 @@ __device__ __forceinline__ void star_plane_iso(const float* __restrict__ tile, c
 }
 
 // In-plane star contribution (centre, x and y arms) for this thread's RY rows.
-template <int R, int RY, int NW = 4>
-__device__ __forceinline__ void star_plane(const float* __restrict__ tile, const Taps& tp,
-                                           float (&p)[RY]) {
+template <int R, int RY, int NW = 4, typename A = float>
+__device__ __forceinline__ void star_plane(const A* __restrict__ tile, const Taps& tp, A (&p)[RY]) {
     using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
-    const float* base = tile + (ty * RY) * G::W + R + tx;   // row ty*RY - R + R, column tx
-    float col[RY + 2 * R];
+    const A* base = tile + (ty * RY) * G::W + R + tx;   // row ty*RY - R + R, column tx
+    A col[RY + 2 * R];
 #pragma unroll
     for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-        float a = tp.c[0] * col[i + R];
+        A a = A(tp.c[0]) * col[i + R];
 #pragma unroll
         for (int d = 1; d <= R; ++d) {
-            a = fmaf(tp.c[star_y<R>(-d)], col[i + R - d], a);
-            a = fmaf(tp.c[star_y<R>(d)], col[i + R + d], a);
+            a = fma_acc(A(tp.c[star_y<R>(-d)]), col[i + R - d], a);
+            a = fma_acc(A(tp.c[star_y<R>(d)]), col[i + R + d], a);
         }
         p[i] = a;
     }
@@ -324,9 +323,9 @@ __device__ __forceinline__ void star_plane(const float* __restrict__ tile, const
     for (int d = 1; d <= R; ++d) {
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            const float* row = tile + (R + ty * RY + i) * G::W + R + tx;
-            p[i] = fmaf(tp.c[star_x<R>(-d)], row[-d], p[i]);
-            p[i] = fmaf(tp.c[star_x<R>(d)], row[d], p[i]);
+            const A* row = tile + (R + ty * RY + i) * G::W + R + tx;
+            p[i] = fma_acc(A(tp.c[star_x<R>(-d)]), row[-d], p[i]);
+            p[i] = fma_acc(A(tp.c[star_x<R>(d)]), row[d], p[i]);
         }
     }
 }

@@ -15,7 +15,8 @@ import torch
 from . import _abi
 from ._abi import check, lib
 
-_DTYPES = {"f32": (_abi.ST_F32, torch.float32), "f16": (_abi.ST_F16, torch.float16)}
+_DTYPES = {"f32": (_abi.ST_F32, torch.float32), "f16": (_abi.ST_F16, torch.float16),
+           "f64": (_abi.ST_F64, torch.float64)}
 _BC = {"periodic": _abi.ST_PERIODIC, "zero": _abi.ST_ZERO}
 _SHAPES = {"star": _abi.ST_STAR, "box": _abi.ST_BOX}
 

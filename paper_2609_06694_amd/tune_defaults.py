@@ -28,6 +28,11 @@ def main(out: str) -> None:
         plans.append((f"box3d r2 512^3 {dt}", st.Stencil((512, 512, 512), "box", 2, c.coeffs, dtype=dt)))
         c = wl.box2d(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
         plans.append((f"box2d 4096^2 {dt}", st.Stencil((4096, 4096), "box", 2, c.coeffs, dtype=dt)))
+    for dt in ("f16", "f32", "f64"):
+        c = wl.star3d(n=(16, 16, 16))
+        plans.append((f"star3d 512^3 {dt}", st.Stencil((512, 512, 512), "star", 1, c.coeffs, dtype=dt)))
+    c = wl.box3d(n=16, dtype=wl.F32)
+    plans.append(("box3d 512^3 f64", st.Stencil((512, 512, 512), "box", 1, c.coeffs, dtype="f64")))
     plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))
     plans.append(("wave 256^3", st.WaveModel((256, 256, 256))))
     # One representative grid per case key of the 64-grid workload; the

@@ -25,10 +25,11 @@ import numpy as np
 STAR, BOX = 0, 1
 PERIODIC, ZERO = 0, 1
 LINEAR, WAVE = 0, 1
-F32, F16 = 0, 1
+F32, F16, F64 = 0, 1, 2
 
 SHAPE_NAMES = {STAR: "star", BOX: "box"}
-DTYPE_NP = {F32: np.float32, F16: np.float16}
+DTYPE_NP = {F32: np.float32, F16: np.float16, F64: np.float64}
+DTYPE_TAGS = {F32: "f32", F16: "f16", F64: "f64"}
 
 # Seeds fixed per workload so every run and every consumer sees the same draw.
 SEED_JACOBI2D = 1
@@ -182,6 +183,17 @@ def box2d(n: int = 4096, steps: int = 100, dtype: int = F16, seed: int = SEED_BO
     u0 = _uniform(rng, 0.0, 1.0, (n, n), DTYPE_NP[dtype])
     tag = "f16" if dtype == F16 else "f32"
     return LinearCase(f"box2d_r2_{tag}", 2, (n, n, 1), BOX, 2, c, PERIODIC, steps, u0, dtype)
+
+
+def star3d(n=(512, 512, 512), r: int = 1, steps: int = 10, dtype: int = F32, seed: int = SEED_BOX + 30) -> LinearCase:
+    """A 3D star of radius r (r = 1: the 7-point star of the paper's kernel
+    matrix) on an nx x ny x nz grid; unit-sum coefficients, U[0,1) data,
+    periodic boundaries."""
+    rng = np.random.default_rng(seed)
+    c = random_unit_sum_coeffs(rng, 3, STAR, r)
+    nx, ny, nz = n
+    u0 = _uniform(rng, 0.0, 1.0, (nz, ny, nx), DTYPE_NP[dtype])
+    return LinearCase(f"star3d_r{r}_{DTYPE_TAGS[dtype]}", 3, (nx, ny, nz), STAR, r, c, PERIODIC, steps, u0, dtype)
 
 
 def box3d_r2(n: int = 512, steps: int = 10, dtype: int = F32, seed: int = SEED_BOX + 20) -> LinearCase:

@@ -71,6 +71,8 @@ def _plan(L, p, opts=None):
     (dict(ndim=3, n=(8, 8, 8), shape=1, r=3), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=1), _abi.ST_EUNSUPPORTED),
     (dict(ndim=2, n=(8, 8, 1), update=1, coeffs=None), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=2, n=(8, 8, 1), dtype=2), _abi.ST_EUNSUPPORTED),
+    (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=2), _abi.ST_EUNSUPPORTED),
 ])
 def test_plan_validation_codes(L, kw, code):
     p, keep = _prob(**kw)
@@ -205,3 +207,15 @@ def test_dispatch_cache_file_overrides_default(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=ROOT)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "128", "16", "3"]
+
+
+def test_f64_plan_uses_zmarch_with_short_tiles(L):
+    """A 3D f64 linear plan is accepted and dispatched to the z-march with
+    8- or 16-row tiles (the f64 kernels hold twice the registers)."""
+    p, keep = _prob(ndim=3, n=(64, 40, 30), shape=1, r=1, dtype=2)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK, L.stencil_last_error()
+    v, tx, ty, k, z = (ctypes.c_int32() for _ in range(5))
+    L.stencil_plan_describe(h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k), ctypes.byref(z))
+    assert v.value == _abi.ST_VARIANT_ZM3D and ty.value in (8, 16) and k.value <= 1
+    L.stencil_plan_destroy(h)

@@ -78,6 +78,19 @@ def test_fullsize_box3d(st, dtype):
     assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
 
 
+@pytest.mark.parametrize("dtype", [wl.F16, wl.F32, wl.F64])
+def test_fullsize_star3d(st, dtype):
+    """The 7-point star on 512^3 x 10 steps in each storage type."""
+    case = wl.star3d(dtype=dtype)
+    dt = wl.DTYPE_TAGS[dtype]
+    s = st.Stencil(case.n, "star", 1, case.coeffs, dtype=dt)
+    got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
+    starts = [(0, 0, 0), (505, 250, 478)]
+    e = _sample_linear(case, got, starts, (4, 6, 8))
+    print(f"star3d {dt} 512^3 x10 sampled rel-L2 {e:.2e}")
+    assert e <= {wl.F16: 2e-3, wl.F32: 1e-5, wl.F64: 1e-12}[dtype]
+
+
 @pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
 def test_fullsize_box3d_r2(st, dtype):
     """The 125-point box on 512^3 x 10 steps (the compute-bound case)."""

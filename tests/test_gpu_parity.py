@@ -16,7 +16,7 @@ from paper_2609_06694_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "f16": 2e-3}
+TOL = {"f32": 1e-5, "f16": 2e-3, "f64": 1e-12}
 
 
 def legal_depth(tx, ty, k, r, lds_bytes=64 * 1024):
@@ -107,6 +107,30 @@ def test_3d_sweep_vs_oracle(st, shape, r, dtype, bc):
         ref = oracle.sweep(u, c, shape, r, bcode, steps)
         e = rel_l2(got, ref)
         assert e <= TOL[dtype], (nx, ny, nz, ty, zc, steps, e)
+
+
+@pytest.mark.parametrize("shape,r", CASES_3D)
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_3d_f64_vs_oracle(st, shape, r, bc):
+    """f64 storage and arithmetic (the f32 coefficient values widened): all
+    3D stencils, 8- and 16-row tiles, plane chunks, ragged tails, grids
+    smaller than 2r+1, in place, and the transpose."""
+    rng = np.random.default_rng(6400 + 10 * r + shape)
+    c = wl.random_unit_sum_coeffs(rng, 3, shape, r)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    for (nx, ny, nz), (ty, zc), steps in [((70, 37, 29), (16, 0), 2), ((130, 20, 41), (8, 16), 3),
+                                          ((6, 5, 7), (16, 0), 2)]:
+        u = wl.small_random_grid(rng, 3, (nx, ny, nz), np.float64, 0.0, 1.0)
+        s = st.Stencil((nx, ny, nz), shape, r, c, dtype="f64", boundary=bc, variant=2, tile_y=ty, zchunk=zc)
+        ref = oracle.sweep(u, c, shape, r, bcode, steps)
+        got = _host(s.apply(_dev(u), steps))
+        assert got.dtype == np.float64
+        assert rel_l2(got, ref) <= TOL["f64"], (nx, ny, nz, ty, zc, steps, rel_l2(got, ref))
+        d = _dev(u)
+        s.apply(d, steps, out=d)
+        assert rel_l2(_host(d), ref) <= TOL["f64"], ("in place", nx, ny, nz)
+        refT = oracle.sweep(u, c, shape, r, bcode, steps, adjoint=True)
+        assert rel_l2(_host(s.apply_adjoint(_dev(u), steps)), refT) <= TOL["f64"], ("adjoint", nx, ny, nz)
 
 
 @pytest.mark.parametrize("shape", [wl.STAR, wl.BOX])
