@@ -50,6 +50,9 @@ def _load():
     lib.oracle_wave_gradient.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                          _dp, _dp, _dp, _i64p, _dp, ctypes.c_int64, _dp,
                                          ctypes.c_int, _dp, _dp]
+    lib.oracle_varcoef_taps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_varcoef_sweep.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _dp,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -100,6 +103,32 @@ def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, r: int, boundary: 
     fn = lib.oracle_sweep_adjoint if adjoint else lib.oracle_sweep
     _check(fn(ndim, _n3(u64.shape), shape, r, _ptr(c64), boundary, steps, _ptr(u64), _ptr(out)),
            "sweep")
+    return out
+
+
+def varcoef_taps(ndim: int, shape: int, r: int) -> int:
+    """Number of offsets of the shape (one coefficient field each)."""
+    k = int(_load().oracle_varcoef_taps(ndim, shape, r))
+    if k < 0:
+        raise ValueError("bad stencil")
+    return k
+
+
+def varcoef_sweep(u: np.ndarray, fields: np.ndarray, shape: int, r: int, boundary: int,
+                  steps: int, adjoint: bool = False) -> np.ndarray:
+    """`steps` applications of the variable-coefficient stencil (or its
+    transpose); fields[k] is the coefficient field of the k-th in-shape
+    offset in (dz,dy,dx) order, shaped like u."""
+    lib = _load()
+    u64 = _f64(u)
+    f64 = _f64(fields)
+    ndim = u64.ndim
+    nt = varcoef_taps(ndim, shape, r)
+    if f64.shape != (nt,) + u64.shape:
+        raise ValueError(f"fields must have shape {(nt,) + u64.shape}")
+    out = np.empty_like(u64)
+    _check(lib.oracle_varcoef_sweep(ndim, _n3(u64.shape), shape, r, _ptr(f64), boundary, steps,
+                                    1 if adjoint else 0, _ptr(u64), _ptr(out)), "varcoef_sweep")
     return out
 
 

@@ -150,6 +150,95 @@ int oracle_sweep_adjoint(int ndim, const int64_t n[3], int shape, int r, const d
  * stencil annihilates odd moments).  Solved by Gaussian elimination with
  * partial pivoting.  Output: w[0..r] = (w_0, w_1, ..., w_r).
  */
+/* ---- Variable coefficients (Section 2.1: a coefficient that varies in
+ * space is one more array to read).  `f` holds one field per offset of the
+ * shape, in (dz,dy,dx) lexicographic order of the in-shape offsets, each a
+ * full grid: f[k][z][y][x].
+ *   forward:   out(x) = sum_k f_k(x) in(B(x + d_k))
+ *   transpose: out(y) = sum over (x, k) with B(x + d_k) = y of f_k(x) in(x),
+ *              written as a scatter over x (zero boundary: terms whose
+ *              target lies outside are dropped). */
+static int taps_of(int ndim, int shape, int r, int (*d)[3]) {
+    const int rz = (ndim == 3) ? r : 0;
+    int k = 0;
+    for (int dz = -rz; dz <= rz; ++dz)
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+                if (!offset_in_shape(shape, dz, dy, dx)) continue;
+                if (d) { d[k][0] = dz; d[k][1] = dy; d[k][2] = dx; }
+                ++k;
+            }
+    return k;
+}
+
+int oracle_varcoef_taps(int ndim, int shape, int r) {
+    if (check_args(ndim, (const int64_t[3]){1, 1, 1}, shape, r, OR_PERIODIC)) return -1;
+    return taps_of(ndim, shape, r, NULL);
+}
+
+static void varcoef_once(int ndim, const int64_t n[3], int shape, int r, const double *f,
+                         int boundary, const double *in, double *out) {
+    int d[729][3];
+    const int nt = taps_of(ndim, shape, r, d);
+    const int64_t nz = n[2], ny = n[1], nx = n[0], cells = nx * ny * nz;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(oracle_max_threads())
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = (z * ny + y) * nx + x;
+                double acc = 0.0;
+                for (int k = 0; k < nt; ++k)
+                    acc += f[k * cells + i] * fetch(in, n, boundary, z + d[k][0], y + d[k][1], x + d[k][2]);
+                out[i] = acc;
+            }
+}
+
+static void varcoef_transpose_once(int ndim, const int64_t n[3], int shape, int r, const double *f,
+                                   int boundary, const double *in, double *out) {
+    int d[729][3];
+    const int nt = taps_of(ndim, shape, r, d);
+    const int64_t nz = n[2], ny = n[1], nx = n[0], cells = nx * ny * nz;
+    memset(out, 0, sizeof(double) * (size_t)cells);
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = (z * ny + y) * nx + x;
+                for (int k = 0; k < nt; ++k) {
+                    int64_t tz = z + d[k][0], ty = y + d[k][1], tx = x + d[k][2];
+                    if (boundary == OR_PERIODIC) {
+                        tz = wrap(tz, nz);
+                        ty = wrap(ty, ny);
+                        tx = wrap(tx, nx);
+                    } else if (tx < 0 || tx >= nx || ty < 0 || ty >= ny || tz < 0 || tz >= nz) {
+                        continue;
+                    }
+                    out[(tz * ny + ty) * nx + tx] += f[k * cells + i] * in[i];
+                }
+            }
+}
+
+int oracle_varcoef_sweep(int ndim, const int64_t n[3], int shape, int r, const double *f,
+                         int boundary, int steps, int transpose, const double *u_in, double *u_out) {
+    int e = check_args(ndim, n, shape, r, boundary);
+    if (e) return e;
+    if (r > 4) return -4;
+    if (steps < 0) return -6;
+    const int64_t cells = cells_of(n);
+    double *a = (double *)malloc(sizeof(double) * (size_t)cells);
+    double *b = (double *)malloc(sizeof(double) * (size_t)cells);
+    if (!a || !b) { free(a); free(b); return -7; }
+    memcpy(a, u_in, sizeof(double) * (size_t)cells);
+    for (int t = 0; t < steps; ++t) {
+        if (transpose) varcoef_transpose_once(ndim, n, shape, r, f, boundary, a, b);
+        else varcoef_once(ndim, n, shape, r, f, boundary, a, b);
+        double *tmp = a; a = b; b = tmp;
+    }
+    memcpy(u_out, a, sizeof(double) * (size_t)cells);
+    free(a);
+    free(b);
+    return 0;
+}
+
 int oracle_fd2_weights(int r, double *w) {
     if (r < 1 || r > 8) return -4;
     const int m = r + 1;

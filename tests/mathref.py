@@ -62,6 +62,20 @@ def operator_matrix(grid_shape, c, shape: int, r: int, boundary: int) -> np.ndar
     return M
 
 
+def varcoef_matrix(grid_shape, fields, shape: int, r: int, boundary: int) -> np.ndarray:
+    """Dense matrix of one variable-coefficient sweep: sum over the in-shape
+    offsets d_k of diag(f_k) times the Kronecker shift matrix of d_k."""
+    ndim = len(grid_shape)
+    nz, ny, nx = (1,) + tuple(grid_shape) if ndim == 2 else tuple(grid_shape)
+    size = nz * ny * nx
+    M = np.zeros((size, size))
+    for k, (dz, dy, dx) in enumerate(offsets(ndim, shape, r)):
+        Sz = shift_matrix(nz, dz, boundary) if ndim == 3 else np.eye(1)
+        S = np.kron(Sz, np.kron(shift_matrix(ny, dy, boundary), shift_matrix(nx, dx, boundary)))
+        M += np.asarray(fields[k], dtype=np.float64).reshape(size)[:, None] * S
+    return M
+
+
 def laplacian_dense_fd8() -> np.ndarray:
     """Dense 9^3 star array of the 3D eighth-order Laplacian from FD8."""
     r = 4

@@ -323,3 +323,58 @@ def test_oracle_rejects_bad_arguments(oracle_lib):
         oracle_lib.sweep(u, np.zeros(9), BOX, 1, 5, 1)           # bad boundary
     with pytest.raises(ValueError):
         oracle_lib.sweep(u, np.zeros(25), BOX, 1, PERIODIC, 1)   # wrong coefficient count
+
+
+# ---- variable coefficients -------------------------------------------------
+VC_CASES = [(2, (5, 7), STAR, 1), (2, (6, 5), BOX, 2), (3, (4, 5, 6), STAR, 1), (3, (5, 4, 3), BOX, 1),
+            (3, (3, 4, 9), STAR, 4), (3, (6, 5, 7), STAR, 2)]
+
+
+@pytest.mark.parametrize("boundary", [PERIODIC, ZERO])
+@pytest.mark.parametrize("ndim,shape_,kind,r", VC_CASES)
+def test_varcoef_matches_brute_force_matrix(oracle_lib, ndim, shape_, kind, r, boundary):
+    """Forward and transpose against sum_k diag(f_k) S_k built from Kronecker
+    shift matrices (grids smaller than 2r+1 included)."""
+    rng = np.random.default_rng(hash(("vc", ndim, shape_, kind, r, boundary)) % 2**32)
+    nt = len(mr.offsets(ndim, kind, r))
+    f = rng.uniform(-1, 1, (nt,) + shape_)
+    u = rng.standard_normal(shape_)
+    M = mr.varcoef_matrix(shape_, f, kind, r, boundary)
+    steps = 3
+    ref = np.linalg.matrix_power(M, steps) @ u.ravel()
+    got = oracle_lib.varcoef_sweep(u, f, kind, r, boundary, steps)
+    assert np.max(np.abs(got.ravel() - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    refT = np.linalg.matrix_power(M.T, steps) @ u.ravel()
+    gotT = oracle_lib.varcoef_sweep(u, f, kind, r, boundary, steps, adjoint=True)
+    assert np.max(np.abs(gotT.ravel() - refT)) <= 1e-12 * max(1.0, np.max(np.abs(refT)))
+
+
+@pytest.mark.parametrize("ndim,kind,r,n", [(3, STAR, 1, (9, 8, 10)), (3, BOX, 1, (6, 7, 5)),
+                                           (2, STAR, 3, (11, 12)), (3, STAR, 4, (10, 9, 11))])
+@pytest.mark.parametrize("boundary", [PERIODIC, ZERO])
+def test_varcoef_constant_fields_reduce_to_constant_sweep(oracle_lib, ndim, kind, r, n, boundary):
+    """Fields that are constant in space give the constant-coefficient sweep."""
+    rng = np.random.default_rng(23)
+    c = _rand_coeffs(rng, ndim, kind, r)
+    offs = mr.offsets(ndim, kind, r)
+    f = np.stack([np.full(n, mr.coeff_at(c, ndim, r, *d)) for d in offs])
+    u = rng.standard_normal(n)
+    got = oracle_lib.varcoef_sweep(u, f, kind, r, boundary, 4)
+    want = oracle_lib.sweep(u, c, kind, r, boundary, 4)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("ndim,kind,r", [(3, STAR, 2), (3, BOX, 1), (2, BOX, 2)])
+def test_varcoef_transpose_column_sums(oracle_lib, ndim, kind, r):
+    """Periodic transpose: every scattered term lands in the grid, so
+    sum(A^T v) = sum_x (sum_k f_k(x)) v(x); and <Au, v> = <u, A^T v>."""
+    rng = np.random.default_rng(31)
+    n = (13, 11, 12) if ndim == 3 else (17, 15)
+    nt = len(mr.offsets(ndim, kind, r))
+    f = rng.uniform(-1, 1, (nt,) + n)
+    u = rng.standard_normal(n)
+    v = rng.standard_normal(n)
+    ATv = oracle_lib.varcoef_sweep(v, f, kind, r, PERIODIC, 1, adjoint=True)
+    assert abs(ATv.sum() - (f.sum(axis=0) * v).sum()) <= 1e-11 * np.abs(f).sum()
+    Au = oracle_lib.varcoef_sweep(u, f, kind, r, PERIODIC, 1)
+    assert abs(np.vdot(Au, v) - np.vdot(u, ATv)) <= 1e-12 * np.linalg.norm(Au) * np.linalg.norm(v)
