@@ -221,6 +221,25 @@ def bench_linear(dev, st, wl, torch, case, reps=3):
             "dispatch": s.describe()}
 
 
+def bench_varcoef(dev, st, torch, shape, r, n=512, steps=10):
+    """Variable-coefficient sweep (f32, periodic) on n^3; fields and data are
+    seeded device-side uniform draws, fields normalised per cell."""
+    ntap = st.varcoef_taps(3, shape, r)
+    g = torch.Generator(device=dev)
+    g.manual_seed(99 + ntap)
+    f = torch.rand((ntap, n, n, n), generator=g, device=dev)
+    f /= f.sum(dim=0, keepdim=True)
+    u = torch.rand((n, n, n), generator=g, device=dev)
+    out = torch.empty_like(u)
+    s = st.VarCoefStencil((n, n, n), shape, r)
+    ms = timed(lambda: s.apply(u, f, steps, out=out), 3, 1, torch.cuda.synchronize)
+    gc = gcells(n ** 3, steps, ms)
+    bpc = (ntap + 2) * 4
+    return {"workload": f"varcoef_{shape}{r}_f32_{n}^3_{steps}steps", "ms": ms, "gcells_s": gc,
+            "bytes_per_cell_update": bpc, "eff_gbs": gc * bpc, "hbm_frac": gc * bpc / HBM_PEAK_GBS,
+            "dispatch": s.describe()}
+
+
 # Cubes of the paper's kernel matrix and slab stand-ins (its slab sizes are
 # not given): thin in z, thin in y, and a long narrow column.
 SHAPES = [("cube128", (128, 128, 128)), ("cube256", (256, 256, 256)), ("cube512", (512, 512, 512)),
@@ -363,6 +382,8 @@ def main():
             ("star3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F16))),
             ("star3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F32))),
             ("star3d_f64", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F64))),
+            ("varcoef_star1", lambda: bench_varcoef(dev, st, torch, "star", 1)),
+            ("varcoef_box1", lambda: bench_varcoef(dev, st, torch, "box", 1)),
             ("box3d_r2_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16))),
             ("box3d_r2_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F32))),
             ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),

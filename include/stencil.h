@@ -63,11 +63,15 @@ typedef enum { ST_F32 = 0, ST_F16 = 1, ST_F64 = 2 } st_dtype;
 typedef enum { ST_PERIODIC = 0, ST_ZERO = 1 } st_boundary;
 typedef enum { ST_STAR = 0, ST_BOX = 1 } st_shape;
 
-/* ST_LINEAR: the weighted-sum sweep above.
- * ST_WAVE:   acoustic leapfrog u_{t+1} = 2 u_t - u_{t-1} + kappa (.) L(u_t),
- *            L a star stencil, kappa a per-cell coefficient field (Section
- *            2.1: a spatially varying coefficient is one more array to read). */
-typedef enum { ST_LINEAR = 0, ST_WAVE = 1 } st_update;
+/* ST_LINEAR:  the weighted-sum sweep above.
+ * ST_WAVE:    acoustic leapfrog u_{t+1} = 2 u_t - u_{t-1} + kappa (.) L(u_t),
+ *             L a star stencil, kappa a per-cell coefficient field (Section
+ *             2.1: a spatially varying coefficient is one more array to read).
+ * ST_VARCOEF: the sweep with one coefficient field per offset,
+ *             u'(x) = sum_k f_k(x) u(B(x + d_k)) (Section 2.1, variable
+ *             coefficients); applied by stencil_apply_varcoef.  3D, star
+ *             r = 1..4 or box r = 1; `coeffs` is ignored (may be NULL). */
+typedef enum { ST_LINEAR = 0, ST_WAVE = 1, ST_VARCOEF = 2 } st_update;
 
 /* Kernel families a dispatch-map entry can name. */
 typedef enum {
@@ -77,7 +81,8 @@ typedef enum {
     ST_VARIANT_WAVE3D = 3, /* 3D leapfrog z-march, fused source/receiver */
     ST_VARIANT_WAVE3D_LDS = 4, /* 3D leapfrog forward with z-neighbours in an LDS ring */
     ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
-    ST_VARIANT_ZM3D_MFMA = 6 /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
+    ST_VARIANT_ZM3D_MFMA = 6, /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
+    ST_VARIANT_VC3D = 7   /* 3D variable-coefficient z-march (ST_VARCOEF plans) */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */
@@ -161,6 +166,26 @@ st_status stencil_apply(const st_plan *plan, const void *u_in, void *u_out, int3
 st_status stencil_apply_adjoint(const st_plan *plan, const void *v_in, void *v_out,
                                 int32_t steps, const st_wave_args *wave, void *workspace,
                                 size_t ws_bytes, void *stream);
+
+/* Variable-coefficient sweep of an ST_VARCOEF plan, `steps` time steps:
+ *   u_out = A^steps u_in,   (A u)(x) = sum_k f_k(x) u(B(x + d_k)).
+ * `fields` (device, read only) holds one coefficient field per offset d_k of
+ * the plan's shape, taken in (dz,dy,dx) lexicographic order of the in-shape
+ * offsets (a star of radius r has 1 + 6r, the radius-1 box 27), each a full
+ * [nz][ny][nx] grid of the plan's storage type, stored one after another.
+ * `fields` must not overlap u_in, u_out or the workspace.
+ * Buffer rules, workspace (mode 0) and steps == 0 as for stencil_apply.
+ * A plan of another update kind returns ST_EINVAL. */
+st_status stencil_apply_varcoef(const st_plan *plan, const void *u_in, void *u_out, const void *fields,
+                                int32_t steps, void *workspace, size_t ws_bytes, void *stream);
+
+/* Its transpose: v_out = (A^T)^steps v_in,
+ *   (A^T v)(y) = sum_k f_k(y - d_k) v(B(y - d_k))   (periodic: y - d_k wraps;
+ *   zero frame: terms with y - d_k outside the grid vanish).
+ * Same arguments and rules as stencil_apply_varcoef. */
+st_status stencil_apply_varcoef_adjoint(const st_plan *plan, const void *v_in, void *v_out,
+                                        const void *fields, int32_t steps, void *workspace,
+                                        size_t ws_bytes, void *stream);
 
 /* Gradient of J = 1/2 sum_{t=1..T} || u_t[z = rec_z] - target[t-1] ||^2 with
  * respect to kappa for an ST_WAVE plan, by the discrete adjoint of the

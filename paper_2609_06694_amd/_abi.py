@@ -19,15 +19,17 @@ STATUS_NAMES = {0: "ST_OK", 1: "ST_EINVAL", 2: "ST_ESHAPE", 3: "ST_EUNSUPPORTED"
 ST_F32, ST_F16, ST_F64 = 0, 1, 2
 ST_PERIODIC, ST_ZERO = 0, 1
 ST_STAR, ST_BOX = 0, 1
-ST_LINEAR, ST_WAVE = 0, 1
+ST_LINEAR, ST_WAVE, ST_VARCOEF = 0, 1, 2
 ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D, ST_VARIANT_WAVE3D_LDS = 0, 1, 2, 3, 4
 ST_VARIANT_YM2D = 5
 ST_VARIANT_ZM3D_MFMA = 6
-VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma"}
+VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma",
+                 7: "vc3d"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",
             "stencil_plan_describe", "stencil_apply", "stencil_apply_adjoint",
+            "stencil_apply_varcoef", "stencil_apply_varcoef_adjoint",
             "stencil_wave_gradient", "stencil_plan_batched", "stencil_apply_batched",
             "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version"]
 
@@ -82,6 +84,10 @@ def lib():
     L.stencil_apply.restype = ctypes.c_int
     L.stencil_apply_adjoint.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P, sz, P]
     L.stencil_apply_adjoint.restype = ctypes.c_int
+    L.stencil_apply_varcoef.argtypes = [P, P, P, P, i32, P, sz, P]
+    L.stencil_apply_varcoef.restype = ctypes.c_int
+    L.stencil_apply_varcoef_adjoint.argtypes = [P, P, P, P, i32, P, sz, P]
+    L.stencil_apply_varcoef_adjoint.restype = ctypes.c_int
     L.stencil_wave_gradient.argtypes = [P, P, ctypes.POINTER(StWaveArgs), i32, P, P, P, sz, P]
     L.stencil_wave_gradient.restype = ctypes.c_int
     L.stencil_plan_batched.argtypes = [ctypes.POINTER(StProblem), i32, ctypes.POINTER(StPlanOpts),

@@ -426,6 +426,10 @@ st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, v
     }
     hipStream_t s = (hipStream_t)stream;
     TuneStats st;
+    if (!plan->batched && plan->prob.update == ST_VARCOEF) {
+        set_error("variable-coefficient plans are not autotuned (the dispatch map's entry is used)");
+        return ST_EUNSUPPORTED;
+    }
     if (!plan->batched) {
         st_status r = tune_one(plan, (char*)scratch, scratch_bytes, s, st);
         plan->tune_tried = st.tried;

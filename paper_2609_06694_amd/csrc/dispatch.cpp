@@ -79,7 +79,7 @@ std::string key_string(const CaseKey& k) {
     char buf[128];
     snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
              k.r, k.dtype == 0 ? "f32" : (k.dtype == 1 ? "f16" : "f64"), k.boundary == kPeriodic ? "periodic" : "zero",
-             k.update == 0 ? "linear" : "wave", k.size_class, k.slab ? " slab" : "");
+             k.update == 0 ? "linear" : (k.update == 1 ? "wave" : "varcoef"), k.size_class, k.slab ? " slab" : "");
     return buf;
 }
 
@@ -89,6 +89,12 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.variant = ST_VARIANT_WAVE3D_LDS;
         c.tile_y = 32;
         c.tsteps = 1;
+        c.zchunk = kAutoChunk;
+        return c;
+    }
+    if (k.update == ST_VARCOEF) {
+        c.variant = ST_VARIANT_VC3D;
+        c.tile_y = k.shape == kStar && k.r == 1 ? 16 : 8;
         c.zchunk = kAutoChunk;
         return c;
     }
@@ -254,6 +260,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }
+    if (p.update == ST_VARCOEF)
+        return c.variant == ST_VARIANT_VC3D && (c.tile_y == 8 || (c.tile_y == 16 && p.shape == ST_STAR && p.radius == 1)) &&
+               c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 1;
     if (p.ndim == 3) {
         if (c.variant == ST_VARIANT_ZM3D_MFMA)
             return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 8 == 0 &&

@@ -90,6 +90,11 @@ bool zm3d_mfma_supported(const Geom& g);
 hipError_t launch_zm3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                            void* out, hipStream_t stream);
 bool zm3d_tb2_supported(int r, int shape);
+// One variable-coefficient step (adjoint = the transpose); fields as in
+// stencil_apply_varcoef.
+hipError_t launch_vc3d(const Geom& g, const LaunchCfg& cfg, const void* in, void* out, const void* fields,
+                       bool adjoint, hipStream_t stream);
+bool vc3d_supported(int r, int shape);
 
 // One launch of a 3D linear sweep (k = 1 or 2 fused steps) through the
 // kernel family the configuration names.

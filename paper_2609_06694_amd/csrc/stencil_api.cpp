@@ -104,7 +104,8 @@ st_status validate(const st_problem* p) {
         ST_FAIL(ST_EINVAL, "unknown dtype %d", p->dtype);
     if (p->boundary != ST_PERIODIC && p->boundary != ST_ZERO)
         ST_FAIL(ST_EINVAL, "unknown boundary %d", p->boundary);
-    if (p->update != ST_LINEAR && p->update != ST_WAVE) ST_FAIL(ST_EINVAL, "unknown update %d", p->update);
+    if (p->update != ST_LINEAR && p->update != ST_WAVE && p->update != ST_VARCOEF)
+        ST_FAIL(ST_EINVAL, "unknown update %d", p->update);
     if (p->radius < 1 || p->radius > 4) ST_FAIL(ST_EINVAL, "radius must be 1..4 (got %d)", p->radius);
     for (int a = 0; a < 3; ++a)
         if (p->n[a] < 1 || p->n[a] > kMaxExtent)
@@ -114,7 +115,12 @@ st_status validate(const st_problem* p) {
         ST_FAIL(ST_ESHAPE, "grid has more than 2^36 cells");
     if ((double)p->n[0] * (double)p->n[1] > 2147483647.0)
         ST_FAIL(ST_ESHAPE, "one plane must hold fewer than 2^31 cells");
-    if (p->update == ST_WAVE) {
+    if (p->update == ST_VARCOEF) {
+        if (p->ndim != 3) ST_FAIL(ST_EUNSUPPORTED, "variable coefficients are provided for 3D sweeps");
+        if (!vc3d_supported(p->radius, p->shape))
+            ST_FAIL(ST_EUNSUPPORTED, "variable-coefficient %s r=%d is not provided",
+                    p->shape == ST_STAR ? "star" : "box", p->radius);
+    } else if (p->update == ST_WAVE) {
         if (p->ndim != 3 || p->shape != ST_STAR)
             ST_FAIL(ST_EUNSUPPORTED, "the wave update needs a 3D star stencil");
         if (p->dtype != ST_F32) ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 storage");
@@ -128,7 +134,7 @@ st_status validate(const st_problem* p) {
             ST_FAIL(ST_EUNSUPPORTED, "3D %s r=%d is not provided", p->shape == ST_STAR ? "star" : "box",
                     p->radius);
     }
-    if (p->coeffs) {
+    if (p->coeffs && p->update != ST_VARCOEF) {
         const int w = 2 * p->radius + 1;
         const int count = p->ndim == 3 ? w * w * w : w * w;
         for (int i = 0; i < count; ++i) {
@@ -149,7 +155,8 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
     pl->prob.coeffs = nullptr;
     const int w = 2 * p->radius + 1;
     const int count = p->ndim == 3 ? w * w * w : w * w;
-    if (p->coeffs) pl->dense.assign(p->coeffs, p->coeffs + count);
+    if (p->update == ST_VARCOEF) pl->dense.assign(count, 0.f);   // the fields carry the weights
+    else if (p->coeffs) pl->dense.assign(p->coeffs, p->coeffs + count);
     else builtin_laplacian(p->radius, pl->dense);
     std::vector<float> flipped(pl->dense.rbegin(), pl->dense.rend());
     pl->taps = pack_taps(p->ndim, p->shape, p->radius, pl->dense);
@@ -483,8 +490,56 @@ st_status stencil_apply(const st_plan* plan, const void* u_in, void* u_out, int3
             ST_FAIL(ST_EINVAL, "wave->u_prev must not alias u_in or u_out");
         return run_wave(plan, false, u_in, u_out, steps, wave, workspace, ws_bytes, as_stream(stream));
     }
+    if (plan->prob.update == ST_VARCOEF) ST_FAIL(ST_EINVAL, "variable-coefficient plan: use stencil_apply_varcoef");
     if (wave) ST_FAIL(ST_EINVAL, "linear plan takes no wave arguments");
     return run_linear(plan, plan->taps, u_in, u_out, steps, workspace, ws_bytes, as_stream(stream));
+}
+
+namespace {
+// `steps` variable-coefficient steps from u_in into u_out through the
+// workspace, with run_linear's buffer schedule (one step per launch).
+st_status run_varcoef(const st_plan* pl, bool adjoint, const void* u_in, void* u_out, const void* fields,
+                      int steps, void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t gb = grid_bytes(pl->prob);
+    if (steps == 0) {
+        if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
+    const Geom g = geom_of(pl->prob);
+    const void* cur = u_in;
+    if (u_in == u_out && (steps % 2) == 1) {
+        HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
+        cur = ws;
+    }
+    for (int j = 1; j <= steps; ++j) {
+        void* dst = ((steps - j) % 2 == 0) ? u_out : ws;
+        HIP_TRY(launch_vc3d(g, pl->cfg, cur, dst, fields, adjoint, s));
+        cur = dst;
+    }
+    return ST_OK;
+}
+
+st_status varcoef_entry(const st_plan* plan, bool adjoint, const void* u_in, void* u_out, const void* fields,
+                        int32_t steps, void* workspace, size_t ws_bytes, void* stream) {
+    stk::set_error("%s", "");
+    if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
+    if (plan->batched || plan->prob.update != ST_VARCOEF)
+        ST_FAIL(ST_EINVAL, "stencil_apply_varcoef needs an ST_VARCOEF plan");
+    if (!u_in || !u_out || !fields) ST_FAIL(ST_EINVAL, "grid or field pointer is NULL");
+    if (steps < 0) ST_FAIL(ST_EINVAL, "steps must be >= 0");
+    return run_varcoef(plan, adjoint, u_in, u_out, fields, steps, workspace, ws_bytes, as_stream(stream));
+}
+}  // namespace
+
+st_status stencil_apply_varcoef(const st_plan* plan, const void* u_in, void* u_out, const void* fields,
+                                int32_t steps, void* workspace, size_t ws_bytes, void* stream) {
+    return varcoef_entry(plan, false, u_in, u_out, fields, steps, workspace, ws_bytes, stream);
+}
+
+st_status stencil_apply_varcoef_adjoint(const st_plan* plan, const void* v_in, void* v_out, const void* fields,
+                                        int32_t steps, void* workspace, size_t ws_bytes, void* stream) {
+    return varcoef_entry(plan, true, v_in, v_out, fields, steps, workspace, ws_bytes, stream);
 }
 
 st_status stencil_apply_adjoint(const st_plan* plan, const void* v_in, void* v_out, int32_t steps,
@@ -502,6 +557,8 @@ st_status stencil_apply_adjoint(const st_plan* plan, const void* v_in, void* v_o
             ST_FAIL(ST_EINVAL, "wave->u_prev must not alias v_in or v_out");
         return run_wave(plan, true, v_in, v_out, steps, wave, workspace, ws_bytes, as_stream(stream));
     }
+    if (plan->prob.update == ST_VARCOEF)
+        ST_FAIL(ST_EINVAL, "variable-coefficient plan: use stencil_apply_varcoef_adjoint");
     if (wave) ST_FAIL(ST_EINVAL, "linear plan takes no wave arguments");
     return run_linear(plan, plan->taps_t, v_in, v_out, steps, workspace, ws_bytes, as_stream(stream));
 }

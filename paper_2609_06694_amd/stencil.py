@@ -148,6 +148,61 @@ class Stencil(_Plan):
         return self._run(lib().stencil_apply_adjoint, v, steps, out, stream)
 
 
+def varcoef_taps(ndim: int, shape, radius: int) -> int:
+    """Number of coefficient fields of a variable-coefficient stencil: one
+    per offset of the shape."""
+    s = _enum(_SHAPES, shape)
+    return (2 * radius + 1) ** ndim if s == _abi.ST_BOX else 1 + 2 * ndim * radius
+
+
+class VarCoefStencil(_Plan):
+    """The sweep u <- sum_k f_k(x) u(B(x + d_k)) with one coefficient field
+    per offset d_k of the shape ((dz,dy,dx) order of the in-shape offsets).
+    `fields` is a device tensor of shape (taps, nz, ny, nx) in the storage
+    type."""
+
+    def __init__(self, n: Sequence[int], shape, radius: int, dtype: str = "f32", boundary="periodic", **opts):
+        super().__init__()
+        self.n = tuple(int(v) for v in n)
+        self.ndim = len(self.n)
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
+        keep: list = []
+        prob = _problem(self.ndim, self.n, _enum(_SHAPES, shape), radius, None, self.dtype_code,
+                        _enum(_BC, boundary), _abi.ST_VARCOEF, keep)
+        o = _opts(**opts) if opts else None
+        check(lib().stencil_plan(ctypes.byref(prob), ctypes.byref(o) if o is not None else None,
+                                 ctypes.byref(self._h)))
+        self.grid_shape = tuple(reversed(self.n))
+        self.taps = varcoef_taps(self.ndim, shape, radius)
+        self._ws: Optional[_Workspace] = None
+
+    def _check(self, t: torch.Tensor, name: str, shape):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != self.torch_dtype or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.torch_dtype} tensor of shape {shape}")
+
+    def _run(self, fn, u, fields, steps, out, stream):
+        self._check(u, "u", self.grid_shape)
+        self._check(fields, "fields", (self.taps,) + self.grid_shape)
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(out, "out", self.grid_shape)
+        if self._ws is None:
+            self._ws = _Workspace(u.device)
+        ws, nb = self._ws.get(self.workspace_bytes(steps))
+        check(fn(self._h, _ptr(u), _ptr(out), _ptr(fields), int(steps), ws, nb, _stream_ptr(stream)))
+        return out
+
+    def apply(self, u: torch.Tensor, fields: torch.Tensor, steps: int, out: Optional[torch.Tensor] = None,
+              stream=None):
+        return self._run(lib().stencil_apply_varcoef, u, fields, steps, out, stream)
+
+    def apply_adjoint(self, v: torch.Tensor, fields: torch.Tensor, steps: int,
+                      out: Optional[torch.Tensor] = None, stream=None):
+        return self._run(lib().stencil_apply_varcoef_adjoint, v, fields, steps, out, stream)
+
+
 class _SweepFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, stencil: Stencil, steps: int):

@@ -264,6 +264,16 @@ def wavegrad3d(n: int = 256, steps: int = 200, seed: int = SEED_WAVEGRAD,
                     target=None, kappa_true=kappa_true, ckpt_every=ckpt_every)
 
 
+def varcoef_fields(rng: np.random.Generator, taps: int, grid_shape, dtype=np.float32) -> np.ndarray:
+    """Coefficient fields of a variable-coefficient stencil: per cell, taps
+    draws U[0,1) normalised by their FP64 sum (a cell-wise unit-sum average,
+    so repeated sweeps stay bounded), rounded to the storage type.  Shape
+    (taps,) + grid_shape."""
+    f = rng.random((taps,) + tuple(grid_shape))
+    f /= f.sum(axis=0, keepdims=True)
+    return f.astype(dtype)
+
+
 def small_random_grid(rng: np.random.Generator, ndim: int, n, dtype=np.float32, lo=-1.0, hi=1.0):
     """Small grid for parity tests: U[lo,hi) rounded to dtype."""
     return _uniform(rng, lo, hi, _grid_shape(ndim, n), dtype)

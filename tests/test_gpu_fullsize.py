@@ -91,6 +91,36 @@ def test_fullsize_star3d(st, dtype):
     assert e <= {wl.F16: 2e-3, wl.F32: 1e-5, wl.F64: 1e-12}[dtype]
 
 
+@pytest.mark.parametrize("shape,r", [("star", 1), ("box", 1)])
+def test_fullsize_varcoef(st, shape, r):
+    """Variable coefficients on 512^3 x 6 steps (f32, periodic); fields and
+    data are seeded device-side draws (cell-wise unit-sum fields), sampled
+    blocks are checked against the oracle on their dependency sub-box."""
+    n, steps = 512, 6
+    ntap = st.varcoef_taps(3, shape, r)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242 + ntap)
+    f = torch.rand((ntap, n, n, n), generator=g, device="cuda")
+    f /= f.sum(dim=0, keepdim=True)
+    u = torch.rand((n, n, n), generator=g, device="cuda")
+    s = st.VarCoefStencil((n, n, n), shape, r)
+    got = s.apply(u, f, steps).cpu().numpy()
+    kind = wl.STAR if shape == "star" else wl.BOX
+    m = r * steps
+    errs = []
+    for s0, blk in [((0, 0, 0), (4, 6, 8)), ((509, 250, 478), (3, 6, 8))]:
+        idx = [torch.arange(a - m, a + b + m, device="cuda") % n for a, b in zip(s0, blk)]
+        zz, yy, xx = torch.meshgrid(*idx, indexing="ij")
+        usub = u[zz, yy, xx].cpu().numpy()
+        fsub = f[:, zz, yy, xx].cpu().numpy()
+        ref = oracle.varcoef_sweep(usub, fsub, kind, r, wl.ZERO, steps)
+        ref = ref[m:m + blk[0], m:m + blk[1], m:m + blk[2]]
+        gb = got[np.ix_(*[np.arange(a, a + b) % n for a, b in zip(s0, blk)])]
+        errs.append(rel_l2(gb.astype(np.float64), ref))
+    print(f"varcoef {shape}{r} 512^3 x{steps} sampled rel-L2 {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+
+
 @pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
 def test_fullsize_box3d_r2(st, dtype):
     """The 125-point box on 512^3 x 10 steps (the compute-bound case)."""
