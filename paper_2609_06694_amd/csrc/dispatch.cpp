@@ -224,6 +224,7 @@ static int resident_wgs(const st_problem& p, const LaunchCfg& c) {
         return c.tile_y >= 32 ? 1 : (c.tile_y >= 16 ? 2 : 3);
     if (p.update == ST_WAVE) return c.tile_y >= 32 ? 1 : 2;   // adjoint/gradient: ~2 waves per SIMD
     if (c.variant == ST_VARIANT_ZM3D_MFMA) return 2;
+    if (c.variant == ST_VARIANT_VC3D) return 2;   // measured: fewer, longer marches stream best
     return 4;
 }
 
