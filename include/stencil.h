@@ -69,8 +69,8 @@ typedef enum { ST_STAR = 0, ST_BOX = 1 } st_shape;
  *             2.1: a spatially varying coefficient is one more array to read).
  * ST_VARCOEF: the sweep with one coefficient field per offset,
  *             u'(x) = sum_k f_k(x) u(B(x + d_k)) (Section 2.1, variable
- *             coefficients); applied by stencil_apply_varcoef.  3D, star
- *             r = 1..4 or box r = 1; `coeffs` is ignored (may be NULL). */
+ *             coefficients); applied by stencil_apply_varcoef.  2D or 3D,
+ *             star r = 1..4 or box r = 1; `coeffs` is ignored (may be NULL). */
 typedef enum { ST_LINEAR = 0, ST_WAVE = 1, ST_VARCOEF = 2 } st_update;
 
 /* Kernel families a dispatch-map entry can name. */
@@ -82,7 +82,7 @@ typedef enum {
     ST_VARIANT_WAVE3D_LDS = 4, /* 3D leapfrog forward with z-neighbours in an LDS ring */
     ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
     ST_VARIANT_ZM3D_MFMA = 6, /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
-    ST_VARIANT_VC3D = 7   /* 3D variable-coefficient z-march (ST_VARCOEF plans) */
+    ST_VARIANT_VC3D = 7   /* variable-coefficient plane march (ST_VARCOEF plans, 2D and 3D) */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */
@@ -171,8 +171,9 @@ st_status stencil_apply_adjoint(const st_plan *plan, const void *v_in, void *v_o
  *   u_out = A^steps u_in,   (A u)(x) = sum_k f_k(x) u(B(x + d_k)).
  * `fields` (device, read only) holds one coefficient field per offset d_k of
  * the plan's shape, taken in (dz,dy,dx) lexicographic order of the in-shape
- * offsets (a star of radius r has 1 + 6r, the radius-1 box 27), each a full
- * [nz][ny][nx] grid of the plan's storage type, stored one after another.
+ * offsets (a star of radius r has 1 + 2*ndim*r, the radius-1 box 3^ndim),
+ * each a full [nz][ny][nx] grid of the plan's storage type, stored one after
+ * another.
  * `fields` must not overlap u_in, u_out or the workspace.
  * Buffer rules, workspace (mode 0) and steps == 0 as for stencil_apply.
  * A plan of another update kind returns ST_EINVAL. */

@@ -1,10 +1,11 @@
-// 3D sweep with variable coefficients (Section 2.1: a coefficient that
-// varies in space is one more array to read):
+// 2D and 3D sweeps with variable coefficients (Section 2.1: a coefficient
+// that varies in space is one more array to read):
 //   forward    out(x) = sum_k f_k(x)       in(B(x + d_k))
 //   transpose  out(y) = sum_k f_k(y - d_k) in(B(y - d_k))
 // f_k is the field of the k-th offset of the shape in (dz,dy,dx) order.
 //
-// A workgroup owns a 64 x 4*RY column of cells and marches z.  Every input
+// A workgroup owns a 64 x 4*RY column of cells and marches z (a 2D grid is
+// one plane: the march has no z halo).  Every input
 // plane is staged once in LDS with its halo into a ring of 2R+2 tiles (2R+1
 // planes in use, one being written, so one barrier per plane suffices); when
 // plane zo+R has arrived, output plane zo is formed from the ring and from
@@ -18,14 +19,15 @@ namespace stk {
 
 namespace {
 
-// Offsets of a shape in (dz,dy,dx) lexicographic order.
-template <int SHAPE, int R>
+// Offsets of a shape in (dz,dy,dx) lexicographic order (dz = 0 in 2D).
+template <int SHAPE, int R, int NDIM>
 struct VcOffsets {
-    static constexpr int N = SHAPE == kBox ? (2 * R + 1) * (2 * R + 1) * (2 * R + 1) : 1 + 6 * R;
+    static constexpr int RZ = NDIM == 3 ? R : 0;
+    static constexpr int N = SHAPE == kBox ? (2 * R + 1) * (2 * R + 1) * (2 * RZ + 1) : 1 + 2 * NDIM * R;
     int d[N][3];
     constexpr VcOffsets() : d{} {
         int k = 0;
-        for (int dz = -R; dz <= R; ++dz)
+        for (int dz = -RZ; dz <= RZ; ++dz)
             for (int dy = -R; dy <= R; ++dy)
                 for (int dx = -R; dx <= R; ++dx)
                     if (SHAPE == kBox || (dz != 0) + (dy != 0) + (dx != 0) <= 1) {
@@ -39,15 +41,16 @@ struct VcOffsets {
 
 }  // namespace
 
-template <int R, int SHAPE, typename T, int BC, int RY, int NW, bool ADJ>
+template <int R, int SHAPE, typename T, int BC, int RY, int NW, bool ADJ, int NDIM>
 __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                           const T* __restrict__ f, int nx, int ny, int nz,
                                                           int zc, int tiles_x, int tiles_y) {
     using G = PlaneGeom<R, RY, NW>;
     using A = acc_t<T>;
-    constexpr VcOffsets<SHAPE, R> kOff{};
-    constexpr int NTAP = VcOffsets<SHAPE, R>::N;
-    constexpr int NR = 2 * R + 2;
+    constexpr VcOffsets<SHAPE, R, NDIM> kOff{};
+    constexpr int NTAP = VcOffsets<SHAPE, R, NDIM>::N;
+    constexpr int RZ = VcOffsets<SHAPE, R, NDIM>::RZ;   // z reach
+    constexpr int NR = 2 * RZ + 2;
     __shared__ A ring[NR][G::H * G::W];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int txi = b % tiles_x;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
     const int gx = x0 + tx;
     const size_t plane_sz = (size_t)nx * ny;
     const size_t cells = plane_sz * nz;
-    const int zbeg = z0 - R, zend = z1 + R;
+    const int zbeg = z0 - RZ, zend = z1 + RZ;
     const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, T, NW>(nx, ny, x0, y0);
 
     // Coefficients of one output plane, loaded one plane ahead (streamed
@@ -106,13 +109,13 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
         vm = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + 1, zend - 1), pidx, vin, vhalo);
         __syncthreads();
 
-        const int zo = zp - R;
+        const int zo = zp - RZ;
         if (zo >= z0) {
-            // ring slot of plane zo + s (|s| <= R): slot - R + s, modulo NR
-            int sl[2 * R + 1];
+            // ring slot of plane zo + s (|s| <= RZ): slot - RZ + s, modulo NR
+            int sl[2 * RZ + 1];
 #pragma unroll
-            for (int s = 0; s <= 2 * R; ++s) {
-                const int v = slot - 2 * R + s;
+            for (int s = 0; s <= 2 * RZ; ++s) {
+                const int v = slot - 2 * RZ + s;
                 sl[s] = v < 0 ? v + NR : v;
             }
             A acc[RY];
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
                 const int sz = ADJ ? -kOff.d[k][0] : kOff.d[k][0];
                 const int sy = ADJ ? -kOff.d[k][1] : kOff.d[k][1];
                 const int sx = ADJ ? -kOff.d[k][2] : kOff.d[k][2];
-                const A* t = ring[sl[R + sz]] + (R + ty * RY + sy) * G::W + R + tx + sx;
+                const A* t = ring[sl[RZ + sz]] + (R + ty * RY + sy) * G::W + R + tx + sx;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) acc[i] = fma_acc(to_acc<T>(cv[k][i]), t[i * G::W], acc[i]);
             }
@@ -149,7 +152,13 @@ static hipError_t go(const Geom& g, int zc, const void* in, void* out, const voi
     using G = PlaneGeom<R, RY, NW>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
-    hipLaunchKernelGGL((vc3d_kernel<R, SHAPE, T, BC, RY, NW, ADJ>), dim3(tiles_x * tiles_y * nchunks),
+    if (g.ndim == 2) {
+        hipLaunchKernelGGL((vc3d_kernel<R, SHAPE, T, BC, RY, NW, ADJ, 2>), dim3(tiles_x * tiles_y),
+                           dim3(NW * kWave), 0, s, (const T*)in, (T*)out, (const T*)fields, g.nx, g.ny, 1, 1,
+                           tiles_x, tiles_y);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((vc3d_kernel<R, SHAPE, T, BC, RY, NW, ADJ, 3>), dim3(tiles_x * tiles_y * nchunks),
                        dim3(NW * kWave), 0, s, (const T*)in, (T*)out, (const T*)fields, g.nx, g.ny, g.nz, zc,
                        tiles_x, tiles_y);
     return hipGetLastError();
@@ -183,7 +192,7 @@ static hipError_t go_t(const Geom& g, const LaunchCfg& c, const void* in, void* 
     return hipErrorInvalidValue;
 }
 
-// One variable-coefficient step (or its transpose) of a 3D grid.
+// One variable-coefficient step (or its transpose) of a 2D or 3D grid.
 hipError_t launch_vc3d(const Geom& g, const LaunchCfg& cfg, const void* in, void* out, const void* fields,
                        bool adjoint, hipStream_t stream) {
     if (!vc3d_supported(g.r, g.shape)) return hipErrorInvalidValue;

@@ -116,7 +116,6 @@ st_status validate(const st_problem* p) {
     if ((double)p->n[0] * (double)p->n[1] > 2147483647.0)
         ST_FAIL(ST_ESHAPE, "one plane must hold fewer than 2^31 cells");
     if (p->update == ST_VARCOEF) {
-        if (p->ndim != 3) ST_FAIL(ST_EUNSUPPORTED, "variable coefficients are provided for 3D sweeps");
         if (!vc3d_supported(p->radius, p->shape))
             ST_FAIL(ST_EUNSUPPORTED, "variable-coefficient %s r=%d is not provided",
                     p->shape == ST_STAR ? "star" : "box", p->radius);

@@ -203,6 +203,27 @@ class VarCoefStencil(_Plan):
         return self._run(lib().stencil_apply_varcoef_adjoint, v, fields, steps, out, stream)
 
 
+class _VarCoefSweepFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, fields, stencil: "VarCoefStencil", steps: int):
+        ctx.stencil = stencil
+        ctx.steps = steps
+        ctx.save_for_backward(fields)
+        return stencil.apply(u.contiguous(), fields, steps)
+
+    @staticmethod
+    def backward(ctx, g):
+        (fields,) = ctx.saved_tensors
+        return ctx.stencil.apply_adjoint(g.contiguous(), fields, ctx.steps), None, None, None
+
+
+def varcoef_sweep(u: torch.Tensor, fields: torch.Tensor, stencil: "VarCoefStencil", steps: int) -> torch.Tensor:
+    """Differentiable A^steps u for a variable-coefficient stencil (the
+    gradient with respect to u is the transposed sweep; the fields are
+    treated as constants)."""
+    return _VarCoefSweepFn.apply(u, fields, stencil, steps)
+
+
 class _SweepFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, stencil: Stencil, steps: int):
