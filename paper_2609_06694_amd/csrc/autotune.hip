@@ -113,14 +113,14 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
         else vars = {ST_VARIANT_ZM3D};
         for (int var : vars)
             for (int ty : {8, 16, 32})
-                for (int zc : {32, 64, 128, 256, 0}) {
+                for (int zc : {16, 32, 64, 128, 256, 0}) {
                     if (zc != 0 && zc >= p.n[2]) continue;
                     LaunchCfg c{var, 0, ty, 1, zc};
                     if (cfg_legal(p, c)) out.push_back(c);
                 }
         // Two fused steps (radius 1: 62 x (tile_y - 2) output tiles).
         for (int ty : {16, 32})
-            for (int zc : {32, 64, 128, 0}) {
+            for (int zc : {16, 32, 64, 128, 0}) {
                 if (zc != 0 && zc >= p.n[2]) continue;
                 LaunchCfg c{ST_VARIANT_ZM3D, 0, ty, 2, zc};
                 if (cfg_legal(p, c)) out.push_back(c);

@@ -28,7 +28,10 @@ struct LaunchCfg {
     int zchunk;    // ZM3D/WAVE3D planes per workgroup (0 = all)
 };
 
-enum WaveMode { kWaveFwd = 0, kWaveAdj = 1, kWaveGrad = 2 };
+// kWaveGrad stages u_t and applies L to it; kWaveGradPt takes L(u_t) as a
+// pointwise field (written by a forward step with lap_out) and the residual
+// plane from the recorded trace.
+enum WaveMode { kWaveFwd = 0, kWaveAdj = 1, kWaveGrad = 2, kWaveGradPt = 3 };
 
 struct WaveLaunch {
     const float* prev;      // u_{t-1} (fwd/adj) or lambda_{t+2} (grad)
@@ -43,6 +46,9 @@ struct WaveLaunch {
     int src_x, src_y, src_z;  // fwd: source cell (src_x < 0 = none)
     const float* src_amp;   // fwd: device pointer to the amplitude added at the source
     float prev_sign;        // adj: next = 2 cur - prev_sign * prev (-1 on the first step, +1 after)
+    float* lap_out;         // fwd (ring kernel): receives L(u_t) at every cell, or null
+    const float* lap;       // gradPt: L(u_t), or null (no gradient update this step)
+    const float* trace_res; // gradPt: u_t on plane rec_z (ny*nx), used with target_t
 };
 
 // Two fused forward leapfrog steps: (u_{t-1}, u_t) -> (u_{t+1}, u_{t+2}).

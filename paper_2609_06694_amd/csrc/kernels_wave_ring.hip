@@ -17,7 +17,7 @@
 
 namespace stk {
 
-template <int R, int BC, int RY, int NW, int D, bool ISO>
+template <int R, int BC, int RY, int NW, int D, bool ISO, bool LAP = false>
 __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
                                                                  int zc, int tiles_x, int tiles_y,
                                                                  Taps tp) {
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
                     float v = 2.f * uo - pv[d][i] + kv[d][i] * a;
                     if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += amp;
                     if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
+                    if constexpr (LAP) __builtin_nontemporal_store(a, &w.lap_out[zoff + o]);
                     __builtin_nontemporal_store(v, &np_[o]);
                 }
             }
@@ -146,6 +147,15 @@ static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w,
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     const dim3 grid(tiles_x * tiles_y * nchunks), block(G::NT);
+    if (w.lap_out) {   // also write L(u_t) (gradient recompute)
+        if (g.iso)
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, true>), grid, block, 0, s, w, g.nx,
+                               g.ny, g.nz, zc, tiles_x, tiles_y, tp);
+        else
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, true>), grid, block, 0, s, w, g.nx,
+                               g.ny, g.nz, zc, tiles_x, tiles_y, tp);
+        return hipGetLastError();
+    }
     if (g.iso)
         hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true>), grid, block, 0, s, w, g.nx,
                            g.ny, g.nz, zc, tiles_x, tiles_y, tp);

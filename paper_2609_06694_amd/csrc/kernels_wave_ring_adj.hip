@@ -6,11 +6,14 @@
 
 namespace stk {
 
-// Adjoint (MODE = kWaveAdj) and gradient (MODE = kWaveGrad) steps in the
-// ring design:
+// Adjoint (MODE = kWaveAdj) and gradient (MODE = kWaveGrad, kWaveGradPt)
+// steps in the ring design:
 //   adjoint : l_t = 2 l_{t+1} - s * l_{t+2} + L^T(kappa (.) l_{t+1})
 //   gradient: the same with s = 1, plus l_t += [z = rec] (u_t - d_t) and
 //             g += l_{t+1} (.) L(u_t).
+// kWaveGrad stages u_t and applies L itself; kWaveGradPt reads L(u_t) as a
+// pointwise field and u_t on the receiver plane from the recorded trace, so
+// it stages one field like the adjoint (half the LDS, twice the waves).
 // kappa (.) l_{t+1} (and, for the gradient, u_t) is staged once per plane:
 // its halo tile gives the in-plane taps and its interior enters an LDS ring
 // of 2R+2 planes for the z taps, as in the forward kernel.  The unscaled
@@ -18,11 +21,13 @@ namespace stk {
 // L^T (the flipped star), `tp2` holds L.  Direct weighted sums, as in the
 // queue kernel of the same steps.
 template <int MODE, int R, int BC, int RY, int NW, int D>
-__global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch w, int nx, int ny,
+__global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 1) void wave3d_ring_adj_kernel(WaveLaunch w, int nx, int ny,
                                                                      int nz, int zc, int tiles_x,
                                                                      int tiles_y, Taps tp, Taps tp2) {
     using G = PlaneGeom<R, RY, NW>;
     constexpr bool TWO = (MODE == kWaveGrad);
+    constexpr bool PT = (MODE == kWaveGradPt);
+    constexpr bool GRAD = TWO || PT;
     constexpr int NR = 2 * R + 2;
     constexpr int IP = G::BX * G::BY;
     __shared__ float tile[TWO ? 2 : 1][2][G::H * G::W];
@@ -51,7 +56,8 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch 
     float vin[D][RY], vhalo[D][G::HT], kin[D][RY], khalo[D][G::HT];
     float uin[TWO ? D : 1][RY], uhalo[TWO ? D : 1][G::HT];
     uint32_t vm[D];
-    float p2v[D][RY], gv[TWO ? D : 1][RY];   // l_{t+2}, g of the output plane
+    float p2v[D][RY], gv[GRAD ? D : 1][RY];   // l_{t+2}, g of the output plane
+    float luv[PT ? D : 1][RY];                // L(u_t) of the output plane
 
     // In-plane addressing, the same for every plane and field of the march.
     const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, float, NW>(nx, ny, x0, y0);
@@ -67,10 +73,14 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch 
         const size_t zoff = (size_t)min(max(zo, z0), z1 - 1) * plane_sz;
         const char* pp = reinterpret_cast<const char*>(w.prev + zoff);
         const char* gp = reinterpret_cast<const char*>(w.grad + zoff);
+        // Without L(u_t) (no gradient term this step) the loads read l_{t+2}
+        // instead, a valid address; their values are not used.
+        const char* lp = reinterpret_cast<const char*>((PT && w.lap ? w.lap : w.prev) + zoff);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             p2v[slot][i] = load_at_nt<float>(pp, pidx.off[i]);
-            if constexpr (TWO) gv[slot][i] = load_at_nt<float>(gp, pidx.off[i]);
+            if constexpr (GRAD) gv[slot][i] = load_at_nt<float>(gp, pidx.off[i]);
+            if constexpr (PT) luv[slot][i] = load_at_nt<float>(lp, pidx.off[i]);
         }
     };
 #pragma unroll
@@ -139,6 +149,11 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_adj_kernel(WaveLaunch 
                     float v;
                     if constexpr (MODE == kWaveAdj) {
                         v = 2.f * lq[0][i] - w.prev_sign * p2v[d][i] + a;
+                    } else if constexpr (PT) {
+                        v = 2.f * lq[0][i] - p2v[d][i] + a;
+                        if (w.target_t != nullptr && zo == w.rec_z) v += w.trace_res[o] - w.target_t[o];
+                        if (w.lap != nullptr)
+                            __builtin_nontemporal_store(fmaf(lq[0][i], luv[d][i], gv[d][i]), &w.grad[zoff + o]);
                     } else {
                         float a2 = pq2[0][i];
 #pragma unroll
@@ -173,7 +188,8 @@ static hipError_t go_adj(const Geom& g, int zc, const Taps& tp, const Taps& tp2,
     using G = PlaneGeom<R, 2, NW>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
-    hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, 2>), dim3(tiles_x * tiles_y * nchunks),
+    constexpr int D = MODE == kWaveGradPt ? 1 : 2;   // planes in flight (registers: see the kernel)
+    hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D>), dim3(tiles_x * tiles_y * nchunks),
                        dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
     return hipGetLastError();
 }
@@ -183,7 +199,7 @@ static hipError_t go_adj_ty(const Geom& g, const LaunchCfg& c, const Taps& tp, c
                             const WaveLaunch& w, hipStream_t s) {
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
     // Two staged fields (gradient) need two rings: 32-row tiles would not fit in LDS.
-    if constexpr (MODE == kWaveAdj)
+    if constexpr (MODE != kWaveGrad)
         if (c.tile_y >= 32) return go_adj<MODE, R, BC, 16>(g, zc, tp, tp2, w, s);
     if (c.tile_y >= 16) return go_adj<MODE, R, BC, 8>(g, zc, tp, tp2, w, s);
     return go_adj<MODE, R, BC, 4>(g, zc, tp, tp2, w, s);
@@ -215,6 +231,7 @@ hipError_t launch_wave3d_ring_adj(const Geom& g, const LaunchCfg& cfg, const Tap
                                   hipStream_t stream) {
     if (mode == kWaveAdj) return go_adj_r<kWaveAdj>(g, cfg, taps, taps_fwd, w, stream);
     if (mode == kWaveGrad) return go_adj_r<kWaveGrad>(g, cfg, taps, taps_fwd, w, stream);
+    if (mode == kWaveGradPt) return go_adj_r<kWaveGradPt>(g, cfg, taps, taps_fwd, w, stream);
     return hipErrorInvalidValue;
 }
 

@@ -183,9 +183,10 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
         pl->cfg = d;
     }
     // The adjoint and gradient steps have their own configuration: the
-    // LDS-ring kernel with 64 x 16 tiles (8 waves; the gradient stages two
-    // fields, so one workgroup fills a CU's LDS).
-    pl->adj_cfg = LaunchCfg{ST_VARIANT_WAVE3D_LDS, 0, 16, 1, 0};
+    // LDS-ring kernel with 64 x 32 tiles (16 waves, one workgroup per CU;
+    // measured best for the pointwise gradient step, 43.0 against 44.6 ms
+    // with 64 x 16 tiles on the 256^3 x 200 workload).
+    pl->adj_cfg = LaunchCfg{ST_VARIANT_WAVE3D_LDS, 0, 32, 1, 0};
     pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg, 1);
     pl->ckpt_every = 20;
     pl->batched = false;
@@ -573,7 +574,8 @@ struct GradLayout {
     int T, K, S;
     size_t grid;        // bytes per f32 grid
     size_t ckpt_off;    // 2*(S-1) grids: checkpoints of segments 1..S-1
-    size_t states_off;  // K grids: u_{t0+1}..u_{t0+K} of the segment being reversed
+    size_t states_off;  // K grids of the segment being reversed: u_{t0+1}..u_{t0+K} (queue
+                        // kernels) or L(u_{t0})..L(u_{t0+K-1}) (ring kernels)
     size_t scratch_off; // 3 grids: forward rotation
     size_t lam_off;     // 2 grids: adjoint ping-pong
     size_t traces_off;  // T planes
@@ -660,12 +662,14 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
     float* traces = wave->traces ? wave->traces : (float*)(ws + L.traces_off);
     const bool has_src = wave->src[0] >= 0 && wave->wavelet;
 
-    auto fwd_step = [&](const float* prev, const float* cur, float* next, int t, bool record) {
+    auto fwd_step = [&](const float* prev, const float* cur, float* next, int t, bool record,
+                        float* lap_out = nullptr) {
         WaveLaunch w = wave_base();
         w.prev = prev;
         w.cur = cur;
         w.next = next;
         w.kappa = wave->kappa;
+        w.lap_out = lap_out;
         if (has_src) {
             w.src_x = (int)wave->src[0];
             w.src_y = (int)wave->src[1];
@@ -710,7 +714,42 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
     HIP_TRY(launch_fill(dkappa, 0.f, cells_of(plan->prob), s));
     float* l_next = lam[0];   // lambda_{t+1}
     float* l_next2 = lam[1];  // lambda_{t+2}
-    for (int seg = S - 1; seg >= 0; --seg) {
+    // With the LDS-ring kernels the recompute also writes L(u_t) (4 more
+    // bytes per cell) and the reverse step takes it pointwise, with u_t on
+    // the receiver plane from the recorded traces: the reverse kernel then
+    // stages one field instead of two.  The queue kernels keep the states.
+    const bool pointwise = plan->cfg.variant == ST_VARIANT_WAVE3D_LDS &&
+                           plan->adj_cfg.variant == ST_VARIANT_WAVE3D_LDS;
+    for (int seg = S - 1; seg >= 0 && pointwise; --seg) {
+        const int t0 = seg * K;
+        const int t1 = std::min(t0 + K, T);
+        const float* p = seg == 0 ? (const float*)wave->u_prev : ckpt(seg, 0);
+        const float* c = seg == 0 ? (const float*)u0 : ckpt(seg, 1);
+        auto lap = [&](int t) { return (float*)(ws + L.states_off + (size_t)(t - t0) * L.grid); };
+        const int tl = (seg == S - 1) ? T - 1 : t1 - 1;   // last t whose L(u_t) is needed
+        for (int t = t0; t <= tl; ++t) {   // recompute u_{t+1} and L(u_t)
+            float* nx = pick(p, c);
+            HIP_TRY(fwd_step(p, c, nx, t, false, lap(t)));
+            p = c;
+            c = nx;
+        }
+        const int tstart = (seg == S - 1) ? T : t1 - 1;
+        for (int t = tstart; t >= t0; --t) {
+            WaveLaunch w = wave_base();
+            w.prev = l_next2;
+            w.cur = l_next;
+            w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place
+            w.kappa = wave->kappa;
+            w.grad = dkappa;
+            w.lap = t <= T - 1 ? lap(t) : nullptr;   // lambda_{T+1} = 0: no term at t = T
+            w.rec_z = (int)wave->rec_z;
+            w.target_t = t >= 1 ? wave->target + (size_t)(t - 1) * plane : nullptr;
+            w.trace_res = t >= 1 ? traces + (size_t)(t - 1) * plane : nullptr;   // u_t[rec_z]
+            HIP_TRY(launch_wave_adjoint(g, plan->adj_cfg, plan->taps_t, plan->taps, kWaveGradPt, w, s));
+            std::swap(l_next, l_next2);
+        }
+    }
+    for (int seg = S - 1; seg >= 0 && !pointwise; --seg) {
         const int t0 = seg * K;
         const int t1 = std::min(t0 + K, T);
         const float* base_prev = seg == 0 ? (const float*)wave->u_prev : ckpt(seg, 0);

@@ -33,6 +33,13 @@ def main(out: str) -> None:
         plans.append((f"star3d 512^3 {dt}", st.Stencil((512, 512, 512), "star", 1, c.coeffs, dtype=dt)))
     c = wl.box3d(n=16, dtype=wl.F32)
     plans.append(("box3d 512^3 f64", st.Stencil((512, 512, 512), "box", 1, c.coeffs, dtype="f64")))
+    # Smaller cubes fall in other size classes (fewer tiles: more plane chunks).
+    for m in (128, 256):
+        for dt in ("f16", "f32"):
+            c = wl.star3d(n=(16, 16, 16))
+            plans.append((f"star3d {m}^3 {dt}", st.Stencil((m, m, m), "star", 1, c.coeffs, dtype=dt)))
+            c = wl.box3d(n=16, dtype=wl.F32)
+            plans.append((f"box3d {m}^3 {dt}", st.Stencil((m, m, m), "box", 1, c.coeffs, dtype=dt)))
     plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))
     plans.append(("wave 256^3", st.WaveModel((256, 256, 256))))
     # One representative grid per case key of the 64-grid workload; the
