@@ -103,6 +103,15 @@ hipError_t fill(void* p, const st_problem& pr, size_t cells, uint32_t seed, floa
 
 std::vector<LaunchCfg> candidates(const st_problem& p) {
     std::vector<LaunchCfg> out;
+    if (p.update == ST_VARCOEF) {   // plane march: tile height and plane chunk
+        for (int ty : {8, 16})
+            for (int zc : {16, 32, 64, 128, 256, 0}) {
+                if (zc != 0 && (p.ndim == 2 || zc >= p.n[2])) continue;
+                LaunchCfg c{ST_VARIANT_VC3D, 0, ty, 1, zc};
+                if (cfg_legal(p, c)) out.push_back(c);
+            }
+        return out;
+    }
     if (p.update == ST_WAVE || p.ndim == 3) {
         std::vector<int> vars;
         // Forward wave candidates come from the difference-form (LDS ring)
@@ -152,11 +161,23 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
 }
 
 // `steps` steps of configuration c (linear: ping-pong in/tmp ending in out;
-// wave: forward leapfrog with prev = tmp).  Taps may be perturbed.
+// wave: forward leapfrog with prev = tmp).  Taps may be perturbed.  `aux` is
+// kappa (wave) or the coefficient fields (variable coefficients).
 hipError_t run_cfg(const st_problem& p, const st_plan* pl, const LaunchCfg& c, const Taps& taps,
-                   const void* in, void* out, void* tmp, const float* kappa, int steps,
+                   const void* in, void* out, void* tmp, const void* aux, int steps,
                    hipStream_t s) {
     Geom g = plan_geom(pl);
+    const float* kappa = (const float*)aux;
+    if (p.update == ST_VARCOEF) {
+        const void* cur = in;
+        for (int j = 1; j <= steps; ++j) {
+            void* dst = ((steps - j) % 2 == 0) ? out : tmp;
+            hipError_t e = launch_vc3d(g, c, cur, dst, aux, false, s);
+            if (e != hipSuccess) return e;
+            cur = dst;
+        }
+        return hipSuccess;
+    }
     if (p.update == ST_WAVE) {
         const float* prev = (const float*)tmp;
         const float* cur = (const float*)in;
@@ -204,8 +225,9 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     const st_problem& p = pl->prob;
     const size_t cells = (size_t)p.n[0] * p.n[1] * p.n[2];
     const size_t gb = (cells * esize(p.dtype) + 255) / 256 * 256;
-    // Scratch: in, out, tmp, ref (each a full grid), kappa, 2 counters.
-    const size_t kb = p.update == ST_WAVE ? gb : 0;
+    // Scratch: in, out, tmp, ref (each a full grid), kappa (wave) or the
+    // coefficient fields (variable coefficients), 2 counters.
+    const size_t kb = p.update == ST_WAVE ? gb : (p.update == ST_VARCOEF ? (size_t)(varcoef_taps(p) + 1) * gb : 0);
     if (bytes < 4 * gb + kb + 64) {
         set_error("autotune scratch of %zu bytes needed", 4 * gb + kb + 64);
         return ST_EWORKSPACE;
@@ -231,6 +253,11 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
         kp.dtype = ST_F32;
         T_TRY(fill(kappa, kp, cells, 7u, 0.05f, 0.2f, s));
     }
+    if (p.update == ST_VARCOEF) {   // fields near 1/taps: bounded repeated sweeps
+        const int nt = varcoef_taps(p);
+        for (int k = 0; k <= nt; ++k)   // one spare field for the planted fault
+            T_TRY(fill((char*)kappa + (size_t)k * gb, p, cells, 11u + k, 0.f, 2.f / nt, s));
+    }
     T_TRY(fill(in, p, cells, 1u, lo, 1.f, s));
     T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
     LaunchCfg plain = candidates(p).front();
@@ -253,9 +280,13 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
             taps.c[0] += 0.25f;
             taps.sum += 0.25f;
         }
+        // A planted fault in a variable-coefficient candidate reads every
+        // field one grid too far.
+        const void* aux = kappa;
+        if (p.update == ST_VARCOEF && faulty(p, c)) aux = (const char*)kappa + gb;
         // Parity: same inputs (tmp is the wave's u_{-1}; refill it each time).
         T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
-        T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
+        T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, aux, steps, s));
         unsigned h[2] = {0u, 0u};
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 2);
         launch_max_diff(p.dtype, out, ref, cells, cnt, s);
@@ -274,7 +305,7 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
         std::vector<float> ms;
         for (int rep = 0; rep < 6; ++rep) {
             T_TRY(hipEventRecord(e0, s));
-            T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, kappa, steps, s));
+            T_TRY(run_cfg(p, pl, c, taps, in, out, tmp, aux, steps, s));
             T_TRY(hipEventRecord(e1, s));
             T_TRY(hipEventSynchronize(e1));
             float t = 0.f;
@@ -426,10 +457,6 @@ st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, v
     }
     hipStream_t s = (hipStream_t)stream;
     TuneStats st;
-    if (!plan->batched && plan->prob.update == ST_VARCOEF) {
-        set_error("variable-coefficient plans are not autotuned (the dispatch map's entry is used)");
-        return ST_EUNSUPPORTED;
-    }
     if (!plan->batched) {
         st_status r = tune_one(plan, (char*)scratch, scratch_bytes, s, st);
         plan->tune_tried = st.tried;

@@ -121,6 +121,12 @@ static LaunchCfg default_cfg(const CaseKey& k) {
     return c;
 }
 
+int varcoef_taps(const st_problem& p) {
+    const int w = 2 * p.radius + 1;
+    if (p.shape == ST_BOX) return p.ndim == 3 ? w * w * w : w * w;
+    return 1 + 2 * p.ndim * p.radius;
+}
+
 // Starting configuration when a plan option forces a kernel family other
 // than the map's: that family's own defaults (the other option fields then
 // override them).

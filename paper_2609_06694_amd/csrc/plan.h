@@ -44,6 +44,8 @@ std::string key_string(const CaseKey& k);
 LaunchCfg dispatch_lookup(const CaseKey& k);
 LaunchCfg default_dispatch(const CaseKey& k);
 LaunchCfg variant_default(const st_problem& p, int variant);
+// Coefficient fields of an ST_VARCOEF problem: one per offset of the shape.
+int varcoef_taps(const st_problem& p);
 void dispatch_store(const CaseKey& k, const LaunchCfg& cfg, bool persist);
 bool cfg_legal(const st_problem& p, const LaunchCfg& c);
 constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk from the grid

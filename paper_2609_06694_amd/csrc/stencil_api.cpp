@@ -629,7 +629,9 @@ size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode)
         return 4 * ((grid_bytes(plan->prob) + 255) / 256 * 256);
     if (mode == 2) {
         const size_t gb = (grid_bytes(plan->prob) + 255) / 256 * 256;
-        const size_t kb = plan->prob.update == ST_WAVE ? gb : 0;
+        const size_t kb = plan->prob.update == ST_WAVE      ? gb
+                          : plan->prob.update == ST_VARCOEF ? (size_t)(varcoef_taps(plan->prob) + 1) * gb
+                                                            : 0;
         return 4 * gb + kb + 64;
     }
     return grid_bytes(plan->prob);

@@ -40,6 +40,8 @@ def main(out: str) -> None:
             plans.append((f"star3d {m}^3 {dt}", st.Stencil((m, m, m), "star", 1, c.coeffs, dtype=dt)))
             c = wl.box3d(n=16, dtype=wl.F32)
             plans.append((f"box3d {m}^3 {dt}", st.Stencil((m, m, m), "box", 1, c.coeffs, dtype=dt)))
+    plans.append(("varcoef star1 512^3 f32", st.VarCoefStencil((512, 512, 512), "star", 1)))
+    plans.append(("varcoef box1 512^3 f32", st.VarCoefStencil((512, 512, 512), "box", 1)))
     plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))
     plans.append(("wave 256^3", st.WaveModel((256, 256, 256))))
     # One representative grid per case key of the 64-grid workload; the

@@ -81,3 +81,29 @@ def test_autotune_batched_picks_a_batch_depth(st):
     outs = bs.apply([torch.from_numpy(c.u0).cuda() for c in cases], 9)
     for c, o in zip(cases, outs):
         assert rel_l2(o.cpu().numpy(), oracle.sweep(c.u0, c.coeffs, c.shape, c.radius, wl.PERIODIC, 9)) <= 1e-5
+
+
+def test_autotune_varcoef(st, monkeypatch):
+    """The variable-coefficient kernel is tuned like the others: with the
+    fault switch, every 16-row candidate reads the wrong fields and must be
+    rejected; the tuned plan still matches the oracle (3D and 2D)."""
+    monkeypatch.setenv("STENCIL_TUNE_FAULT", "1")
+    rng = np.random.default_rng(64)
+    n = (130, 70, 90)
+    f = wl.varcoef_fields(rng, 7, n[::-1], np.float32)
+    u = wl.small_random_grid(rng, 3, n, np.float32, 0.0, 1.0)
+    s = st.VarCoefStencil(n, "star", 1)
+    stats = s.autotune()
+    d = s.describe()
+    print("varcoef tuned:", d, stats)
+    assert stats["tried"] >= 6 and stats["rejected"] >= 1 and d["variant"] == "vc3d" and d["tile_y"] == 8
+    got = s.apply(torch.from_numpy(u).cuda(), torch.from_numpy(f).cuda(), 3).cpu().numpy()
+    assert rel_l2(got, oracle.varcoef_sweep(u, f, wl.STAR, 1, wl.PERIODIC, 3)) <= 1e-5
+    monkeypatch.delenv("STENCIL_TUNE_FAULT")
+    f2 = wl.varcoef_fields(rng, 9, (300, 500), np.float32)
+    u2 = wl.small_random_grid(rng, 2, (500, 300), np.float32, 0.0, 1.0)
+    s2 = st.VarCoefStencil((500, 300), "box", 1, boundary="zero")
+    stats2 = s2.autotune()
+    assert stats2["tried"] >= 1 and stats2["rejected"] == 0   # one legal tile for the box
+    got2 = s2.apply(torch.from_numpy(u2).cuda(), torch.from_numpy(f2).cuda(), 4).cpu().numpy()
+    assert rel_l2(got2, oracle.varcoef_sweep(u2, f2, wl.BOX, 1, wl.ZERO, 4)) <= 1e-5
