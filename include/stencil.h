@@ -57,7 +57,8 @@ typedef enum {
 
 /* Storage type of the grid.  ST_F32 and ST_F16 (IEEE binary16, rounded to
  * nearest even on every store) compute in f32; ST_F64 computes in f64 with
- * the f32 coefficient values widened exactly (3D linear sweeps only).
+ * the f32 coefficient values widened exactly (linear and variable-coefficient
+ * sweeps; not the wave update or batched plans).
  * Section 2.1 names f16/f32/f64 as the precision axis of a case. */
 typedef enum { ST_F32 = 0, ST_F16 = 1, ST_F64 = 2 } st_dtype;
 typedef enum { ST_PERIODIC = 0, ST_ZERO = 1 } st_boundary;
@@ -95,7 +96,7 @@ typedef struct {
     const float *coeffs;   /* HOST, (2r+1)^ndim dense; for ST_WAVE may be NULL,
                               meaning the central second-difference Laplacian
                               of accuracy order 2r */
-    int32_t dtype;         /* st_dtype (ST_WAVE requires ST_F32; ST_F64 requires ndim 3) */
+    int32_t dtype;         /* st_dtype (ST_WAVE requires ST_F32) */
     int32_t boundary;      /* st_boundary */
     int32_t update;        /* st_update (ST_WAVE requires ndim 3, star) */
 } st_problem;

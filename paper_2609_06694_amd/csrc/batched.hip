@@ -229,6 +229,10 @@ st_status stencil_plan_batched(const st_problem* problems, int32_t count, const 
             stencil_plan_destroy(pl);
             B_FAIL(ST_EUNSUPPORTED, "batched member %d: only 2D linear sweeps are batched", i);
         }
+        if (p.dtype == ST_F64) {
+            stencil_plan_destroy(pl);
+            B_FAIL(ST_EUNSUPPORTED, "batched member %d: f64 storage is not batched", i);
+        }
         if (p.dtype != problems[0].dtype || p.boundary != problems[0].boundary) {
             stencil_plan_destroy(pl);
             B_FAIL(ST_EINVAL, "batched members must share dtype and boundary (member %d)", i);

@@ -104,7 +104,7 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.zchunk = kAutoChunk;
         return c;
     }
-    if (k.size_class <= 1) {
+    if (k.size_class <= 1 && k.dtype != ST_F64) {   // (f64 in 2D: row march only)
         // Small grids: square LDS tiles give enough workgroups; deeper
         // fusion for narrow stencils (these launches are short).
         c.variant = ST_VARIANT_TB2D;
@@ -287,9 +287,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         if (c.tile_x != 256 && c.tile_x != 512) return false;
         if (c.tile_y < 0 || c.tsteps < 1 || c.tsteps > 16) return false;
         if (c.tile_x - 2 * c.tsteps * p.radius < kWave) return false;
-        return ym2d_lds_bytes(c.tile_x, c.tsteps, p.radius) <= ym2d_max_lds_bytes();
+        return ym2d_lds_bytes(c.tile_x, c.tsteps, p.radius, p.dtype == ST_F64 ? 8 : 4) <= ym2d_max_lds_bytes();
     }
-    if (c.variant != ST_VARIANT_TB2D) return false;
+    if (c.variant != ST_VARIANT_TB2D || p.dtype == ST_F64) return false;
     if (c.tile_x < kWave || c.tile_x % kWave || c.tile_x > 512) return false;
     if (c.tile_y < 4 || c.tile_y > 512 || c.tsteps < 1 || c.tsteps > 16) return false;
     return (int)sizeof(float) * tb2d_lds_floats_host(c.tile_x, c.tile_y, c.tsteps, p.radius) <=

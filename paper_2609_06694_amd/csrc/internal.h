@@ -146,8 +146,8 @@ int zm3d_rows(const LaunchCfg& cfg);    // rows per workgroup actually used
 int tb2d_max_lds_bytes();
 int tb2d_lds_floats_host(int BX, int BY, int k, int R);
 bool ym2d_supported(int r, int shape);
-int ym2d_rows(int nt, int k, int R);            // input rows per march iteration
-int ym2d_lds_bytes(int nt, int k, int R);
+int ym2d_rows(int nt, int k, int R, int esz = 4);        // input rows per march iteration
+int ym2d_lds_bytes(int nt, int k, int R, int esz = 4);   // esz: 8 for f64 storage
 int ym2d_max_lds_bytes();
 int ym2d_auto_chunk(int nx, int ny, int nt, int k, int R);
 

@@ -11,19 +11,21 @@ template <int R, int SHAPE, typename T, int BC, int NT, int RY, int D>
 __global__ __launch_bounds__(NT) void ym2d_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                   int nx, int ny, int k, int ow, int ych, int strips,
                                                   Taps tp) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     ym2d_run<R, SHAPE, T, BC, NT, RY, D>(in, out, nx, ny, k, k, ow, ych, strips,
-                                         xcd_remap(blockIdx.x, gridDim.x), tp, lds);
+                                         xcd_remap(blockIdx.x, gridDim.x), tp,
+                                         reinterpret_cast<acc_t<T>*>(lds_raw));
 }
 
-int ym2d_lds_bytes(int nt, int k, int R) {
-    const int RY = ym2d_rows(nt, k, R);
-    return (int)sizeof(float) * k * ym2d_ring_rows(RY, R) * (nt + 2 * R);
+// esz: bytes of the arithmetic type (4, or 8 for f64 storage).
+int ym2d_lds_bytes(int nt, int k, int R, int esz) {
+    const int RY = ym2d_rows(nt, k, R, esz);
+    return esz * k * ym2d_ring_rows(RY, R) * (nt + 2 * R);
 }
 
-int ym2d_rows(int nt, int k, int R) {
+int ym2d_rows(int nt, int k, int R, int esz) {
     // Eight rows per iteration unless the rings would outgrow 64 KiB.
-    return (int)sizeof(float) * k * ym2d_ring_rows(8, R) * (nt + 2 * R) <= 64 * 1024 ? 8 : 4;
+    return esz * k * ym2d_ring_rows(8, R) * (nt + 2 * R) <= 64 * 1024 ? 8 : 4;
 }
 
 int ym2d_max_lds_bytes() { return 160 * 1024; }
@@ -59,7 +61,7 @@ static hipError_t go(const Geom& g, int k, int ych, const Taps& tp, const void* 
     const int ow = NT - 2 * k * R;
     const int strips = (g.nx + ow - 1) / ow;
     const int chunks = (g.ny + ych - 1) / ych;
-    const size_t lds = sizeof(float) * (size_t)k * ym2d_ring_rows(RY, R) * (NT + 2 * R);
+    const size_t lds = sizeof(acc_t<T>) * (size_t)k * ym2d_ring_rows(RY, R) * (NT + 2 * R);
     if (lds > 64 * 1024) {
         hipError_t e = allow_large_lds<ym2d_kernel<R, SHAPE, T, BC, NT, RY, D>>();
         if (e != hipSuccess) return e;
@@ -72,7 +74,7 @@ static hipError_t go(const Geom& g, int k, int ych, const Taps& tp, const void* 
 template <int R, int SHAPE, typename T, int BC, int NT>
 static hipError_t go_ry(const Geom& g, int k, int ych, const Taps& tp, const void* in, void* out,
                         hipStream_t s) {
-    if (ym2d_rows(NT, k, R) == 8) return go<R, SHAPE, T, BC, NT, 8>(g, k, ych, tp, in, out, s);
+    if (ym2d_rows(NT, k, R, (int)sizeof(acc_t<T>)) == 8) return go<R, SHAPE, T, BC, NT, 8>(g, k, ych, tp, in, out, s);
     return go<R, SHAPE, T, BC, NT, 4>(g, k, ych, tp, in, out, s);
 }
 
@@ -115,9 +117,11 @@ hipError_t launch_ym2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
                        void* out, int k, hipStream_t stream) {
     const int nt = cfg.tile_x == 512 ? 512 : 256;
     if (k < 1 || (cfg.tile_x != 256 && cfg.tile_x != 512) || nt - 2 * k * g.r < kWave) return hipErrorInvalidValue;
-    if (ym2d_lds_bytes(nt, k, g.r) > ym2d_max_lds_bytes()) return hipErrorInvalidValue;
+    const int esz = g.dtype == 2 ? 8 : 4;
+    if (ym2d_lds_bytes(nt, k, g.r, esz) > ym2d_max_lds_bytes()) return hipErrorInvalidValue;
     const int ych = cfg.tile_y > 0 ? std::min(cfg.tile_y, g.ny) : ym2d_auto_chunk(g.nx, g.ny, nt, k, g.r);
     if (g.dtype == 0) return go_t<float>(g, nt, k, ych, taps, in, out, stream);
+    if (g.dtype == 2) return go_t<double>(g, nt, k, ych, taps, in, out, stream);
     return go_t<_Float16>(g, nt, k, ych, taps, in, out, stream);
 }
 

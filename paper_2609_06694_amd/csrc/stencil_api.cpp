@@ -125,7 +125,6 @@ st_status validate(const st_problem* p) {
         if (p->dtype != ST_F32) ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 storage");
     } else {
         if (!p->coeffs) ST_FAIL(ST_EINVAL, "coefficients are NULL");
-        if (p->dtype == ST_F64 && p->ndim != 3) ST_FAIL(ST_EUNSUPPORTED, "f64 storage is provided for 3D sweeps");
         if (p->ndim == 2 && !tb2d_supported(p->radius, p->shape))
             ST_FAIL(ST_EUNSUPPORTED, "2D %s r=%d is not provided", p->shape == ST_STAR ? "star" : "box",
                     p->radius);

@@ -56,12 +56,13 @@ __device__ __forceinline__ bool ym_fix(int& i, int n) {
 // The window geometry (output width ow = NT - 2 kgeo R, halo rows) is laid
 // out for kgeo fused steps; klev <= kgeo levels are computed (a final,
 // shorter time block keeps the geometry of the others).  `lds` holds
-// klev rings of ym2d_ring_rows(RY, R) x (NT + 2R) floats.  Called by all NT
+// klev rings of ym2d_ring_rows(RY, R) x (NT + 2R) values of the arithmetic type.  Called by all NT
 // threads.
 template <int R, int SHAPE, typename T, int BC, int NT, int RY, int D>
 __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int kgeo,
                          int klev, int ow, int ych, int strips, int b, const Taps& tp,
-                         float* __restrict__ lds) {
+                         acc_t<T>* __restrict__ lds) {
+    using A = acc_t<T>;   // arithmetic type (f64 for f64 storage, else f32)
     constexpr int C = ym2d_ring_rows(RY, R);   // ring rows per level
     constexpr int U = C / RY;                  // iterations per ring period
     constexpr int NRD = RY + 2 * R;            // rows a stage reads from the level below
@@ -111,27 +112,27 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
 
             // Stage 0: stage the input rows of this iteration in ring 0.
             {
-                float* r0 = lds;
+                A* r0 = lds;
 #pragma unroll
                 for (int j = 0; j < RY; ++j) {
                     int q = base + 2 * R + j;
                     q = q >= C ? q - C : q;
-                    const float val = to_f32(v[d][j]);
-                    r0[q * RW + R + x] = (BC == kPeriodic || ((vm[d] >> j) & 1u)) ? val : 0.f;
+                    const A val = to_acc<T>(v[d][j]);
+                    r0[q * RW + R + x] = (BC == kPeriodic || ((vm[d] >> j) & 1u)) ? val : A(0);
                 }
             }
             issue(d, i + D);
             __syncthreads();
 
             for (int s = 1; s <= k; ++s) {
-                const float* src = lds + (s - 1) * (C * RW);
-                float acc[RY];
+                const A* src = lds + (s - 1) * (C * RW);
+                A acc[RY];
                 if constexpr (SHAPE == kBox) {
 #pragma unroll
-                    for (int j = 0; j < RY; ++j) acc[j] = 0.f;
+                    for (int j = 0; j < RY; ++j) acc[j] = A(0);
 #pragma unroll
                     for (int dx = -R; dx <= R; ++dx) {
-                        float col[NRD];
+                        A col[NRD];
 #pragma unroll
                         for (int j = 0; j < NRD; ++j) {
                             int q = base + j;
@@ -142,10 +143,10 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                         for (int j = 0; j < RY; ++j)
 #pragma unroll
                             for (int dy = -R; dy <= R; ++dy)
-                                acc[j] = fmaf(tp.c[box2<R>(dy, dx)], col[j + R + dy], acc[j]);
+                                acc[j] = fma_acc(A(tp.c[box2<R>(dy, dx)]), col[j + R + dy], acc[j]);
                     }
                 } else {
-                    float col[NRD];
+                    A col[NRD];
 #pragma unroll
                     for (int j = 0; j < NRD; ++j) {
                         int q = base + j;
@@ -154,11 +155,11 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                     }
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
-                        float a = tp.c[0] * col[j + R];
+                        A a = A(tp.c[0]) * col[j + R];
 #pragma unroll
                         for (int e = 1; e <= R; ++e) {
-                            a = fmaf(tp.c[star_y<R>(-e)], col[j + R - e], a);
-                            a = fmaf(tp.c[star_y<R>(e)], col[j + R + e], a);
+                            a = fma_acc(A(tp.c[star_y<R>(-e)]), col[j + R - e], a);
+                            a = fma_acc(A(tp.c[star_y<R>(e)]), col[j + R + e], a);
                         }
                         acc[j] = a;
                     }
@@ -166,25 +167,25 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                     for (int j = 0; j < RY; ++j) {
                         int q = base + R + j;
                         q = q >= C ? q - C : q;
-                        const float* row = src + q * RW + R + x;
+                        const A* row = src + q * RW + R + x;
 #pragma unroll
                         for (int e = 1; e <= R; ++e) {
-                            acc[j] = fmaf(tp.c[star_x<R>(-e)], row[-e], acc[j]);
-                            acc[j] = fmaf(tp.c[star_x<R>(e)], row[e], acc[j]);
+                            acc[j] = fma_acc(A(tp.c[star_x<R>(-e)]), row[-e], acc[j]);
+                            acc[j] = fma_acc(A(tp.c[star_x<R>(e)]), row[e], acc[j]);
                         }
                     }
                 }
                 const int y0 = Y + i * RY - s * R;   // global row of acc[0]
                 if (s < k) {
-                    float* dst = lds + s * (C * RW);
+                    A* dst = lds + s * (C * RW);
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
                         int q = base + 2 * R + j;
                         q = q >= C ? q - C : q;
-                        float val = round_to_storage<T>(acc[j]);
+                        A val = to_acc<T>(from_acc<T>(acc[j]));   // storage rounding
                         if (BC == kZero) {
                             const int gy = y0 + j;
-                            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) val = 0.f;
+                            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) val = A(0);
                         }
                         dst[q * RW + R + x] = val;
                     }
@@ -194,7 +195,7 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                     for (int j = 0; j < RY; ++j) {
                         const int gy = y0 + j;
                         if (gy >= oy0 && gy < oy1)
-                            __builtin_nontemporal_store(from_f32<T>(acc[j]), &out[(size_t)gy * nx + gx]);
+                            __builtin_nontemporal_store(from_acc<T>(acc[j]), &out[(size_t)gy * nx + gx]);
                     }
                 }
             }

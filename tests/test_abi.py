@@ -71,7 +71,6 @@ def _plan(L, p, opts=None):
     (dict(ndim=3, n=(8, 8, 8), shape=1, r=3), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=1), _abi.ST_EUNSUPPORTED),
     (dict(ndim=2, n=(8, 8, 1), update=1, coeffs=None), _abi.ST_EUNSUPPORTED),
-    (dict(ndim=2, n=(8, 8, 1), dtype=2), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=2), _abi.ST_EUNSUPPORTED),
 ])
 def test_plan_validation_codes(L, kw, code):
@@ -219,3 +218,19 @@ def test_f64_plan_uses_zmarch_with_short_tiles(L):
     L.stencil_plan_describe(h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k), ctypes.byref(z))
     assert v.value == _abi.ST_VARIANT_ZM3D and ty.value in (8, 16) and k.value <= 1
     L.stencil_plan_destroy(h)
+
+
+def test_f64_2d_plan_uses_row_march_and_batch_rejects_f64(L):
+    """2D f64 sweeps go to the row march (the only 2D family with an f64
+    path); a batched plan refuses f64 members."""
+    p, keep = _prob(ndim=2, n=(300, 200, 1), shape=0, r=2, dtype=2)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK, L.stencil_last_error()
+    v = ctypes.c_int32()
+    L.stencil_plan_describe(h, ctypes.byref(v), None, None, None, None)
+    assert v.value == 5
+    L.stencil_plan_destroy(h)
+    arr = (_abi.StProblem * 2)(p, p)
+    hb = ctypes.c_void_p()
+    assert L.stencil_plan_batched(arr, 2, None, ctypes.byref(hb)) == _abi.ST_EUNSUPPORTED
+    assert not hb.value
