@@ -140,6 +140,27 @@ def timed(fn, reps, warmup, sync):
     return float(np.median(ts))
 
 
+def timed_pair(fa, fb, reps, warmup, sync):
+    """Median times (ms) of two variants measured in interleaved passes (a,
+    b, a, b, ...), so drift of clocks or temperature affects both alike."""
+    import torch
+    for _ in range(warmup):
+        fa()
+        fb()
+    sync()
+    ta, tb = [], []
+    for _ in range(reps):
+        for fn, ts in ((fa, ta), (fb, tb)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+    return float(np.median(ta)), float(np.median(tb))
+
+
 def gcells(cells, steps, ms):
     return cells * steps / (ms * 1e-3) / 1e9
 
@@ -284,11 +305,11 @@ def bench_batch(dev, st, wl, torch):
         for p, u, o, c in zip(plans, ins, outs, cases):
             p.apply(u, c.steps, out=o)
 
-    ms = timed(run, 3, 1, torch.cuda.synchronize)
-    g = gcells(cells, 32, ms)
     bs = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
                             for c in cases])
-    bms = timed(lambda: bs.apply(ins, 32, outs=outs), 5, 2, torch.cuda.synchronize)
+    # Seven interleaved passes of the two variants, medians.
+    ms, bms = timed_pair(run, lambda: bs.apply(ins, 32, outs=outs), 7, 2, torch.cuda.synchronize)
+    g = gcells(cells, 32, ms)
     bg = gcells(cells, 32, bms)
     return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms": bms, "gcells_s": bg,
             "launches": "one per time block for all 64 grids", "eff_gbs": bg * 8,
@@ -307,14 +328,15 @@ def bench_grad(dev, st, wl, torch):
     _, _, target = model.forward(zeros, zeros, kt, case.steps, src=case.src, wavelet=wav,
                                  rec_z=case.rec_z, record=True)
     target = target.contiguous()
-    fwd_ms = timed(lambda: model.forward(zeros, zeros, kap, case.steps, src=case.src, wavelet=wav,
-                                         rec_z=case.rec_z, record=True), 3, 1, torch.cuda.synchronize)
     res = {}
 
     def grad():
         res["g"] = model.gradient(zeros, zeros, kap, case.steps, case.src, wav, case.rec_z, target)
 
-    g_ms = timed(grad, 3, 1, torch.cuda.synchronize)
+    # Forward and forward + backward in seven interleaved passes, medians.
+    fwd_ms, g_ms = timed_pair(lambda: model.forward(zeros, zeros, kap, case.steps, src=case.src, wavelet=wav,
+                                                    rec_z=case.rec_z, record=True), grad, 7, 1,
+                              torch.cuda.synchronize)
     dk, loss = res["g"]
     return {"workload": "wavegrad3d_star4_256^3_200steps_ckpt20", "fwd_ms": fwd_ms, "fwd_bwd_ms": g_ms,
             "ratio_fwd_bwd_over_fwd": g_ms / fwd_ms,
