@@ -261,7 +261,8 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     T_TRY(fill(in, p, cells, 1u, lo, 1.f, s));
     T_TRY(fill(tmp, p, cells, 2u, lo, 1.f, s));
     LaunchCfg plain = candidates(p).front();
-    if (p.ndim == 2 && p.update == ST_LINEAR) plain = LaunchCfg{ST_VARIANT_TB2D, 64, 32, 1, 0};
+    if (p.ndim == 2 && p.update == ST_LINEAR)   // one step per launch; f64 has the row march only
+        plain = p.dtype == ST_F64 ? LaunchCfg{ST_VARIANT_YM2D, 256, 0, 1, 0} : LaunchCfg{ST_VARIANT_TB2D, 64, 32, 1, 0};
     else plain.zchunk = 0;
     T_TRY(run_cfg(p, pl, plain, pl->taps, in, ref, tmp, kappa, steps, s));
 

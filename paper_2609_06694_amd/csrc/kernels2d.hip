@@ -63,6 +63,7 @@ static hipError_t go_t(const Geom& g, int BX, int BY, int k, const Taps& taps, c
 hipError_t launch_tb2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                        void* out, int k, hipStream_t stream) {
     if (k < 1 || cfg.tile_x < kWave || cfg.tile_x % kWave || cfg.tile_y < 1) return hipErrorInvalidValue;
+    if (g.dtype != 0 && g.dtype != 1) return hipErrorInvalidValue;   // fp16 / f32 storage only
     if ((int)sizeof(float) * tb2d_lds_floats(cfg.tile_x, cfg.tile_y, k, g.r) > tb2d_max_lds_bytes())
         return hipErrorInvalidValue;
     if (g.dtype == 0) return go_t<float>(g, cfg.tile_x, cfg.tile_y, k, taps, in, out, stream);

@@ -211,7 +211,7 @@ static hipError_t go_bc(const Geom& g, int ty, int zc, const Taps& tp, const voi
 // Two steps of a radius-1 3D linear sweep in one launch.
 hipError_t launch_zm3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                            void* out, hipStream_t stream) {
-    if (!zm3d_tb2_supported(g.r, g.shape)) return hipErrorInvalidValue;
+    if (!zm3d_tb2_supported(g.r, g.shape) || (g.dtype != 0 && g.dtype != 1)) return hipErrorInvalidValue;
     const int zc = cfg.zchunk > 0 ? cfg.zchunk : g.nz;
     const int ty = cfg.tile_y;
     if (g.dtype == 0)

@@ -107,3 +107,27 @@ def test_autotune_varcoef(st, monkeypatch):
     assert stats2["tried"] >= 1 and stats2["rejected"] == 0   # one legal tile for the box
     got2 = s2.apply(torch.from_numpy(u2).cuda(), torch.from_numpy(f2).cuda(), 4).cpu().numpy()
     assert rel_l2(got2, oracle.varcoef_sweep(u2, f2, wl.BOX, 1, wl.ZERO, 4)) <= 1e-5
+
+
+def test_autotune_f64(st):
+    """f64 plans tune over their legal families only (2D: the row march; 3D:
+    the one-step z-march) and stay at the f64 gate."""
+    rng = np.random.default_rng(65)
+    c = wl.random_unit_sum_coeffs(rng, 2, wl.BOX, 2)
+    u = wl.small_random_grid(rng, 2, (600, 300), np.float64, 0.0, 1.0)
+    s = st.Stencil((600, 300), "box", 2, c, dtype="f64")
+    stats = s.autotune()
+    d = s.describe()
+    print("f64 2D tuned:", d, stats)
+    assert stats["tried"] >= 4 and stats["rejected"] == 0 and d["variant"] == "ym2d"
+    got = s.apply(torch.from_numpy(u).cuda(), 7).cpu().numpy()
+    assert rel_l2(got, oracle.sweep(u, c, wl.BOX, 2, wl.PERIODIC, 7)) <= 1e-12
+    c3 = wl.random_unit_sum_coeffs(rng, 3, wl.STAR, 2)
+    u3 = wl.small_random_grid(rng, 3, (100, 60, 70), np.float64, 0.0, 1.0)
+    s3 = st.Stencil((100, 60, 70), "star", 2, c3, dtype="f64", boundary="zero")
+    stats3 = s3.autotune()
+    d3 = s3.describe()
+    print("f64 3D tuned:", d3, stats3)
+    assert stats3["rejected"] == 0 and d3["variant"] == "zm3d" and d3["tsteps"] <= 1 and d3["tile_y"] in (8, 16)
+    got3 = s3.apply(torch.from_numpy(u3).cuda(), 3).cpu().numpy()
+    assert rel_l2(got3, oracle.sweep(u3, c3, wl.STAR, 2, wl.ZERO, 3)) <= 1e-12
