@@ -238,7 +238,8 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     char* ref = scratch + 3 * gb;
     float* kappa = (float*)(scratch + 4 * gb);
     unsigned* cnt = (unsigned*)(scratch + 4 * gb + kb);
-    const int steps = p.update == ST_WAVE ? 2 : (p.ndim == 2 ? 8 : 2);
+    // 2D probes run ten steps: depths that divide it need no remainder launch.
+    const int steps = p.update == ST_WAVE ? 2 : (p.ndim == 2 ? 10 : 2);
     const float lo = p.update == ST_WAVE ? -1.f : 0.f;
 #define T_TRY(e)                                                                         \
     do {                                                                                 \
