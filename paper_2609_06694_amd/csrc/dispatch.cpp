@@ -71,7 +71,10 @@ CaseKey classify(const st_problem& p) {
         lo = p.n[a] < lo ? p.n[a] : lo;
         hi = p.n[a] > hi ? p.n[a] : hi;
     }
-    k.slab = hi >= 4 * lo ? 1 : 0;
+    // Slabs (longest side >= 4x the shortest) split by their thin axis: 1 if
+    // it is the slowest one (z in 3D, y in 2D: few planes or rows to march),
+    // 2 if it lies across the march (long columns, thin rows).
+    k.slab = hi < 4 * lo ? 0 : (p.n[p.ndim - 1] == lo ? 1 : 2);
     return k;
 }
 
@@ -79,7 +82,8 @@ std::string key_string(const CaseKey& k) {
     char buf[128];
     snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
              k.r, k.dtype == 0 ? "f32" : (k.dtype == 1 ? "f16" : "f64"), k.boundary == kPeriodic ? "periodic" : "zero",
-             k.update == 0 ? "linear" : (k.update == 1 ? "wave" : "varcoef"), k.size_class, k.slab ? " slab" : "");
+             k.update == 0 ? "linear" : (k.update == 1 ? "wave" : "varcoef"), k.size_class,
+             k.slab == 0 ? "" : (k.slab == 1 ? " slab-thin-slow-axis" : " slab-thin-cross-axis"));
     return buf;
 }
 
