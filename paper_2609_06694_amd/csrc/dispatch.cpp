@@ -71,10 +71,12 @@ CaseKey classify(const st_problem& p) {
         lo = p.n[a] < lo ? p.n[a] : lo;
         hi = p.n[a] > hi ? p.n[a] : hi;
     }
-    // Slabs (longest side >= 4x the shortest) split by their thin axis: 1 if
-    // it is the slowest one (z in 3D, y in 2D: few planes or rows to march),
-    // 2 if it lies across the march (long columns, thin rows).
-    k.slab = hi < 4 * lo ? 0 : (p.n[p.ndim - 1] == lo ? 1 : 2);
+    // Slabs (longest side >= 4x the shortest) by orientation to the march
+    // (the slowest axis: z in 3D, y in 2D): 1 = the march axis is the
+    // shortest (few planes or rows), 2 = it is the longest (a long column),
+    // 3 = both the thin and the long side lie across it.
+    const int64_t nm = p.n[p.ndim - 1];
+    k.slab = hi < 4 * lo ? 0 : (nm == lo ? 1 : (nm == hi ? 2 : 3));
     return k;
 }
 
@@ -83,7 +85,7 @@ std::string key_string(const CaseKey& k) {
     snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
              k.r, k.dtype == 0 ? "f32" : (k.dtype == 1 ? "f16" : "f64"), k.boundary == kPeriodic ? "periodic" : "zero",
              k.update == 0 ? "linear" : (k.update == 1 ? "wave" : "varcoef"), k.size_class,
-             k.slab == 0 ? "" : (k.slab == 1 ? " slab-thin-slow-axis" : " slab-thin-cross-axis"));
+             k.slab == 0 ? "" : (k.slab == 1 ? " slab-few-planes" : (k.slab == 2 ? " slab-long-march" : " slab-across")));
     return buf;
 }
 

@@ -33,7 +33,7 @@ namespace stk {
 struct CaseKey {
     int ndim, shape, r, dtype, boundary, update;
     int size_class;   // 0: <= 2^18 cells, 1: <= 2^20, 2: <= 2^22, 3: <= 2^25, 4: larger
-    int slab;         // longest side >= 4x the shortest: 1 thin along the slowest axis, 2 across; else 0
+    int slab;         // longest side >= 4x the shortest: 1 march axis shortest, 2 longest, 3 neither; else 0
 };
 
 CaseKey classify(const st_problem& p);

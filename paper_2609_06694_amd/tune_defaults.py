@@ -33,9 +33,9 @@ def main(out: str) -> None:
         plans.append((f"star3d 512^3 {dt}", st.Stencil((512, 512, 512), "star", 1, c.coeffs, dtype=dt)))
     c = wl.box3d(n=16, dtype=wl.F32)
     plans.append(("box3d 512^3 f64", st.Stencil((512, 512, 512), "box", 1, c.coeffs, dtype="f64")))
-    # Slabs, thin along z (few planes) and thin across the march.
+    # Slabs: few planes, a long column, thin across the march.
     for dt in ("f16", "f32"):
-        for shp in ((4096, 4096, 8), (4096, 64, 512)):
+        for shp in ((4096, 4096, 8), (64, 64, 32768), (4096, 64, 512)):
             c = wl.star3d(n=(16, 16, 16))
             plans.append((f"star3d slab {shp} {dt}", st.Stencil(shp, "star", 1, c.coeffs, dtype=dt)))
             c = wl.box3d(n=16, dtype=wl.F32)
@@ -57,8 +57,8 @@ def main(out: str) -> None:
     for g in wl.batch2d():
         cells = g.n[0] * g.n[1]
         size_class = sum(cells > 1 << b for b in (18, 20, 22, 25))
-        lo = min(g.n[:2])
-        slab = 0 if max(g.n[:2]) < 4 * lo else (1 if g.n[1] == lo else 2)
+        lo, hi = min(g.n[:2]), max(g.n[:2])
+        slab = 0 if hi < 4 * lo else (1 if g.n[1] == lo else (2 if g.n[1] == hi else 3))
         key = (g.shape, g.radius, size_class, slab)
         if key in seen:
             continue
