@@ -492,11 +492,16 @@ def _grad_case(n=(40, 36, 44), steps=30, seed=41, blob=True):
     return kappa, zeros, src, wav, rec, target.astype(np.float32)
 
 
-def test_wave_gradient_vs_oracle(st):
-    """Large residual (zero target): the f32 gradient must meet the 1e-5 gate."""
+@pytest.mark.parametrize("family", ["ring", "queue"])
+def test_wave_gradient_vs_oracle(st, family):
+    """Large residual (zero target): the f32 gradient must meet the 1e-5 gate,
+    through the ring kernels (L(u_t) written by the recompute, pointwise
+    reverse step) and through the queue kernels (u_t staged in the reverse
+    step)."""
     kappa, zeros, src, wav, rec, target = _grad_case(blob=False)
     steps = 30
-    m = st.WaveModel(kappa.shape[::-1], ckpt_every=7)
+    kw = {} if family == "ring" else dict(variant=3)
+    m = st.WaveModel(kappa.shape[::-1], ckpt_every=7, **kw)
     dk, loss = m.gradient(_dev(zeros), _dev(zeros), _dev(kappa), steps, src, _dev(wav), rec, _dev(target))
     g_ref, J_ref = oracle.wave_gradient(zeros, zeros, kappa, steps, src, wav, rec, target, ckpt_every=0)
     eJ = abs(float(_host(loss)[0]) - J_ref) / abs(J_ref)
