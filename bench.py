@@ -242,21 +242,22 @@ def bench_linear(dev, st, wl, torch, case, reps=3):
             "dispatch": s.describe()}
 
 
-def bench_varcoef(dev, st, torch, shape, r, n=512, steps=10):
-    """Variable-coefficient sweep (f32, periodic) on n^3; fields and data are
-    seeded device-side uniform draws, fields normalised per cell."""
-    ntap = st.varcoef_taps(3, shape, r)
+def bench_varcoef(dev, st, torch, shape, r, n=512, steps=10, ndim=3):
+    """Variable-coefficient sweep (f32, periodic) on n^ndim; fields and data
+    are seeded device-side uniform draws, fields normalised per cell."""
+    ntap = st.varcoef_taps(ndim, shape, r)
     g = torch.Generator(device=dev)
     g.manual_seed(99 + ntap)
-    f = torch.rand((ntap, n, n, n), generator=g, device=dev)
+    grid = (n,) * ndim
+    f = torch.rand((ntap,) + grid, generator=g, device=dev)
     f /= f.sum(dim=0, keepdim=True)
-    u = torch.rand((n, n, n), generator=g, device=dev)
+    u = torch.rand(grid, generator=g, device=dev)
     out = torch.empty_like(u)
-    s = st.VarCoefStencil((n, n, n), shape, r)
+    s = st.VarCoefStencil(grid, shape, r)
     ms = timed(lambda: s.apply(u, f, steps, out=out), 3, 1, torch.cuda.synchronize)
-    gc = gcells(n ** 3, steps, ms)
+    gc = gcells(n ** ndim, steps, ms)
     bpc = (ntap + 2) * 4
-    return {"workload": f"varcoef_{shape}{r}_f32_{n}^3_{steps}steps", "ms": ms, "gcells_s": gc,
+    return {"workload": f"varcoef_{shape}{r}_f32_{n}^{ndim}_{steps}steps", "ms": ms, "gcells_s": gc,
             "bytes_per_cell_update": bpc, "eff_gbs": gc * bpc, "hbm_frac": gc * bpc / HBM_PEAK_GBS,
             "dispatch": s.describe()}
 
@@ -406,6 +407,8 @@ def main():
             ("star3d_f64", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F64))),
             ("varcoef_star1", lambda: bench_varcoef(dev, st, torch, "star", 1)),
             ("varcoef_box1", lambda: bench_varcoef(dev, st, torch, "box", 1)),
+            ("varcoef2d_star1", lambda: bench_varcoef(dev, st, torch, "star", 1, n=4096, steps=20, ndim=2)),
+            ("box2d_f64", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F64))),
             ("box3d_r2_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16))),
             ("box3d_r2_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F32))),
             ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),

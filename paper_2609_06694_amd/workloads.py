@@ -173,16 +173,14 @@ def box3d(n: int = 512, steps: int = 50, dtype: int = F16, seed: int = SEED_BOX)
     rng = np.random.default_rng(seed)
     c = random_unit_sum_coeffs(rng, 3, BOX, 1)
     u0 = _uniform(rng, 0.0, 1.0, (n, n, n), DTYPE_NP[dtype])
-    tag = "f16" if dtype == F16 else "f32"
-    return LinearCase(f"box3d_r1_{tag}", 3, (n, n, n), BOX, 1, c, PERIODIC, steps, u0, dtype)
+    return LinearCase(f"box3d_r1_{DTYPE_TAGS[dtype]}", 3, (n, n, n), BOX, 1, c, PERIODIC, steps, u0, dtype)
 
 
 def box2d(n: int = 4096, steps: int = 100, dtype: int = F16, seed: int = SEED_BOX + 10) -> LinearCase:
     rng = np.random.default_rng(seed)
     c = random_unit_sum_coeffs(rng, 2, BOX, 2)
     u0 = _uniform(rng, 0.0, 1.0, (n, n), DTYPE_NP[dtype])
-    tag = "f16" if dtype == F16 else "f32"
-    return LinearCase(f"box2d_r2_{tag}", 2, (n, n, 1), BOX, 2, c, PERIODIC, steps, u0, dtype)
+    return LinearCase(f"box2d_r2_{DTYPE_TAGS[dtype]}", 2, (n, n, 1), BOX, 2, c, PERIODIC, steps, u0, dtype)
 
 
 def star3d(n=(512, 512, 512), r: int = 1, steps: int = 10, dtype: int = F32, seed: int = SEED_BOX + 30) -> LinearCase:
@@ -203,8 +201,7 @@ def box3d_r2(n: int = 512, steps: int = 10, dtype: int = F32, seed: int = SEED_B
     rng = np.random.default_rng(seed)
     c = random_unit_sum_coeffs(rng, 3, BOX, 2)
     u0 = _uniform(rng, 0.0, 1.0, (n, n, n), DTYPE_NP[dtype])
-    tag = "f16" if dtype == F16 else "f32"
-    return LinearCase(f"box3d_r2_{tag}", 3, (n, n, n), BOX, 2, c, PERIODIC, steps, u0, dtype)
+    return LinearCase(f"box3d_r2_{DTYPE_TAGS[dtype]}", 3, (n, n, n), BOX, 2, c, PERIODIC, steps, u0, dtype)
 
 
 # --------------------------------------------------------------------------
