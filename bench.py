@@ -7,8 +7,9 @@ eighth-order Laplacian star, f32, 512^3 cells, zero frame, kappa per cell)
 over inputs already resident in HBM.  `value` is GCells/s = cells * time
 steps / second.  The JSON line also carries the live roofline of the
 dominant kernel (the fused leapfrog step), the FP64 oracle timed on a
-bounded sample on the host, and the other workloads (2D Jacobi, fp16/f32
-box stencils, 64 uneven grids, the wave gradient) as `per_config`.
+bounded sample on the host, and the other workloads (2D Jacobi, the 7-point
+star and the 27- and 125-point boxes in fp16/f32/f64, the 2D box, 64 uneven
+grids, variable coefficients, the wave gradient) as `per_config`.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
