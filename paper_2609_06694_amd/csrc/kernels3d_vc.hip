@@ -106,7 +106,10 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
     int slot = 0;   // ring slot of plane zp
     for (int zp = zbeg; zp < zend; ++zp) {
         store_plane<R, RY, BC, T, NW>(ring[slot], vin, vhalo, vm);
-        vm = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + 1, zend - 1), pidx, vin, vhalo);
+        // A 2D grid is a single pass with nothing to prefetch.  In 3D the
+        // last pass reloads a clamped plane: cheaper than a branch here.
+        if constexpr (NDIM == 3)
+            vm = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + 1, zend - 1), pidx, vin, vhalo);
         __syncthreads();
 
         const int zo = zp - RZ;
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
                     if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[i]), &o[(uint32_t)(gy * nx + gx)]);
                 }
             }
-            load_coef(zo + 1);
+            if constexpr (NDIM == 3) load_coef(zo + 1);
         }
         slot = slot + 1 == NR ? 0 : slot + 1;
     }
