@@ -104,13 +104,14 @@ typedef struct {
 /* Per-plan overrides.  Zero fields mean "dispatch map decides". */
 typedef struct {
     int32_t variant;       /* st_variant */
-    int32_t tile_x;        /* TB2D: output tile width (multiple of 64);
+    int32_t tile_x;        /* TB2D: output tile width (8..512);
                               YM2D: window width = threads per workgroup (256 or 512) */
     int32_t tile_y;        /* TB2D: output tile height; YM2D: rows per chunk (0 = automatic);
                               ZM3D/WAVE3D: rows per workgroup */
     int32_t tsteps;        /* TB2D/YM2D: time steps fused per launch (1..16);
                               WAVE3D: 1, or 2 = two fused leapfrog steps (radius 2 or 4) */
-    int32_t zchunk;        /* ZM3D/WAVE3D: planes per workgroup (0 = whole depth) */
+    int32_t zchunk;        /* ZM3D/WAVE3D: planes per workgroup (0 = whole depth);
+                              TB2D: waves per workgroup (0 = 4, or 8, 16) */
     int32_t ckpt_every;    /* wave gradient checkpoint interval (0 = 20) */
 } st_plan_opts;
 

@@ -149,6 +149,15 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                 LaunchCfg c{ST_VARIANT_TB2D, tx, ty, k, 0};
                 if (cfg_legal(p, c)) out.push_back(c);
             }
+    // Windows of 64 columns with their halo, one pass per fused step: 64 or
+    // 32 rows run by 16 or 8 waves (small, latency-bound grids).
+    for (int k : {1, 2, 4, 8, 10, 16})
+        for (int h : {64, 32}) {
+            const int bx = 64 - 2 * k * (int)p.radius, by = h - 2 * k * (int)p.radius;
+            if (bx < 16 || by < 8 || bx > 2 * p.n[0] || by > 2 * p.n[1]) continue;
+            LaunchCfg c{ST_VARIANT_TB2D, bx, by, k, h / 4};
+            if (cfg_legal(p, c)) out.push_back(c);
+        }
     // Row march: window width, fused depth, rows per chunk (0 = automatic).
     for (int nt : {256, 512})
         for (int k : {1, 2, 4, 8, 10, 16})

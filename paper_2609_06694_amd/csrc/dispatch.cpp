@@ -296,7 +296,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         return ym2d_lds_bytes(c.tile_x, c.tsteps, p.radius, p.dtype == ST_F64 ? 8 : 4) <= ym2d_max_lds_bytes();
     }
     if (c.variant != ST_VARIANT_TB2D || p.dtype == ST_F64) return false;
-    if (c.tile_x < kWave || c.tile_x % kWave || c.tile_x > 512) return false;
+    // zchunk: waves per workgroup (0 = 4).
+    if (c.zchunk != 0 && c.zchunk != 4 && c.zchunk != 8 && c.zchunk != 16) return false;
+    if (c.tile_x < 8 || c.tile_x > 512) return false;
     if (c.tile_y < 4 || c.tile_y > 512 || c.tsteps < 1 || c.tsteps > 16) return false;
     return (int)sizeof(float) * tb2d_lds_floats_host(c.tile_x, c.tile_y, c.tsteps, p.radius) <=
            tb2d_max_lds_bytes();

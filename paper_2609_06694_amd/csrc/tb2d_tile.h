@@ -8,6 +8,11 @@
 // level is rounded to binary16 exactly as a one-step-per-launch sweep would
 // store it.  Zero boundary: cells outside the grid are forced to zero at
 // every level.  Periodic boundary: the halo is loaded with wrapped indices.
+//
+// NW waves share a tile: lanes take columns, waves take strips of kRY2 rows.
+// A 64-column window run by 16 waves covers the whole tile in one pass per
+// fused step, which suits small grids, where the sweep is a chain of short
+// dependent steps (latency) rather than a stream of bytes.
 #pragma once
 
 #include "common.h"
@@ -67,8 +72,8 @@ __device__ __forceinline__ void strip2d(const float* __restrict__ src, int W, in
 }
 
 // Processes the tile whose first output is (gx0, gy0).  `lds` holds
-// tb2d_lds_floats(BX, BY, k, R) floats.  Must be called by all 256 threads.
-template <int R, int SHAPE, typename T, int BC>
+// tb2d_lds_floats(BX, BY, k, R) floats.  Must be called by all NW * 64 threads.
+template <int R, int SHAPE, typename T, int BC, int NW = 4>
 __device__ void tb2d_tile(const T* __restrict__ in, T* __restrict__ out, int nx, int ny,
                           int gx0, int gy0, int BX, int BY, int k, const Taps& tp,
                           float* __restrict__ lds) {
@@ -80,23 +85,36 @@ __device__ void tb2d_tile(const T* __restrict__ in, T* __restrict__ out, int nx,
     const int ox = gx0 - k * R, oy = gy0 - k * R;
     const bool interior = ox >= 0 && oy >= 0 && ox + W <= nx && oy + H <= ny;
 
-    // Stage the input tile with its k*R halo.
-    for (int ly = ty; ly < H; ly += 4) {
-        int gy = oy + ly;
-        bool yin = true;
+    // Stage the input tile with its k*R halo, four rows per thread at a time:
+    // the loads (rows clamped into the tile and the grid, so every address
+    // is valid) are all issued before the first LDS store.
+    constexpr int SB = 4;
+    for (int lx = tx; lx < W; lx += kWave) {
+        int gx = ox + lx;
+        bool xin = true;
         if (!interior) {
-            if (BC == kPeriodic) gy = wrap_index(gy, ny);
-            else yin = gy >= 0 && gy < ny;
-        }
-        const T* row = in + (size_t)(yin ? gy : 0) * nx;
-        for (int lx = tx; lx < W; lx += kWave) {
-            int gx = ox + lx;
-            bool xin = true;
-            if (!interior) {
-                if (BC == kPeriodic) gx = wrap_index(gx, nx);
-                else xin = gx >= 0 && gx < nx;
+            if (BC == kPeriodic) gx = wrap_index(gx, nx);
+            else {
+                xin = gx >= 0 && gx < nx;
+                gx = min(max(gx, 0), nx - 1);
             }
-            b0[ly * W + lx] = (yin && xin) ? to_f32(row[gx]) : 0.f;
+        }
+        for (int ly0 = ty; ly0 < H; ly0 += SB * NW) {
+            T v[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                int gy = oy + min(ly0 + u * NW, H - 1);
+                if (!interior) gy = BC == kPeriodic ? wrap_index(gy, ny) : min(max(gy, 0), ny - 1);
+                v[u] = in[(size_t)gy * nx + gx];
+            }
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int ly = ly0 + u * NW;
+                if (ly >= H) break;
+                const int gy = oy + ly;
+                const bool yin = BC == kPeriodic || interior || (gy >= 0 && gy < ny);
+                b0[ly * W + lx] = (yin && xin) ? to_f32(v[u]) : 0.f;
+            }
         }
     }
     __syncthreads();
@@ -107,7 +125,7 @@ __device__ void tb2d_tile(const T* __restrict__ in, T* __restrict__ out, int nx,
         const int lo = s * R;
         const int yhi = H - lo, xhi = W - lo;
         const bool last = (s == k);
-        for (int y0 = lo + ty * RY; y0 < yhi; y0 += 4 * RY) {
+        for (int y0 = lo + ty * RY; y0 < yhi; y0 += NW * RY) {
             for (int x = lo + tx; x < xhi; x += kWave) {
                 float acc[RY];
                 strip2d<R, SHAPE>(src, W, x, y0, tp, acc);

@@ -121,11 +121,15 @@ def test_wave_plan_gradient_workspace(L):
 
 def test_plan_options_validated(L):
     p, keep = _prob(n=(256, 256, 1))
-    assert _plan(L, p, _abi.StPlanOpts(0, 96, 0, 0, 0, 0))[0] == _abi.ST_EINVAL   # tile_x % 64
+    assert _plan(L, p, _abi.StPlanOpts(1, 4, 16, 1, 0, 0))[0] == _abi.ST_EINVAL   # tile_x < 8
+    assert _plan(L, p, _abi.StPlanOpts(1, 64, 16, 1, 12, 0))[0] == _abi.ST_EINVAL  # waves per tile
     assert _plan(L, p, _abi.StPlanOpts(0, 0, 0, 17, 0, 0))[0] == _abi.ST_EINVAL   # depth
     assert _plan(L, p, _abi.StPlanOpts(2, 0, 0, 0, 0, 0))[0] == _abi.ST_EINVAL    # 3D family on 2D
     assert _plan(L, p, _abi.StPlanOpts(0, 512, 512, 16, 0, 0))[0] == _abi.ST_EINVAL  # LDS budget
     st, h = _plan(L, p, _abi.StPlanOpts(1, 128, 16, 2, 0, 0))
+    assert st == _abi.ST_OK
+    L.stencil_plan_destroy(h)
+    st, h = _plan(L, p, _abi.StPlanOpts(1, 44, 44, 10, 16, 0))   # 64 x 64 window, 16 waves
     assert st == _abi.ST_OK
     L.stencil_plan_destroy(h)
 

@@ -68,6 +68,38 @@ def test_2d_sweep_vs_oracle(st, shape, r, dtype, bc):
 @pytest.mark.parametrize("shape,r", CASES_2D)
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_2d_tile_waves_vs_oracle(st, shape, r, dtype, bc):
+    """LDS tiles run by 8 or 16 waves: 64-column windows whose outputs are
+    64 - 2kR wide (one pass per fused step), and wider or odd-width tiles
+    that still take several passes; grids of several tiles with ragged
+    edges, and one smaller than a tile."""
+    rng = np.random.default_rng(900 + 100 * r + shape)
+    npdt = np.float32 if dtype == "f32" else np.float16
+    c = wl.random_unit_sum_coeffs(rng, 2, shape, r)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    cfgs = []
+    for k in (1, 4, 10):
+        for h, nw in ((64, 16), (32, 8)):
+            bx, by = 64 - 2 * k * r, h - 2 * k * r
+            if bx >= 16 and by >= 8:
+                cfgs.append((bx, by, k, nw))
+    cfgs += [(100, 40, legal_depth(100, 40, 2, r), 8), (128, 32, legal_depth(128, 32, 2, r), 16),
+             (64, 16, legal_depth(64, 16, 3, r), 16)]
+    for (nx, ny), steps in [((197, 131), 11), ((9, 12), 5)]:
+        u = wl.small_random_grid(rng, 2, (nx, ny), npdt, 0.0, 1.0)
+        ref = oracle.sweep(u, c, shape, r, bcode, steps)
+        for tx, ty, k, nw in cfgs:
+            s = st.Stencil((nx, ny), shape, r, c, dtype=dtype, boundary=bc, variant=1, tile_x=tx, tile_y=ty,
+                           tsteps=k, zchunk=nw)
+            assert s.describe()["zchunk"] == nw
+            got = _host(s.apply(_dev(u), steps)).astype(np.float64)
+            e = rel_l2(got, ref)
+            assert e <= TOL[dtype], (nx, ny, tx, ty, k, nw, steps, e)
+
+
+@pytest.mark.parametrize("shape,r", CASES_2D)
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
 def test_2d_rowmarch_vs_oracle(st, shape, r, dtype, bc):
     """Row-march kernel: window widths 256/512, fused depths 1..8, automatic
     and explicit chunks (several chunks and strips, ragged tails, grids
