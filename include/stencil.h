@@ -90,7 +90,9 @@ typedef struct st_plan st_plan;   /* opaque; immutable after creation */
 
 typedef struct {
     int32_t ndim;          /* 2 or 3 */
-    int64_t n[3];          /* nx, ny, nz */
+    int64_t n[3];          /* nx, ny, nz: each 1..2^24, at most 2^36 cells, one
+                              x-y plane under 2^31 cells; 3D and variable-
+                              coefficient grids: one plane under 4 GiB */
     int32_t shape;         /* st_shape */
     int32_t radius;        /* 1..4; box: r <= 2 */
     const float *coeffs;   /* HOST, (2r+1)^ndim dense; for ST_WAVE may be NULL,

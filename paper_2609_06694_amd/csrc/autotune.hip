@@ -120,17 +120,22 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
         // probe, exceeds the 1e-5 gate after tens of steps.
         if (p.update == ST_WAVE) vars = {ST_VARIANT_WAVE3D_LDS};
         else vars = {ST_VARIANT_ZM3D};
+        // Chunks of 8 planes only on small grids (up to 2^22 cells), where
+        // they give enough workgroups to fill the chip.
+        const bool small = (double)p.n[0] * p.n[1] * p.n[2] <= (double)(1 << 22);
         for (int var : vars)
             for (int ty : {8, 16, 32})
-                for (int zc : {16, 32, 64, 128, 256, 0}) {
+                for (int zc : {8, 16, 32, 64, 128, 256, 0}) {
                     if (zc != 0 && zc >= p.n[2]) continue;
+                    if (zc == 8 && !small) continue;
                     LaunchCfg c{var, 0, ty, 1, zc};
                     if (cfg_legal(p, c)) out.push_back(c);
                 }
         // Two fused steps (radius 1: 62 x (tile_y - 2) output tiles).
         for (int ty : {16, 32})
-            for (int zc : {16, 32, 64, 128, 0}) {
+            for (int zc : {8, 16, 32, 64, 128, 0}) {
                 if (zc != 0 && zc >= p.n[2]) continue;
+                if (zc == 8 && !small) continue;
                 LaunchCfg c{ST_VARIANT_ZM3D, 0, ty, 2, zc};
                 if (cfg_legal(p, c)) out.push_back(c);
             }

@@ -115,6 +115,11 @@ st_status validate(const st_problem* p) {
         ST_FAIL(ST_ESHAPE, "grid has more than 2^36 cells");
     if ((double)p->n[0] * (double)p->n[1] > 2147483647.0)
         ST_FAIL(ST_ESHAPE, "one plane must hold fewer than 2^31 cells");
+    // The plane marches (every 3D kernel, and the variable-coefficient
+    // kernel in 2D) address a plane by 32-bit byte offsets.
+    if ((p->ndim == 3 || p->update == ST_VARCOEF) &&
+        (double)p->n[0] * (double)p->n[1] * (double)elem_bytes(p->dtype) > 4294967295.0)
+        ST_FAIL(ST_ESHAPE, "one x-y plane of a 3D or variable-coefficient grid must fit in 4 GiB");
     if (p->update == ST_VARCOEF) {
         if (!vc3d_supported(p->radius, p->shape))
             ST_FAIL(ST_EUNSUPPORTED, "variable-coefficient %s r=%d is not provided",

@@ -67,6 +67,10 @@ def _plan(L, p, opts=None):
     (dict(n=(64, 48, 2)), _abi.ST_ESHAPE),
     (dict(n=(0, 48, 1)), _abi.ST_ESHAPE),
     (dict(n=(1 << 25, 4, 1)), _abi.ST_ESHAPE),
+    # a 4 GiB plane overflows the 32-bit in-plane byte offsets of the plane marches
+    (dict(ndim=3, n=(32768, 32768, 2)), _abi.ST_ESHAPE),
+    (dict(ndim=3, n=(23200, 23200, 2), dtype=2), _abi.ST_ESHAPE),
+    (dict(n=(40000, 40000, 1), update=2, coeffs=None), _abi.ST_ESHAPE),
     (dict(shape=1, r=3), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), shape=1, r=3), _abi.ST_EUNSUPPORTED),
     (dict(ndim=3, n=(8, 8, 8), update=1, coeffs=None, dtype=1), _abi.ST_EUNSUPPORTED),
@@ -79,6 +83,16 @@ def test_plan_validation_codes(L, kw, code):
     assert st == code, L.stencil_last_error()
     assert not h.value
     assert L.stencil_last_error() != b""
+
+
+@pytest.mark.parametrize("kw", [dict(ndim=3, n=(32768, 32768, 2), dtype=1),   # 2 GiB planes
+                                dict(n=(40000, 40000, 1)),                      # 2D linear: cells < 2^31
+                                dict(n=(32000, 32000, 1), update=2, coeffs=None, dtype=1)])
+def test_plan_accepts_large_planes(L, kw):
+    p, keep = _prob(**kw)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK, L.stencil_last_error()
+    L.stencil_plan_destroy(h)
 
 
 def test_star_rejects_off_axis_coefficients(L):
@@ -99,7 +113,8 @@ def test_plan_describe_and_workspace(L):
     v, tx, ty, k, zc = (ctypes.c_int32() for _ in range(5))
     assert L.stencil_plan_describe(h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k),
                                    ctypes.byref(zc)) == _abi.ST_OK
-    assert v.value == _abi.ST_VARIANT_TB2D and tx.value % 64 == 0 and k.value >= 1
+    assert v.value == _abi.ST_VARIANT_TB2D and 8 <= tx.value <= 512 and k.value >= 1
+    assert zc.value in (0, 4, 8, 16)   # waves per tile
     assert L.stencil_workspace_bytes(h, 10, 0) == 512 * 512 * 4
     assert L.stencil_workspace_bytes(None, 10, 0) == 0
     L.stencil_plan_destroy(h)
