@@ -166,7 +166,7 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
     // Row march: window width, fused depth, rows per chunk (0 = automatic).
     for (int nt : {256, 512})
         for (int k : {1, 2, 4, 8, 10, 16})
-            for (int ych : {0, 32, 64, 128}) {
+            for (int ych : {0, 32, 64, 128, 256}) {
                 if (nt > 2 * p.n[0] + 256 || (ych != 0 && ych >= p.n[1])) continue;
                 LaunchCfg c{ST_VARIANT_YM2D, nt, ych, k, 0};
                 if (cfg_legal(p, c)) out.push_back(c);
