@@ -694,7 +694,18 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
         return nullptr;
     };
 
-    // Forward: record traces, keep (u_{sK-1}, u_{sK}) for s = 1..S-1.
+    // With the LDS-ring kernels the recompute also writes L(u_t) (4 more
+    // bytes per cell) and the reverse step takes it pointwise, with u_t on
+    // the receiver plane from the recorded traces: the reverse kernel then
+    // stages one field instead of two.  The queue kernels keep the states.
+    const bool pointwise = plan->cfg.variant == ST_VARIANT_WAVE3D_LDS &&
+                           plan->adj_cfg.variant == ST_VARIANT_WAVE3D_LDS;
+    const int t_last = (S - 1) * K;   // first step of the last segment
+    auto lap = [&](int t, int t0) { return (float*)(ws + L.states_off + (size_t)(t - t0) * L.grid); };
+
+    // Forward: record traces, keep (u_{sK-1}, u_{sK}) for s = 1..S-1.  The
+    // last segment is reversed first, right after this pass, so (pointwise
+    // reverse) its steps write L(u_t) now and it needs no recompute.
     const float* prev = (const float*)wave->u_prev;
     const float* cur = (const float*)u0;
     for (int t = 0; t < T; ++t) {
@@ -704,7 +715,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
         if ((tn + 1) % K == 0 && (tn + 1) / K >= 1 && (tn + 1) / K < S) as_prev = ckpt((tn + 1) / K, 0);
         if (tn % K == 0 && tn / K >= 1 && tn / K < S) as_cur = ckpt(tn / K, 1);
         float* next = as_cur ? as_cur : (as_prev ? as_prev : pick(prev, cur));
-        HIP_TRY(fwd_step(prev, cur, next, t, true));
+        HIP_TRY(fwd_step(prev, cur, next, t, true, pointwise && t >= t_last ? lap(t, t_last) : nullptr));
         if (as_cur && as_prev)   // K == 1: the same state opens two checkpoints
             HIP_TRY(hipMemcpyAsync(as_prev, as_cur, cells_of(plan->prob) * 4, hipMemcpyDeviceToDevice, s));
         prev = cur;
@@ -720,22 +731,16 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
     HIP_TRY(launch_fill(dkappa, 0.f, cells_of(plan->prob), s));
     float* l_next = lam[0];   // lambda_{t+1}
     float* l_next2 = lam[1];  // lambda_{t+2}
-    // With the LDS-ring kernels the recompute also writes L(u_t) (4 more
-    // bytes per cell) and the reverse step takes it pointwise, with u_t on
-    // the receiver plane from the recorded traces: the reverse kernel then
-    // stages one field instead of two.  The queue kernels keep the states.
-    const bool pointwise = plan->cfg.variant == ST_VARIANT_WAVE3D_LDS &&
-                           plan->adj_cfg.variant == ST_VARIANT_WAVE3D_LDS;
     for (int seg = S - 1; seg >= 0 && pointwise; --seg) {
         const int t0 = seg * K;
         const int t1 = std::min(t0 + K, T);
         const float* p = seg == 0 ? (const float*)wave->u_prev : ckpt(seg, 0);
         const float* c = seg == 0 ? (const float*)u0 : ckpt(seg, 1);
-        auto lap = [&](int t) { return (float*)(ws + L.states_off + (size_t)(t - t0) * L.grid); };
-        const int tl = (seg == S - 1) ? T - 1 : t1 - 1;   // last t whose L(u_t) is needed
-        for (int t = t0; t <= tl; ++t) {   // recompute u_{t+1} and L(u_t)
+        // Recompute u_{t+1} and L(u_t) for the segment (the last one has
+        // them from the forward pass).
+        for (int t = t0; t < t1 && seg < S - 1; ++t) {
             float* nx = pick(p, c);
-            HIP_TRY(fwd_step(p, c, nx, t, false, lap(t)));
+            HIP_TRY(fwd_step(p, c, nx, t, false, lap(t, t0)));
             p = c;
             c = nx;
         }
@@ -747,7 +752,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
             w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place
             w.kappa = wave->kappa;
             w.grad = dkappa;
-            w.lap = t <= T - 1 ? lap(t) : nullptr;   // lambda_{T+1} = 0: no term at t = T
+            w.lap = t <= T - 1 ? lap(t, t0) : nullptr;   // lambda_{T+1} = 0: no term at t = T
             w.rec_z = (int)wave->rec_z;
             w.target_t = t >= 1 ? wave->target + (size_t)(t - 1) * plane : nullptr;
             w.trace_res = t >= 1 ? traces + (size_t)(t - 1) * plane : nullptr;   // u_t[rec_z]
