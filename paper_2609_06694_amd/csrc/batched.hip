@@ -162,8 +162,6 @@ Layout layout(const st_plan* plan, int steps, int cus) {
         int ych = (b.ny + chunks - 1) / chunks;
         ych = std::max(ych, std::max(16, 4 * b.k * b.r));
         b.ych = std::min(ych, b.ny);
-        b.first = lay.grid;
-        lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
         b.taps = m->taps;
         lay.rounds = std::max(lay.rounds, b.L);
         if ((int)sizeof(float) * b.k * ym2d_ring_rows(8, b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
@@ -172,8 +170,15 @@ Layout layout(const st_plan* plan, int steps, int cus) {
     // Eight input rows per iteration unless a member's rings would outgrow
     // 64 KiB; the launch reserves the largest member's rings.
     lay.ry = need8 ? 4 : 8;
-    for (const GMember& b : lay.members)
+    // With the row count known, each chunk fills its last march iteration;
+    // the workgroup ranges follow.
+    lay.grid = 0;
+    for (GMember& b : lay.members) {
+        b.ych = ym2d_fill_chunk(b.ych, b.k * b.r, lay.ry, b.ny);
+        b.first = lay.grid;
+        lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
         lay.lds = std::max(lay.lds, sizeof(float) * (size_t)b.k * ym2d_ring_rows(lay.ry, b.r) * (kGroupThreads + 2 * b.r));
+    }
     return lay;
 }
 

@@ -119,7 +119,9 @@ hipError_t launch_ym2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
     if (k < 1 || (cfg.tile_x != 256 && cfg.tile_x != 512) || nt - 2 * k * g.r < kWave) return hipErrorInvalidValue;
     const int esz = g.dtype == 2 ? 8 : 4;
     if (ym2d_lds_bytes(nt, k, g.r, esz) > ym2d_max_lds_bytes()) return hipErrorInvalidValue;
-    const int ych = cfg.tile_y > 0 ? std::min(cfg.tile_y, g.ny) : ym2d_auto_chunk(g.nx, g.ny, nt, k, g.r);
+    const int ych = cfg.tile_y > 0 ? std::min(cfg.tile_y, g.ny)
+                                   : ym2d_fill_chunk(ym2d_auto_chunk(g.nx, g.ny, nt, k, g.r), k * g.r,
+                                                     ym2d_rows(nt, k, g.r, esz), g.ny);
     if (g.dtype == 0) return go_t<float>(g, nt, k, ych, taps, in, out, stream);
     if (g.dtype == 2) return go_t<double>(g, nt, k, ych, taps, in, out, stream);
     return go_t<_Float16>(g, nt, k, ych, taps, in, out, stream);

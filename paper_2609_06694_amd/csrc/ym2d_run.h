@@ -41,6 +41,14 @@ __host__ __device__ constexpr int ym2d_ring_rows(int RY, int R) {
     return c;
 }
 
+// A chunk of ych output rows marches ych + 2kR input rows in iterations of
+// ry rows; an automatic chunk is lengthened to fill its last iteration (the
+// rows past the chunk are computed either way).
+inline int ym2d_fill_chunk(int ych, int kr, int ry, int ny) {
+    const int rows = (ych + 2 * kr + ry - 1) / ry * ry;
+    return rows - 2 * kr < ny ? rows - 2 * kr : ny;
+}
+
 template <int BC>
 __device__ __forceinline__ bool ym_fix(int& i, int n) {
     if (BC == kPeriodic) {
