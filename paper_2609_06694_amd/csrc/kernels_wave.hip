@@ -270,6 +270,7 @@ hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
         case kWaveFwd: return go_r<kWaveFwd>(g, cfg, taps, taps_fwd, w, stream);
         case kWaveAdj: return go_r<kWaveAdj>(g, cfg, taps, taps_fwd, w, stream);
         case kWaveGrad: return go_r<kWaveGrad>(g, cfg, taps, taps_fwd, w, stream);
+        case kWaveGradPt: break;   // the pointwise gradient step is the ring kernel's
     }
     return hipErrorInvalidValue;
 }
