@@ -134,16 +134,42 @@ def test_fullsize_box3d_r2(st, dtype):
     assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
 
 
-@pytest.mark.parametrize("dtype", [wl.F16, wl.F32])
+@pytest.mark.parametrize("dtype", [wl.F16, wl.F32, wl.F64])
 def test_fullsize_box2d(st, dtype):
     case = wl.box2d(dtype=dtype)
-    dt = "f16" if dtype == wl.F16 else "f32"
+    dt = wl.DTYPE_TAGS[dtype]
     s = st.Stencil(case.n[:2], "box", 2, case.coeffs, dtype=dt)
     got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
     starts = [(0, 0), (2000, 3001), (4080, 4080), (1234, 0)]
     e = _sample_linear(case, got, starts, (16, 16))
     print(f"box2d {dt} 4096^2 x100 sampled rel-L2 {e:.2e}")
-    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+    assert e <= {"f16": 2e-3, "f32": 1e-5, "f64": 1e-12}[dt]
+
+
+def test_fullsize_varcoef2d(st):
+    """Variable-coefficient 5-point star on 4096^2 x 20 steps (f32,
+    periodic), as the benchmark runs it; sampled blocks against the oracle
+    on their dependency sub-boxes."""
+    n, steps, r = 4096, 20, 1
+    ntap = st.varcoef_taps(2, "star", r)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5151)
+    f = torch.rand((ntap, n, n), generator=g, device="cuda")
+    f /= f.sum(dim=0, keepdim=True)
+    u = torch.rand((n, n), generator=g, device="cuda")
+    s = st.VarCoefStencil((n, n), "star", r)
+    got = s.apply(u, f, steps).cpu().numpy()
+    m = r * steps
+    errs = []
+    for s0, blk in [((0, 0), (16, 16)), ((4090, 2047), (6, 16)), ((1000, 4080), (16, 16))]:
+        idx = [torch.arange(a - m, a + b + m, device="cuda") % n for a, b in zip(s0, blk)]
+        yy, xx = torch.meshgrid(*idx, indexing="ij")
+        ref = oracle.varcoef_sweep(u[yy, xx].cpu().numpy(), f[:, yy, xx].cpu().numpy(), wl.STAR, r, wl.ZERO,
+                                   steps)[m:m + blk[0], m:m + blk[1]]
+        gb = got[np.ix_(*[np.arange(a, a + b) % n for a, b in zip(s0, blk)])]
+        errs.append(rel_l2(gb.astype(np.float64), ref))
+    print(f"varcoef2d star1 4096^2 x{steps} sampled rel-L2 {max(errs):.2e}")
+    assert max(errs) <= 1e-5
 
 
 def test_fullsize_wave3d(st):
