@@ -141,7 +141,13 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
                     if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[i]), &o[(uint32_t)(gy * nx + gx)]);
                 }
             }
-            if constexpr (NDIM == 3) load_coef(zo + 1);
+            if constexpr (NDIM == 3) {
+                // The box streams 27 fields: issuing them at raised wave
+                // priority measured 3 % faster (the 7-point star 2 % slower).
+                if constexpr (SHAPE == kBox) __builtin_amdgcn_s_setprio(3);
+                load_coef(zo + 1);
+                if constexpr (SHAPE == kBox) __builtin_amdgcn_s_setprio(0);
+            }
         }
         slot = slot + 1 == NR ? 0 : slot + 1;
     }
