@@ -57,8 +57,8 @@ typedef enum {
 
 /* Storage type of the grid.  ST_F32 and ST_F16 (IEEE binary16, rounded to
  * nearest even on every store) compute in f32; ST_F64 computes in f64 with
- * the f32 coefficient values widened exactly (linear and variable-coefficient
- * sweeps; not the wave update or batched plans).
+ * the f32 coefficient values widened exactly (linear sweeps, single and
+ * batched, and variable-coefficient sweeps; not the wave update).
  * Section 2.1 names f16/f32/f64 as the precision axis of a case. */
 typedef enum { ST_F32 = 0, ST_F16 = 1, ST_F64 = 2 } st_dtype;
 typedef enum { ST_PERIODIC = 0, ST_ZERO = 1 } st_boundary;

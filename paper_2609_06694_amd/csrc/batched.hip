@@ -45,7 +45,7 @@ struct GMember {
 };
 
 template <typename T, int BC, int RY, int R, int SHAPE>
-__device__ void grouped_member(const GMember& m, int round, int steps, int local, float* lds) {
+__device__ void grouped_member(const GMember& m, int round, int steps, int local, acc_t<T>* lds) {
     const int kl = min(m.k, steps - round * m.k);
     // Block j = round + 1 writes out if (L - j) is even, else the partner.
     const int j = round + 1;
@@ -58,7 +58,8 @@ __device__ void grouped_member(const GMember& m, int round, int steps, int local
 template <typename T, int BC, int RY>
 __global__ __launch_bounds__(kGroupThreads) void grouped_kernel(const GMember* __restrict__ ms, int nm,
                                                                 int round, int steps) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    acc_t<T>* lds = reinterpret_cast<acc_t<T>*>(lds_raw);   // member rings in the arithmetic type
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int lo = 0, hi = nm - 1;   // last member whose first workgroup is <= b
     while (lo < hi) {
@@ -114,8 +115,13 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Bytes of one storage value and of one ring value (the arithmetic type:
+// f64 for f64 storage, else f32).
+int storage_bytes(int dtype) { return dtype == ST_F16 ? 2 : (dtype == ST_F64 ? 8 : 4); }
+int ring_bytes(int dtype) { return dtype == ST_F64 ? 8 : 4; }
+
 size_t member_grid_bytes(const st_plan* m) {
-    return (size_t)m->prob.n[0] * m->prob.n[1] * (m->prob.dtype == ST_F16 ? 2 : 4);
+    return (size_t)m->prob.n[0] * m->prob.n[1] * storage_bytes(m->prob.dtype);
 }
 
 // Fused depth of member m in a grouped launch: the batch depth, within the
@@ -124,7 +130,7 @@ int member_depth(const st_plan* m, int kbatch) {
     const int r = m->prob.radius;
     int k = std::min(16, std::max(1, kbatch));
     while (k > 1 && (kGroupThreads - 2 * k * r < kWave ||
-                     (int)sizeof(float) * k * ym2d_ring_rows(4, r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
+                     ring_bytes(m->prob.dtype) * k * ym2d_ring_rows(4, r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
         --k;
     return k;
 }
@@ -164,7 +170,7 @@ Layout layout(const st_plan* plan, int steps, int cus) {
         b.ych = std::min(ych, b.ny);
         b.taps = m->taps;
         lay.rounds = std::max(lay.rounds, b.L);
-        if ((int)sizeof(float) * b.k * ym2d_ring_rows(8, b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
+        if (ring_bytes(m->prob.dtype) * b.k * ym2d_ring_rows(8, b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
         lay.members.push_back(b);
     }
     // Eight input rows per iteration unless a member's rings would outgrow
@@ -177,7 +183,8 @@ Layout layout(const st_plan* plan, int steps, int cus) {
         b.ych = ym2d_fill_chunk(b.ych, b.k * b.r, lay.ry, b.ny);
         b.first = lay.grid;
         lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
-        lay.lds = std::max(lay.lds, sizeof(float) * (size_t)b.k * ym2d_ring_rows(lay.ry, b.r) * (kGroupThreads + 2 * b.r));
+        lay.lds = std::max(lay.lds, (size_t)ring_bytes(plan->prob.dtype) * b.k * ym2d_ring_rows(lay.ry, b.r) *
+                                        (kGroupThreads + 2 * b.r));
     }
     return lay;
 }
@@ -233,10 +240,6 @@ st_status stencil_plan_batched(const st_problem* problems, int32_t count, const 
         if (p.ndim != 2 || p.update != ST_LINEAR) {
             stencil_plan_destroy(pl);
             B_FAIL(ST_EUNSUPPORTED, "batched member %d: only 2D linear sweeps are batched", i);
-        }
-        if (p.dtype == ST_F64) {
-            stencil_plan_destroy(pl);
-            B_FAIL(ST_EUNSUPPORTED, "batched member %d: f64 storage is not batched", i);
         }
         if (p.dtype != problems[0].dtype || p.boundary != problems[0].boundary) {
             stencil_plan_destroy(pl);
@@ -319,9 +322,10 @@ st_status stencil_apply_batched(const st_plan* plan, const void* const* u_in, vo
 
     const int bc = plan->prob.boundary;
     for (int round = 0; round < lay.rounds; ++round) {
-        hipError_t e = plan->prob.dtype == ST_F16
-                           ? launch_round_t<_Float16>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
-                           : launch_round_t<float>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s);
+        const int dt = plan->prob.dtype;
+        hipError_t e = dt == ST_F16   ? launch_round_t<_Float16>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
+                       : dt == ST_F64 ? launch_round_t<double>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
+                                      : launch_round_t<float>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s);
         if (e != hipSuccess) B_FAIL(ST_EHIP, "batched launch %d failed: %s", round, hipGetErrorString(e));
     }
     return ST_OK;

@@ -239,9 +239,9 @@ def test_f64_plan_uses_zmarch_with_short_tiles(L):
     L.stencil_plan_destroy(h)
 
 
-def test_f64_2d_plan_uses_row_march_and_batch_rejects_f64(L):
+def test_f64_2d_plan_uses_row_march_and_batches(L):
     """2D f64 sweeps go to the row march (the only 2D family with an f64
-    path); a batched plan refuses f64 members."""
+    path); a batched plan accepts f64 members, and needs them all f64."""
     p, keep = _prob(ndim=2, n=(300, 200, 1), shape=0, r=2, dtype=2)
     st, h = _plan(L, p)
     assert st == _abi.ST_OK, L.stencil_last_error()
@@ -251,5 +251,10 @@ def test_f64_2d_plan_uses_row_march_and_batch_rejects_f64(L):
     L.stencil_plan_destroy(h)
     arr = (_abi.StProblem * 2)(p, p)
     hb = ctypes.c_void_p()
-    assert L.stencil_plan_batched(arr, 2, None, ctypes.byref(hb)) == _abi.ST_EUNSUPPORTED
+    assert L.stencil_plan_batched(arr, 2, None, ctypes.byref(hb)) == _abi.ST_OK, L.stencil_last_error()
+    L.stencil_plan_destroy(hb)
+    p32, keep32 = _prob(ndim=2, n=(300, 200, 1), shape=0, r=2, dtype=0)
+    arr = (_abi.StProblem * 2)(p, p32)
+    hb = ctypes.c_void_p()
+    assert L.stencil_plan_batched(arr, 2, None, ctypes.byref(hb)) == _abi.ST_EINVAL
     assert not hb.value

@@ -597,12 +597,12 @@ def _batched_cases(count, lo, hi, steps, seed, dtype=np.float32):
     return cases
 
 
-@pytest.mark.parametrize("dtype,bc", [("f32", "periodic"), ("f16", "zero")])
+@pytest.mark.parametrize("dtype,bc", [("f32", "periodic"), ("f16", "zero"), ("f64", "periodic"), ("f64", "zero")])
 def test_batched_matches_plain_and_oracle(st, dtype, bc):
     """Every member of a grouped batch equals the oracle and its own
     single-grid plan; in place with odd and even block counts; members
     with different fused depths (so some finish before the last launch)."""
-    npdt = np.float32 if dtype == "f32" else np.float16
+    npdt = {"f32": np.float32, "f16": np.float16, "f64": np.float64}[dtype]
     cases = _batched_cases(10, 64, 400, 7, 9, npdt)
     bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
     spec = [dict(n=c.n[:2], shape=c.shape, radius=c.radius, coeffs=c.coeffs, dtype=dtype, boundary=bc)
