@@ -131,3 +131,16 @@ def test_autotune_f64(st):
     assert stats3["rejected"] == 0 and d3["variant"] == "zm3d" and d3["tsteps"] <= 1 and d3["tile_y"] in (8, 16)
     got3 = s3.apply(torch.from_numpy(u3).cuda(), 3).cpu().numpy()
     assert rel_l2(got3, oracle.sweep(u3, c3, wl.STAR, 2, wl.ZERO, 3)) <= 1e-12
+    # A batch of f64 grids: member cases and the grouped depth are tuned at
+    # the f64 gate, and the tuned batch keeps it.
+    cases = wl.batch2d(count=4, lo=96, hi=260, steps=6, seed=66)
+    for cb in cases:
+        cb.u0 = cb.u0.astype(np.float64)
+    bs = st.BatchedStencil([dict(n=cb.n[:2], shape=cb.shape, radius=cb.radius, coeffs=cb.coeffs, dtype="f64")
+                            for cb in cases])
+    statsb = bs.autotune()
+    print("f64 batch tuned:", bs.describe(), statsb)
+    assert statsb["rejected"] == 0 and bs.describe()["variant"] == "ym2d"
+    outs = bs.apply([torch.from_numpy(cb.u0).cuda() for cb in cases], 6)
+    for cb, o in zip(cases, outs):
+        assert rel_l2(o.cpu().numpy(), oracle.sweep(cb.u0, cb.coeffs, cb.shape, cb.radius, wl.PERIODIC, 6)) <= 1e-12
