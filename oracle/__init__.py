@@ -53,6 +53,11 @@ def _load():
     lib.oracle_varcoef_taps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_varcoef_sweep.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _dp,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.oracle_round_storage.argtypes = [_dp, ctypes.c_int64, ctypes.c_int]
+    lib.oracle_sweep_stored.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _dp,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.oracle_wave_forward_stored.argtypes = lib.oracle_wave_forward.argtypes + [ctypes.c_int]
+    lib.oracle_wave_gradient_stored.argtypes = lib.oracle_wave_gradient.argtypes + [ctypes.c_int]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -82,6 +87,24 @@ def _check(rc: int, what: str):
         raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
 
 
+# Storage formats of the floor diagnostic: every stored state is rounded to
+# the format (nearest, ties to even); None means exact FP64.
+STORAGE = {None: 0, "binary32": 1, "binary16": 2}
+
+
+def _storage(name) -> int:
+    if name not in STORAGE:
+        raise ValueError(f"storage must be one of {sorted(k for k in STORAGE if k)} or None")
+    return STORAGE[name]
+
+
+def round_storage(u, storage) -> np.ndarray:
+    """u rounded to the storage format (a float64 copy)."""
+    a = _f64(u).copy()
+    _check(_load().oracle_round_storage(_ptr(a), a.size, _storage(storage)), "round_storage")
+    return a
+
+
 def set_threads(n: int) -> None:
     _load().oracle_set_threads(int(n))
 
@@ -91,8 +114,10 @@ def max_threads() -> int:
 
 
 def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, r: int, boundary: int,
-          steps: int, adjoint: bool = False) -> np.ndarray:
-    """`steps` applications of the linear stencil (or its transpose) to u."""
+          steps: int, adjoint: bool = False, storage=None) -> np.ndarray:
+    """`steps` applications of the linear stencil (or its transpose) to u.
+    storage="binary16"/"binary32" rounds every step's result to that format
+    (the floor diagnostic; forward sweep only)."""
     lib = _load()
     u64 = _f64(u)
     c64 = _f64(coeffs)
@@ -100,6 +125,12 @@ def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, r: int, boundary: 
     if c64.size != (2 * r + 1) ** ndim:
         raise ValueError("coefficient array must be dense (2r+1)^ndim")
     out = np.empty_like(u64)
+    if storage is not None:
+        if adjoint:
+            raise ValueError("the storage diagnostic covers the forward sweep")
+        _check(lib.oracle_sweep_stored(ndim, _n3(u64.shape), shape, r, _ptr(c64), boundary, steps,
+                                       _storage(storage), _ptr(u64), _ptr(out)), "sweep_stored")
+        return out
     fn = lib.oracle_sweep_adjoint if adjoint else lib.oracle_sweep
     _check(fn(ndim, _n3(u64.shape), shape, r, _ptr(c64), boundary, steps, _ptr(u64), _ptr(out)),
            "sweep")
@@ -146,8 +177,9 @@ def laplacian3d(r: int = 4) -> np.ndarray:
 
 def wave_forward(u_prev, u0, kappa, steps: int, r: int = 4, boundary: int = 1,
                  lap: Optional[np.ndarray] = None, src=None, wavelet=None,
-                 rec_z: int = -1):
-    """Leapfrog forward.  Returns (u_{T-1}, u_T, traces or None)."""
+                 rec_z: int = -1, storage=None):
+    """Leapfrog forward.  Returns (u_{T-1}, u_T, traces or None).
+    storage="binary32"/"binary16" rounds every new state (floor diagnostic)."""
     lib = _load()
     a = _f64(u_prev).copy()
     b = _f64(u0).copy()
@@ -157,10 +189,12 @@ def wave_forward(u_prev, u0, kappa, steps: int, r: int = 4, boundary: int = 1,
     srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
     wv = _f64(wavelet) if wavelet is not None else None
     traces = np.zeros((steps, ny, nx), dtype=np.float64) if rec_z >= 0 else None
-    _check(lib.oracle_wave_forward(_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k),
-                                   _ptr(a), _ptr(b), srcp, _ptr(wv) if wv is not None else None,
-                                   rec_z, _ptr(traces) if traces is not None else None),
-           "wave_forward")
+    args = (_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k), _ptr(a), _ptr(b), srcp,
+            _ptr(wv) if wv is not None else None, rec_z, _ptr(traces) if traces is not None else None)
+    if storage is None:
+        _check(lib.oracle_wave_forward(*args), "wave_forward")
+    else:
+        _check(lib.oracle_wave_forward_stored(*args, _storage(storage)), "wave_forward_stored")
     return a, b, traces
 
 
@@ -180,8 +214,10 @@ def wave_adjoint(a_in, b_in, kappa, steps: int, r: int = 4, boundary: int = 1,
 
 def wave_gradient(u_prev0, u0, kappa, steps: int, src, wavelet, rec_z: int, target,
                   ckpt_every: int = 0, r: int = 4, boundary: int = 1,
-                  lap: Optional[np.ndarray] = None):
-    """(dJ/dkappa, J) for J = 1/2 sum_t ||u_t[rec_z] - target[t-1]||^2."""
+                  lap: Optional[np.ndarray] = None, storage=None):
+    """(dJ/dkappa, J) for J = 1/2 sum_t ||u_t[rec_z] - target[t-1]||^2.
+    storage="binary32" rounds every stored state, co-state and the running
+    gradient (floor diagnostic)."""
     lib = _load()
     k = _f64(kappa)
     up = _f64(u_prev0)
@@ -192,8 +228,10 @@ def wave_gradient(u_prev0, u0, kappa, steps: int, src, wavelet, rec_z: int, targ
     grad = np.empty_like(k)
     loss = ctypes.c_double(0.0)
     srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
-    _check(lib.oracle_wave_gradient(_n3(k.shape), r, _ptr(lp), boundary, steps, _ptr(k),
-                                    _ptr(up), _ptr(u), srcp, _ptr(wv), rec_z, _ptr(tg),
-                                    ckpt_every, _ptr(grad), ctypes.byref(loss)),
-           "wave_gradient")
+    args = (_n3(k.shape), r, _ptr(lp), boundary, steps, _ptr(k), _ptr(up), _ptr(u), srcp, _ptr(wv),
+            rec_z, _ptr(tg), ckpt_every, _ptr(grad), ctypes.byref(loss))
+    if storage is None:
+        _check(lib.oracle_wave_gradient(*args), "wave_gradient")
+    else:
+        _check(lib.oracle_wave_gradient_stored(*args, _storage(storage)), "wave_gradient_stored")
     return grad, float(loss.value)

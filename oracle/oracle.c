@@ -22,6 +22,10 @@
  *    with its own checkpoint/recompute loop.
  *  - Central second-difference weights of order 2r from the Taylor moment
  *    conditions.
+ *  - A diagnostic of the numerical floor: the same sweeps with every stored
+ *    state rounded to binary32 or binary16 (FP64 arithmetic otherwise), to
+ *    set a storage format's measured error against the error that format
+ *    alone must incur.
  *
  * Conventions: x is unit stride; a 3D array is [nz][ny][nx]; n[0]=nx,
  * n[1]=ny, n[2]=nz (nz=1 in 2D).  Coefficients are a dense (2r+1)^ndim
@@ -61,6 +65,52 @@ static int offset_in_shape(int shape, int dz, int dy, int dx) {
 
 static int64_t wrap(int64_t i, int64_t n) { return ((i % n) + n) % n; }
 
+/*
+ * Storage-rounding diagnostic (not used by the gate results).  Storing a
+ * value in a binary floating-point format with p significant bits, minimum
+ * normal exponent emin and largest finite value maxfin keeps the multiple
+ * of the format's spacing at that magnitude nearest to it, ties to the even
+ * multiple (IEEE 754 round-to-nearest-even); below 2^emin the spacing stays
+ * 2^(emin-p+1) (gradual underflow), and a result beyond maxfin overflows to
+ * infinity.  binary32: p = 24, emin = -126; binary16: p = 11, emin = -14.
+ * Running a sweep with every stored state rounded this way measures the
+ * error floor that the storage format alone imposes (FP64 arithmetic
+ * otherwise).
+ */
+#define OR_STORE_EXACT 0
+#define OR_STORE_BINARY32 1
+#define OR_STORE_BINARY16 2
+
+static double round_to_format(double x, int p, int emin, double maxfin) {
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);                 /* |x| in [2^(e-1), 2^e) */
+    int lead = e - 1;
+    if (lead < emin) lead = emin;
+    const double spacing = ldexp(1.0, lead - (p - 1));
+    const double q = nearbyint(x / spacing) * spacing;   /* x / spacing is exact */
+    if (fabs(q) > maxfin) return copysign(INFINITY, x);
+    return q;
+}
+
+static double store_round(double x, int storage) {
+    if (storage == OR_STORE_BINARY32) return round_to_format(x, 24, -126, 3.4028234663852886e38);
+    if (storage == OR_STORE_BINARY16) return round_to_format(x, 11, -14, 65504.0);
+    return x;
+}
+
+static void store_round_all(double *u, int64_t count, int storage) {
+    if (storage == OR_STORE_EXACT) return;
+    for (int64_t i = 0; i < count; ++i) u[i] = store_round(u[i], storage);
+}
+
+/* Rounds `count` values in place to the storage format (0 = unchanged). */
+int oracle_round_storage(double *u, int64_t count, int storage) {
+    if (storage < OR_STORE_EXACT || storage > OR_STORE_BINARY16 || count < 0) return -11;
+    store_round_all(u, count, storage);
+    return 0;
+}
+
 /* u at (z,y,x) under the boundary rule. */
 static double fetch(const double *u, const int64_t n[3], int boundary,
                     int64_t z, int64_t y, int64_t x) {
@@ -84,26 +134,34 @@ static int check_args(int ndim, const int64_t n[3], int shape, int r, int bounda
     return 0;
 }
 
-/* out(x) = sum_{d in S} c_d in(B(x + sign*d)); sign = -1 gives the transpose. */
+/* out(x) = sum_{d in S} c_d in(B(x + sign*d)); sign = -1 gives the transpose.
+ * The offsets of S are listed once, in (dz,dy,dx) lexicographic order, and
+ * every cell sums its terms in that order. */
 static void apply_once(int ndim, const int64_t n[3], int shape, int r,
                        const double *c, int boundary, int sign,
                        const double *in, double *out) {
     const int rz = (ndim == 3) ? r : 0;
     const int w = 2 * r + 1;
     const int64_t nz = n[2], ny = n[1], nx = n[0];
+    int d[17 * 17 * 17][3];
+    double cd[17 * 17 * 17];
+    int nt = 0;
+    for (int dz = -rz; dz <= rz; ++dz)
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+                if (!offset_in_shape(shape, dz, dy, dx)) continue;
+                d[nt][0] = dz; d[nt][1] = dy; d[nt][2] = dx;
+                cd[nt] = c[((dz + rz) * w + (dy + r)) * w + (dx + r)];
+                ++nt;
+            }
 #pragma omp parallel for collapse(2) schedule(static) num_threads(oracle_max_threads())
     for (int64_t z = 0; z < nz; ++z) {
         for (int64_t y = 0; y < ny; ++y) {
             for (int64_t x = 0; x < nx; ++x) {
                 double acc = 0.0;
-                for (int dz = -rz; dz <= rz; ++dz)
-                    for (int dy = -r; dy <= r; ++dy)
-                        for (int dx = -r; dx <= r; ++dx) {
-                            if (!offset_in_shape(shape, dz, dy, dx)) continue;
-                            const double cd = c[((dz + rz) * w + (dy + r)) * w + (dx + r)];
-                            acc += cd * fetch(in, n, boundary, z + sign * dz,
-                                              y + sign * dy, x + sign * dx);
-                        }
+                for (int k = 0; k < nt; ++k)
+                    acc += cd[k] * fetch(in, n, boundary, z + sign * d[k][0],
+                                         y + sign * d[k][1], x + sign * d[k][2]);
                 out[(z * ny + y) * nx + x] = acc;
             }
         }
@@ -114,11 +172,12 @@ static int64_t cells_of(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 
 /* `steps` forward (sign=+1) or transposed (sign=-1) sweeps of u_in into u_out. */
 static int sweep_common(int ndim, const int64_t n[3], int shape, int r,
-                        const double *c, int boundary, int steps, int sign,
+                        const double *c, int boundary, int steps, int sign, int storage,
                         const double *u_in, double *u_out) {
     int e = check_args(ndim, n, shape, r, boundary);
     if (e) return e;
     if (steps < 0) return -6;
+    if (storage < OR_STORE_EXACT || storage > OR_STORE_BINARY16) return -11;
     const int64_t cells = cells_of(n);
     double *a = (double *)malloc(sizeof(double) * (size_t)cells);
     double *b = (double *)malloc(sizeof(double) * (size_t)cells);
@@ -126,6 +185,7 @@ static int sweep_common(int ndim, const int64_t n[3], int shape, int r,
     memcpy(a, u_in, sizeof(double) * (size_t)cells);
     for (int t = 0; t < steps; ++t) {
         apply_once(ndim, n, shape, r, c, boundary, sign, a, b);
+        store_round_all(b, cells, storage);
         double *tmp = a; a = b; b = tmp;
     }
     memcpy(u_out, a, sizeof(double) * (size_t)cells);
@@ -136,12 +196,19 @@ static int sweep_common(int ndim, const int64_t n[3], int shape, int r,
 
 int oracle_sweep(int ndim, const int64_t n[3], int shape, int r, const double *c,
                  int boundary, int steps, const double *u_in, double *u_out) {
-    return sweep_common(ndim, n, shape, r, c, boundary, steps, +1, u_in, u_out);
+    return sweep_common(ndim, n, shape, r, c, boundary, steps, +1, OR_STORE_EXACT, u_in, u_out);
 }
 
 int oracle_sweep_adjoint(int ndim, const int64_t n[3], int shape, int r, const double *c,
                          int boundary, int steps, const double *v_in, double *v_out) {
-    return sweep_common(ndim, n, shape, r, c, boundary, steps, -1, v_in, v_out);
+    return sweep_common(ndim, n, shape, r, c, boundary, steps, -1, OR_STORE_EXACT, v_in, v_out);
+}
+
+/* The forward sweep with every step's result rounded to the storage format
+ * (diagnostic floor; storage 0 is oracle_sweep). */
+int oracle_sweep_stored(int ndim, const int64_t n[3], int shape, int r, const double *c,
+                        int boundary, int steps, int storage, const double *u_in, double *u_out) {
+    return sweep_common(ndim, n, shape, r, c, boundary, steps, +1, storage, u_in, u_out);
 }
 
 /*
@@ -288,13 +355,15 @@ int oracle_laplacian3d(int r, double *dense) {
 /* One leapfrog step: next = 2 cur - prev + kappa * L(cur); then the source. */
 static void wave_step(const int64_t n[3], int r, const double *lap, int boundary,
                       const double *kappa, const double *prev, const double *cur,
-                      double *next, double *scratch, const int64_t *src, double amp) {
+                      double *next, double *scratch, const int64_t *src, double amp,
+                      int storage) {
     const int64_t cells = cells_of(n);
     apply_once(3, n, OR_STAR, r, lap, boundary, +1, cur, scratch);
 #pragma omp parallel for schedule(static) num_threads(oracle_max_threads())
     for (int64_t i = 0; i < cells; ++i)
         next[i] = 2.0 * cur[i] - prev[i] + kappa[i] * scratch[i];
     if (src) next[(src[2] * n[1] + src[1]) * n[0] + src[0]] += amp;
+    store_round_all(next, cells, storage);
 }
 
 static int check_wave(const int64_t n[3], int r, int boundary, const int64_t *src, int64_t rec_z) {
@@ -313,13 +382,14 @@ static int check_wave(const int64_t n[3], int r, int boundary, const int64_t *sr
  * the plane z = rec_z of u_{t+1} (after the source), t = 0..T-1.
  * lap is the dense (2r+1)^3 star coefficient array of L.
  */
-int oracle_wave_forward(const int64_t n[3], int r, const double *lap, int boundary,
-                        int steps, const double *kappa, double *u_prev, double *u_cur,
-                        const int64_t *src, const double *wavelet, int64_t rec_z,
-                        double *traces) {
+static int wave_forward_common(const int64_t n[3], int r, const double *lap, int boundary,
+                               int steps, const double *kappa, double *u_prev, double *u_cur,
+                               const int64_t *src, const double *wavelet, int64_t rec_z,
+                               double *traces, int storage) {
     int e = check_wave(n, r, boundary, src, rec_z);
     if (e) return e;
     if (steps < 0) return -6;
+    if (storage < OR_STORE_EXACT || storage > OR_STORE_BINARY16) return -11;
     const int64_t cells = cells_of(n), plane = n[0] * n[1];
     double *a = (double *)malloc(sizeof(double) * (size_t)cells);
     double *b = (double *)malloc(sizeof(double) * (size_t)cells);
@@ -329,7 +399,7 @@ int oracle_wave_forward(const int64_t n[3], int r, const double *lap, int bounda
     memcpy(a, u_prev, sizeof(double) * (size_t)cells);
     memcpy(b, u_cur, sizeof(double) * (size_t)cells);
     for (int t = 0; t < steps; ++t) {
-        wave_step(n, r, lap, boundary, kappa, a, b, c, s, src, src ? wavelet[t] : 0.0);
+        wave_step(n, r, lap, boundary, kappa, a, b, c, s, src, src ? wavelet[t] : 0.0, storage);
         if (rec_z >= 0) memcpy(traces + (int64_t)t * plane, c + rec_z * plane, sizeof(double) * (size_t)plane);
         double *tmp = a; a = b; b = c; c = tmp;
     }
@@ -337,6 +407,24 @@ int oracle_wave_forward(const int64_t n[3], int r, const double *lap, int bounda
     memcpy(u_cur, b, sizeof(double) * (size_t)cells);
     free(a); free(b); free(c); free(s);
     return 0;
+}
+
+int oracle_wave_forward(const int64_t n[3], int r, const double *lap, int boundary,
+                        int steps, const double *kappa, double *u_prev, double *u_cur,
+                        const int64_t *src, const double *wavelet, int64_t rec_z,
+                        double *traces) {
+    return wave_forward_common(n, r, lap, boundary, steps, kappa, u_prev, u_cur, src, wavelet,
+                               rec_z, traces, OR_STORE_EXACT);
+}
+
+/* The leapfrog with every new state rounded to the storage format
+ * (diagnostic floor; storage 0 is oracle_wave_forward). */
+int oracle_wave_forward_stored(const int64_t n[3], int r, const double *lap, int boundary,
+                               int steps, const double *kappa, double *u_prev, double *u_cur,
+                               const int64_t *src, const double *wavelet, int64_t rec_z,
+                               double *traces, int storage) {
+    return wave_forward_common(n, r, lap, boundary, steps, kappa, u_prev, u_cur, src, wavelet,
+                               rec_z, traces, storage);
 }
 
 /*
@@ -387,15 +475,16 @@ int oracle_wave_adjoint(const int64_t n[3], int r, const double *lap, int bounda
  * every `ckpt_every` steps (0 = keep every state).  Outputs grad (cells) and
  * *loss.
  */
-int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int boundary,
-                         int steps, const double *kappa, const double *u_prev0,
-                         const double *u0, const int64_t *src, const double *wavelet,
-                         int64_t rec_z, const double *target, int ckpt_every,
-                         double *grad, double *loss) {
+static int wave_gradient_common(const int64_t n[3], int r, const double *lap, int boundary,
+                                int steps, const double *kappa, const double *u_prev0,
+                                const double *u0, const int64_t *src, const double *wavelet,
+                                int64_t rec_z, const double *target, int ckpt_every,
+                                double *grad, double *loss, int storage) {
     int e = check_wave(n, r, boundary, src, rec_z);
     if (e) return e;
     if (rec_z < 0) return -10;
     if (steps < 1) return -6;
+    if (storage < OR_STORE_EXACT || storage > OR_STORE_BINARY16) return -11;
     const int64_t cells = cells_of(n), plane = n[0] * n[1];
     const int T = steps;
     const int K = (ckpt_every <= 0 || ckpt_every > T) ? T : ckpt_every;
@@ -426,7 +515,7 @@ int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int bound
             memcpy(ck + (size_t)cells * 2 * (size_t)(t / K), p0, sizeof(double) * (size_t)cells);
             memcpy(ck + (size_t)cells * (2 * (size_t)(t / K) + 1), p1, sizeof(double) * (size_t)cells);
         }
-        wave_step(n, r, lap, boundary, kappa, p0, p1, p2, s, src, src ? wavelet[t] : 0.0);
+        wave_step(n, r, lap, boundary, kappa, p0, p1, p2, s, src, src ? wavelet[t] : 0.0, storage);
         const double *d = target + (int64_t)t * plane;
         const double *pl = p2 + rec_z * plane;
         for (int64_t i = 0; i < plane; ++i) J += 0.5 * (pl[i] - d[i]) * (pl[i] - d[i]);
@@ -447,14 +536,14 @@ int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int bound
             const int j = t - t0 + 1;
             wave_step(n, r, lap, boundary, kappa, states + (size_t)cells * (j - 1),
                       states + (size_t)cells * j, states + (size_t)cells * (j + 1), s,
-                      src, src ? wavelet[t] : 0.0);
+                      src, src ? wavelet[t] : 0.0, storage);
         }
         const int tstart = (seg == nseg - 1) ? T : t1 - 1;
         for (int t = tstart; t >= t0; --t) {
             const double *ut = states + (size_t)cells * (t - t0 + 1);
             /* gradient term lambda_{t+1} (.) L(u_t) */
             apply_once(3, n, OR_STAR, r, lap, boundary, +1, ut, s);
-            for (int64_t i = 0; i < cells; ++i) grad[i] += l1[i] * s[i];
+            for (int64_t i = 0; i < cells; ++i) grad[i] = store_round(grad[i] + l1[i] * s[i], storage);
             if (t >= 1) {
                 for (int64_t i = 0; i < cells; ++i) kl[i] = kappa[i] * l1[i];
                 apply_once(3, n, OR_STAR, r, lap, boundary, -1, kl, s);
@@ -463,6 +552,7 @@ int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int bound
                 const double *pl = ut + rec_z * plane;
                 double *lp = l0 + rec_z * plane;
                 for (int64_t i = 0; i < plane; ++i) lp[i] += pl[i] - d[i];
+                store_round_all(l0, cells, storage);
                 double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
             }
         }
@@ -470,4 +560,25 @@ int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int bound
     free(ck); free(states); free(l2); free(l1); free(l0); free(kl); free(s);
     free(p0); free(p1); free(p2);
     return 0;
+}
+
+int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int boundary,
+                         int steps, const double *kappa, const double *u_prev0,
+                         const double *u0, const int64_t *src, const double *wavelet,
+                         int64_t rec_z, const double *target, int ckpt_every,
+                         double *grad, double *loss) {
+    return wave_gradient_common(n, r, lap, boundary, steps, kappa, u_prev0, u0, src, wavelet,
+                                rec_z, target, ckpt_every, grad, loss, OR_STORE_EXACT);
+}
+
+/* The gradient with every stored state (u_t, lambda_t and the running
+ * gradient) rounded to the storage format (diagnostic floor; storage 0 is
+ * oracle_wave_gradient). */
+int oracle_wave_gradient_stored(const int64_t n[3], int r, const double *lap, int boundary,
+                                int steps, const double *kappa, const double *u_prev0,
+                                const double *u0, const int64_t *src, const double *wavelet,
+                                int64_t rec_z, const double *target, int ckpt_every,
+                                double *grad, double *loss, int storage) {
+    return wave_gradient_common(n, r, lap, boundary, steps, kappa, u_prev0, u0, src, wavelet,
+                                rec_z, target, ckpt_every, grad, loss, storage);
 }

@@ -378,3 +378,118 @@ def test_varcoef_transpose_column_sums(oracle_lib, ndim, kind, r):
     assert abs(ATv.sum() - (f.sum(axis=0) * v).sum()) <= 1e-11 * np.abs(f).sum()
     Au = oracle_lib.varcoef_sweep(u, f, kind, r, PERIODIC, 1)
     assert abs(np.vdot(Au, v) - np.vdot(u, ATv)) <= 1e-12 * np.linalg.norm(Au) * np.linalg.norm(v)
+
+
+# ---- Storage-rounding diagnostic (the numerical floor of a storage format) ----
+
+def _format_probe_values(rng, fmt):
+    """Values spanning normals, subnormals, exact ties and overflow of the
+    format: random magnitudes, plus midpoints between neighbouring values
+    (where ties-to-even decides) and values around the overflow threshold."""
+    if fmt == "binary16":
+        p, emin, top = 11, -14, 65504.0
+    else:
+        p, emin, top = 24, -126, float(np.finfo(np.float32).max)
+    mags = np.exp(rng.uniform(np.log(2.0 ** (emin - p)), np.log(top), 4000))
+    vals = list(mags * rng.choice([-1.0, 1.0], mags.size))
+    for e in (emin - 3, emin, 0, 5):   # midpoints: (k + 1/2) ulp above 2^e (subnormal below emin)
+        lead = max(e, emin)
+        ulp = 2.0 ** (lead - p + 1)
+        for k in (0, 1, 2, 3, 1000):
+            vals += [2.0 ** e + (k + 0.5) * ulp if e >= emin else (k + 0.5) * ulp]
+    vals += [top, -top, top * (1 + 2.0 ** -(p + 1)) * 0.999999, 1e300, -1e300, 0.0, -0.0]
+    if fmt == "binary16":
+        vals += [65519.0, 65520.0, -65520.0, 65536.0]
+    return np.array(vals, dtype=np.float64)
+
+
+@pytest.mark.parametrize("fmt,npdt", [("binary16", np.float16), ("binary32", np.float32)])
+def test_round_storage_matches_numpy_casts(oracle_lib, fmt, npdt):
+    """The oracle's rounding to a storage format, written from the format's
+    definition, agrees with numpy's float64 -> float16/float32 conversion on
+    normals, subnormals, exact ties and overflow."""
+    x = _format_probe_values(np.random.default_rng(5), fmt)
+    with np.errstate(over="ignore"):
+        ref = x.astype(npdt).astype(np.float64)
+    got = oracle_lib.round_storage(x, fmt)
+    assert np.array_equal(got, ref, equal_nan=True)
+    assert np.array_equal(np.signbit(got), np.signbit(ref))
+
+
+@pytest.mark.parametrize("ndim,kind,r,n", [(2, BOX, 2, (23, 19)), (3, BOX, 1, (9, 8, 7)), (3, STAR, 4, (10, 9, 11))])
+def test_stored_sweep_rounds_every_step(oracle_lib, ndim, kind, r, n):
+    """The binary16 floor sweep equals single exact steps each followed by
+    numpy's binary16 rounding, and the exact mode equals the plain sweep."""
+    rng = np.random.default_rng(61)
+    c = _rand_coeffs(rng, ndim, kind, r)
+    u = rng.random(n).astype(np.float16).astype(np.float64)
+    T = 4
+    v = u
+    for _ in range(T):
+        v = oracle_lib.sweep(v, c, kind, r, PERIODIC, 1).astype(np.float16).astype(np.float64)
+    got = oracle_lib.sweep(u, c, kind, r, PERIODIC, T, storage="binary16")
+    assert np.array_equal(got, v)
+    import ctypes
+    lib = oracle_lib._load()
+    c64, u64 = np.ascontiguousarray(c, dtype=np.float64), np.ascontiguousarray(u)
+    out0 = np.empty_like(u64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    nn = (n[1], n[0], 1) if ndim == 2 else (n[2], n[1], n[0])
+    assert lib.oracle_sweep_stored(ndim, (ctypes.c_int64 * 3)(*nn), kind, r, c64.ctypes.data_as(dp), ZERO, T, 0,
+                                   u64.ctypes.data_as(dp), out0.ctypes.data_as(dp)) == 0
+    assert np.array_equal(out0, oracle_lib.sweep(u, c, kind, r, ZERO, T))
+    exact = oracle_lib.sweep(u, c, kind, r, PERIODIC, T)
+    assert not np.array_equal(got, exact)
+
+
+def test_stored_wave_forward_rounds_every_state(oracle_lib):
+    """The binary32 floor leapfrog equals exact single steps (source
+    included) each followed by numpy's binary32 rounding."""
+    rng = np.random.default_rng(67)
+    n = (9, 8, 10)
+    kappa = rng.uniform(0.05, 0.2, n[::-1]).astype(np.float32).astype(np.float64)
+    u0 = rng.standard_normal(n[::-1]).astype(np.float32).astype(np.float64)
+    up = rng.standard_normal(n[::-1]).astype(np.float32).astype(np.float64)
+    T, src, rec = 5, (4, 3, 6), 2
+    wav = wl.ricker(T, 3.0).astype(np.float64)
+    a, b = up, u0
+    tr = []
+    for t in range(T):
+        _, nb, trt = oracle_lib.wave_forward(a, b, kappa, 1, src=src, wavelet=wav[t:t + 1], rec_z=rec)
+        a, b = b, nb.astype(np.float32).astype(np.float64)
+        tr.append(b[rec])
+    ga, gb, gtr = oracle_lib.wave_forward(up, u0, kappa, T, src=src, wavelet=wav, rec_z=rec, storage="binary32")
+    assert np.array_equal(ga, a) and np.array_equal(gb, b) and np.array_equal(gtr, np.stack(tr))
+
+
+def test_stored_gradient_exact_mode_and_floor_size(oracle_lib):
+    """The gradient's floor diagnostic: mode 0 of the stored entry point is
+    the exact gradient bit for bit; binary32 storage moves it by a small
+    nonzero amount (order of the format's precision times the conditioning)."""
+    import ctypes
+    import oracle
+    rng = np.random.default_rng(71)
+    n = (12, 11, 13)
+    T = 16
+    kappa, zeros, src, wav, rec, target = _grad_problem(rng, n, T)
+    kappa = kappa.astype(np.float32).astype(np.float64)
+    target = target.astype(np.float32).astype(np.float64)
+    g, J = oracle_lib.wave_gradient(zeros, zeros, kappa, T, src, wav, rec, target, ckpt_every=5)
+    lib = oracle._load()
+    lp = oracle.laplacian3d(4)
+    g0 = np.empty_like(kappa)
+    J0 = ctypes.c_double()
+    i64 = ctypes.c_int64 * 3
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.oracle_wave_gradient_stored(i64(n[2], n[1], n[0]), 4, lp.ctypes.data_as(dp), 1, T,
+                                           kappa.ctypes.data_as(dp), zeros.ctypes.data_as(dp),
+                                           zeros.ctypes.data_as(dp), i64(*src), wav.ctypes.data_as(dp), rec,
+                                           target.ctypes.data_as(dp), 5, g0.ctypes.data_as(dp),
+                                           ctypes.byref(J0), 0) == 0
+    assert np.array_equal(g0, g) and J0.value == J
+    g32, J32 = oracle_lib.wave_gradient(zeros, zeros, kappa, T, src, wav, rec, target, ckpt_every=5,
+                                        storage="binary32")
+    e = mr.rel_l2(g32, g)
+    assert 0 < e < 1e-3
+    with pytest.raises(ValueError):
+        oracle_lib.wave_gradient(zeros, zeros, kappa, T, src, wav, rec, target, storage="binary8")
