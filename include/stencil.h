@@ -149,6 +149,18 @@ size_t stencil_workspace_bytes(const st_plan *plan, int32_t steps, int32_t mode)
 st_status stencil_plan_describe(const st_plan *plan, int32_t *variant, int32_t *tile_x,
                                 int32_t *tile_y, int32_t *tsteps, int32_t *zchunk);
 
+/* The coefficients a plan applies (Section 2.1: the case's weights c_d).
+ * `dense` (HOST, may be NULL) receives min(count, (2r+1)^ndim) floats in the
+ * layout of st_problem.coeffs; for an ST_WAVE plan created without
+ * coefficients these are the f32-rounded weights of the built-in Laplacian.
+ * *weight_sum (may be NULL) receives the weight sum the difference-form
+ * kernels use, sum_{d != 0} c_d (u(x+d) - u(x)) + (weight sum) u(x): the
+ * FP64 sum of the given weights, and exactly 0 for the built-in Laplacian
+ * (its weights sum to 0 in real arithmetic; its rounded ones do not).
+ * ST_EINVAL for a NULL or batched plan, or count < 0.  Host only. */
+st_status stencil_plan_coefficients(const st_plan *plan, float *dense, int32_t count,
+                                    double *weight_sum);
+
 /* Forward sweep, `steps` time steps (Section 2.1 update rule, iterated).
  *  ST_LINEAR: u_out = A^steps u_in.  u_in == u_out is allowed; other overlap
  *             is not.  `wave` must be NULL.

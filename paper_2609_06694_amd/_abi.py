@@ -28,7 +28,7 @@ VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",
-            "stencil_plan_describe", "stencil_apply", "stencil_apply_adjoint",
+            "stencil_plan_describe", "stencil_plan_coefficients", "stencil_apply", "stencil_apply_adjoint",
             "stencil_apply_varcoef", "stencil_apply_varcoef_adjoint",
             "stencil_wave_gradient", "stencil_plan_batched", "stencil_apply_batched",
             "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version"]
@@ -80,6 +80,9 @@ def lib():
     ip = ctypes.POINTER(i32)
     L.stencil_plan_describe.argtypes = [P, ip, ip, ip, ip, ip]
     L.stencil_plan_describe.restype = ctypes.c_int
+    L.stencil_plan_coefficients.argtypes = [P, ctypes.POINTER(ctypes.c_float), i32,
+                                            ctypes.POINTER(ctypes.c_double)]
+    L.stencil_plan_coefficients.restype = ctypes.c_int
     L.stencil_apply.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P, sz, P]
     L.stencil_apply.restype = ctypes.c_int
     L.stencil_apply_adjoint.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P, sz, P]

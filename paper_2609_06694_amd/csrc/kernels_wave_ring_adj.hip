@@ -18,9 +18,12 @@ namespace stk {
 // its halo tile gives the in-plane taps and its interior enters an LDS ring
 // of 2R+2 planes for the z taps, as in the forward kernel.  The unscaled
 // l_{t+1} of the output plane waits R planes in a register queue.  `tp` holds
-// L^T (the flipped star), `tp2` holds L.  Direct weighted sums, as in the
-// queue kernel of the same steps.
-template <int MODE, int R, int BC, int RY, int NW, int D>
+// L^T (the flipped star), `tp2` holds L.  Both are applied in the forward
+// kernel's difference form, sum_{d != 0} c_d (v(x+d) - v(x)) + (sum of
+// weights) v(x), so the reverse sweep applies exactly the transpose of the
+// operator the forward sweep applies (a direct weighted sum with an f32
+// centre weight would differ from it by up to half an ulp of that weight).
+template <int MODE, int R, int BC, int RY, int NW, int D, bool ISO>
 __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 1) void wave3d_ring_adj_kernel(WaveLaunch w, int nx, int ny,
                                                                      int nz, int zc, int tiles_x,
                                                                      int tiles_y, Taps tp, Taps tp2) {
@@ -114,12 +117,12 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
             __syncthreads();
 
             {
-                float p[RY];
-                star_plane<R, RY, NW>(t1, tp, p);
+                float p[RY], uc[RY];
+                star_plane_diff<R, RY, ISO, NW>(t1, tp, p, uc);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) pq[R][i] = p[i];
                 if constexpr (TWO) {
-                    star_plane<R, RY, NW>(t2, tp2, p);
+                    star_plane_diff<R, RY, ISO, NW>(t2, tp2, p, uc);
 #pragma unroll
                     for (int i = 0; i < RY; ++i) pq2[R][i] = p[i];
                 }
@@ -137,12 +140,18 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     const int cell = (ty * RY + i) * G::BX + tx;
+                    const float ko = ring[0][sl[R]][cell];
                     float a = pq[0][i];
 #pragma unroll
                     for (int e = 1; e <= R; ++e) {
-                        a = fmaf(tp.c[star_z<R>(-e)], ring[0][sl[R - e]][cell], a);
-                        a = fmaf(tp.c[star_z<R>(e)], ring[0][sl[R + e]][cell], a);
+                        if constexpr (ISO) {
+                            a = fmaf(tp.c[star_x<R>(e)], (ring[0][sl[R - e]][cell] - ko) + (ring[0][sl[R + e]][cell] - ko), a);
+                        } else {
+                            a = fmaf(tp.c[star_z<R>(-e)], ring[0][sl[R - e]][cell] - ko, a);
+                            a = fmaf(tp.c[star_z<R>(e)], ring[0][sl[R + e]][cell] - ko, a);
+                        }
                     }
+                    a = fmaf(tp.sum, ko, a);
                     const int gy = y0 + ty * RY + i;
                     if (gy >= ny) continue;
                     const uint32_t o = (uint32_t)(gy * nx + gx);
@@ -155,12 +164,18 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
                         if (w.lap != nullptr)
                             __builtin_nontemporal_store(fmaf(lq[0][i], luv[d][i], gv[d][i]), &w.grad[zoff + o]);
                     } else {
+                        const float uo = ring[1][sl[R]][cell];
                         float a2 = pq2[0][i];
 #pragma unroll
                         for (int e = 1; e <= R; ++e) {
-                            a2 = fmaf(tp2.c[star_z<R>(-e)], ring[1][sl[R - e]][cell], a2);
-                            a2 = fmaf(tp2.c[star_z<R>(e)], ring[1][sl[R + e]][cell], a2);
+                            if constexpr (ISO) {
+                                a2 = fmaf(tp2.c[star_x<R>(e)], (ring[1][sl[R - e]][cell] - uo) + (ring[1][sl[R + e]][cell] - uo), a2);
+                            } else {
+                                a2 = fmaf(tp2.c[star_z<R>(-e)], ring[1][sl[R - e]][cell] - uo, a2);
+                                a2 = fmaf(tp2.c[star_z<R>(e)], ring[1][sl[R + e]][cell] - uo, a2);
+                            }
                         }
+                        a2 = fmaf(tp2.sum, uo, a2);
                         v = 2.f * lq[0][i] - p2v[d][i] + a;
                         if (w.target_t != nullptr && zo == w.rec_z) v += ring[1][sl[R]][cell] - w.target_t[o];
                         __builtin_nontemporal_store(fmaf(lq[0][i], a2, gv[d][i]), &w.grad[zoff + o]);
@@ -189,8 +204,12 @@ static hipError_t go_adj(const Geom& g, int zc, const Taps& tp, const Taps& tp2,
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = MODE == kWaveGradPt ? 1 : 2;   // planes in flight (registers: see the kernel)
-    hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D>), dim3(tiles_x * tiles_y * nchunks),
-                       dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+    if (g.iso)
+        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, true>), dim3(tiles_x * tiles_y * nchunks),
+                           dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+    else
+        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, false>), dim3(tiles_x * tiles_y * nchunks),
+                           dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
     return hipGetLastError();
 }
 

@@ -164,6 +164,15 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
     std::vector<float> flipped(pl->dense.rbegin(), pl->dense.rend());
     pl->taps = pack_taps(p->ndim, p->shape, p->radius, pl->dense);
     pl->taps_t = pack_taps(p->ndim, p->shape, p->radius, flipped);
+    if (p->update == ST_WAVE && !p->coeffs) {
+        // The built-in Laplacian is a sum of per-axis second differences,
+        // each of which annihilates constants: its weights sum to exactly 0.
+        // The sum of the f32-rounded weights is not 0 (about -1.9e-7 for
+        // r = 4), and the difference form's (sum) u(x) term would add that
+        // spurious multiple of u to every evaluation.
+        pl->taps.sum = 0.f;
+        pl->taps_t.sum = 0.f;
+    }
     pl->iso = false;
     if (p->shape == ST_STAR) {
         // One weight per distance on every arm and sign (e.g. a Laplacian).
@@ -392,7 +401,7 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
         HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
         cur = (const float*)ws;
     }
-    const Geom g = geom_of(pl->prob);
+    const Geom g = plan_geom(pl);
     const float* prev = P;
     const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1];
     for (int t = 0; t < steps; ++t) {
@@ -475,6 +484,18 @@ st_status stencil_plan_describe(const st_plan* plan, int32_t* variant, int32_t* 
     if (tile_y) *tile_y = c.tile_y;
     if (tsteps) *tsteps = c.tsteps;
     if (zchunk) *zchunk = c.zchunk;
+    return ST_OK;
+}
+
+st_status stencil_plan_coefficients(const st_plan* plan, float* dense, int32_t count, double* weight_sum) {
+    stk::set_error("%s", "");
+    if (!plan || plan->batched) ST_FAIL(ST_EINVAL, "needs a single-grid plan");
+    if (count < 0) ST_FAIL(ST_EINVAL, "count must be >= 0");
+    if (dense) {
+        const size_t m = std::min((size_t)count, plan->dense.size());
+        for (size_t i = 0; i < m; ++i) dense[i] = plan->dense[i];
+    }
+    if (weight_sum) *weight_sum = (double)plan->taps.sum;
     return ST_OK;
 }
 
@@ -657,7 +678,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
         ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", L.total);
     hipStream_t s = as_stream(stream);
     char* ws = (char*)workspace;
-    const Geom g = geom_of(plan->prob);
+    const Geom g = plan_geom(plan);
     const size_t plane = (size_t)plan->prob.n[0] * plan->prob.n[1];
     const int T = L.T, K = L.K, S = L.S;
     auto ckpt = [&](int seg, int which) -> float* {   // seg >= 1; which 0 = u_{sK-1}, 1 = u_{sK}

@@ -82,6 +82,15 @@ class _Plan:
         return {"variant": _abi.VARIANT_NAMES.get(v.value, v.value), "tile_x": tx.value,
                 "tile_y": ty.value, "tsteps": k.value, "zchunk": zc.value}
 
+    def coefficients(self) -> Tuple[np.ndarray, float]:
+        """(dense coefficients the plan applies, weight sum its difference-form
+        kernels use); host only."""
+        dense = np.zeros(9 ** 3, dtype=np.float32)
+        wsum = ctypes.c_double()
+        check(lib().stencil_plan_coefficients(self._h, dense.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               dense.size, ctypes.byref(wsum)))
+        return dense, float(wsum.value)
+
     def workspace_bytes(self, steps: int, mode: int = 0) -> int:
         return int(lib().stencil_workspace_bytes(self._h, int(steps), int(mode)))
 
@@ -257,16 +266,35 @@ class WaveModel(_Plan):
         self.grid_shape = tuple(reversed(self.n))
         self._ws: Optional[_Workspace] = None
 
-    def _chk(self, t, name):
-        if t is None:
-            return
-        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    def _chk(self, ops):
+        """Each (name, tensor, shape, min_len) must be a contiguous float32
+        device tensor of that shape (or, with min_len, at least that many
+        elements); None passes.  Shapes and lengths are checked for every
+        operand before any placement check."""
+        for name, t, shape, min_len in ops:
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+                raise ValueError(f"{name} must be a float32 tensor")
+            if shape is not None and tuple(t.shape) != tuple(shape):
+                raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+            if min_len is not None and t.numel() < min_len:
+                raise ValueError(f"{name} must hold at least {min_len} values, got {t.numel()}")
+        for name, t, _, _ in ops:
+            if t is not None and (not t.is_cuda or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous device tensor")
+
+    def _ops(self, steps, u_prev=None, kappa=None, wavelet=None, traces=None, target=None, **grids):
+        g = self.grid_shape
+        tr = (int(steps), self.n[1], self.n[0])
+        ops = [(k, v, g, None) for k, v in grids.items()]
+        ops += [("u_prev", u_prev, g, None), ("kappa", kappa, g, None), ("wavelet", wavelet, None, int(steps)),
+                ("traces", traces, tr, None), ("target", target, tr, None)]
+        return ops
 
     def _args(self, u_prev, kappa, src=None, wavelet=None, rec_z=-1, traces=None, target=None):
-        for name, t in (("u_prev", u_prev), ("kappa", kappa), ("wavelet", wavelet), ("traces", traces),
-                        ("target", target)):
-            self._chk(t, name)
+        if kappa is None:
+            raise ValueError("kappa is required")
         s = (-1, -1, -1) if src is None else tuple(int(v) for v in src)
         return _abi.StWaveArgs(_ptr(u_prev), _ptr(kappa), (ctypes.c_int64 * 3)(*s), _ptr(wavelet),
                                int(rec_z), _ptr(traces), _ptr(target))
@@ -281,7 +309,9 @@ class WaveModel(_Plan):
         """Returns (u_T, u_{T-1}, traces or None).  u0 is not modified; u_prev
         is copied first unless prev_inout, in which case it is overwritten
         with u_{T-1} and returned."""
-        self._chk(u0, "u0")
+        if src is not None and wavelet is None:
+            raise ValueError("a source needs a wavelet")
+        self._chk(self._ops(steps, u_prev, kappa, wavelet if src is not None else None, u0=u0, out=out))
         prev = u_prev if prev_inout else u_prev.clone()
         out = torch.empty_like(u0) if out is None else out
         traces = None
@@ -296,7 +326,7 @@ class WaveModel(_Plan):
     def adjoint(self, a, b, kappa, steps: int, stream=None):
         """Transpose of (u_{-1}, u_0) -> (u_{T-1}, u_T): (a, b) are co-states of
         (u_{T-1}, u_T); returns the co-states of (u_{-1}, u_0)."""
-        self._chk(b, "b")
+        self._chk(self._ops(steps, kappa=kappa, a=a, b=b))
         a_io = a.clone()
         out = torch.empty_like(b)
         wa = self._args(a_io, kappa)
@@ -308,7 +338,13 @@ class WaveModel(_Plan):
     def gradient(self, u0, u_prev, kappa, steps: int, src, wavelet, rec_z: int, target,
                  traces: Optional[torch.Tensor] = None, stream=None):
         """(dJ/dkappa, J) with J = 1/2 sum_t ||u_t[rec_z] - target[t-1]||^2."""
-        self._chk(u0, "u0")
+        if target is None:
+            raise ValueError("the gradient needs a target")
+        if src is not None and wavelet is None:
+            raise ValueError("a source needs a wavelet")
+        if not 0 <= int(rec_z) < self.n[2]:
+            raise ValueError(f"rec_z must lie in [0, {self.n[2]})")
+        self._chk(self._ops(steps, u_prev, kappa, wavelet if src is not None else None, traces, target, u0=u0))
         dk = torch.empty_like(kappa)
         loss = torch.empty(1, dtype=torch.float64, device=u0.device)
         wa = self._args(u_prev, kappa, src, wavelet, rec_z, traces, target)
@@ -363,10 +399,19 @@ class BatchedStencil(_Plan):
               stream=None) -> List[torch.Tensor]:
         if len(us) != len(self.shapes):
             raise ValueError("one tensor per batch member is required")
-        for u, shp in zip(us, self.shapes):
-            if not u.is_cuda or u.dtype != self.torch_dtype or tuple(u.shape) != shp or not u.is_contiguous():
-                raise ValueError(f"member tensors must be contiguous {self.torch_dtype} of shape {shp}")
-        outs = [torch.empty_like(u) for u in us] if outs is None else outs
+        if outs is not None and len(outs) != len(self.shapes):
+            raise ValueError("one output tensor per batch member is required")
+        lists = [("member tensors", us)] + ([("member outputs", outs)] if outs is not None else [])
+        for what, ts in lists:   # dtypes and shapes first, then placement
+            for t, shp in zip(ts, self.shapes):
+                if not isinstance(t, torch.Tensor) or t.dtype != self.torch_dtype or tuple(t.shape) != shp:
+                    raise ValueError(f"{what} must be {self.torch_dtype} of shape {shp}")
+        for what, ts in lists:
+            for t in ts:
+                if not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"{what} must be contiguous device tensors")
+        if outs is None:
+            outs = [torch.empty_like(u) for u in us]
         ins = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
         ots = (ctypes.c_void_p * len(us))(*[o.data_ptr() for o in outs])
         if self._ws is None:

@@ -258,3 +258,78 @@ def test_f64_2d_plan_uses_row_march_and_batches(L):
     hb = ctypes.c_void_p()
     assert L.stencil_plan_batched(arr, 2, None, ctypes.byref(hb)) == _abi.ST_EINVAL
     assert not hb.value
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_builtin_laplacian_weight_sum_is_exactly_zero(L, r):
+    """The built-in order-2r Laplacian annihilates constants, so the weight
+    sum its difference-form kernels add back is exactly 0, although the sum
+    of its f32-rounded weights is not (for r >= 2); its weights are the
+    oracle's FP64 table rounded to f32."""
+    import oracle
+    p, keep = _prob(ndim=3, n=(16, 16, 16), update=1, coeffs=None, bc=1, r=r)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    w = (2 * r + 1) ** 3
+    dense = np.zeros(w, dtype=np.float32)
+    s = ctypes.c_double(1.0)
+    assert L.stencil_plan_coefficients(h, dense.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w,
+                                       ctypes.byref(s)) == _abi.ST_OK
+    assert s.value == 0.0
+    assert np.array_equal(dense, oracle.laplacian3d(r).astype(np.float32))
+    if r >= 2:
+        assert float(np.sum(dense.astype(np.float64))) != 0.0
+    L.stencil_plan_destroy(h)
+
+
+def test_plan_coefficients_of_given_weights(L):
+    """A plan with given weights reports them unchanged, and their FP64 sum
+    rounded to f32; NULL and batched plans are rejected."""
+    p, keep = _prob(ndim=2, n=(64, 48, 1), shape=1, r=2)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    dense = np.zeros(25, dtype=np.float32)
+    s = ctypes.c_double()
+    assert L.stencil_plan_coefficients(h, dense.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 25,
+                                       ctypes.byref(s)) == _abi.ST_OK
+    assert np.array_equal(dense, keep[0])
+    assert s.value == float(np.float32(np.sum(keep[0].astype(np.float64))))
+    assert L.stencil_plan_coefficients(h, None, -1, None) == _abi.ST_EINVAL
+    assert L.stencil_plan_coefficients(None, None, 0, None) == _abi.ST_EINVAL
+    L.stencil_plan_destroy(h)
+
+
+def test_binding_rejects_misshaped_wave_and_batch_operands(L):
+    """The Python binding checks every operand's shape and length before any
+    call reaches the device (an undersized buffer would be read or written
+    out of bounds by the kernels)."""
+    import torch
+    from paper_2609_06694_amd import stencil
+    n = (12, 10, 9)
+    m = stencil.WaveModel(n)
+    good = torch.zeros(n[::-1])
+    bad = torch.zeros((9, 10, 11))
+    with pytest.raises(ValueError, match="shape"):
+        m.forward(bad, good, good, 3)
+    with pytest.raises(ValueError, match="shape"):
+        m.forward(good, bad, good, 3)
+    with pytest.raises(ValueError, match="kappa"):
+        m.forward(good, good, bad, 3)
+    with pytest.raises(ValueError, match="at least 3"):
+        m.forward(good, good, good, 3, src=(1, 1, 1), wavelet=torch.zeros(2))
+    with pytest.raises(ValueError, match="wavelet"):
+        m.forward(good, good, good, 3, src=(1, 1, 1))
+    with pytest.raises(ValueError, match="shape"):
+        m.adjoint(bad, good, good, 3)
+    with pytest.raises(ValueError, match="target"):
+        m.gradient(good, good, good, 3, (1, 1, 1), torch.zeros(3), 2, torch.zeros((3, 10, 11)))
+    with pytest.raises(ValueError, match="rec_z"):
+        m.gradient(good, good, good, 3, (1, 1, 1), torch.zeros(3), 9, torch.zeros((3, 10, 12)))
+    with pytest.raises(ValueError, match="device"):   # right shapes, host memory
+        m.forward(good, good, good, 3)
+    bs = stencil.BatchedStencil([dict(n=(20, 16), shape="star", radius=1, coeffs=np.full(9, 0.1, np.float32) *
+                                      np.array([0, 1, 0, 1, 1, 1, 0, 1, 0], np.float32))])
+    with pytest.raises(ValueError):
+        bs.apply([torch.zeros((16, 20))], 2)   # host tensor
+    with pytest.raises(ValueError, match="one output"):
+        bs.apply([torch.zeros((16, 20))], 2, outs=[])
