@@ -1,5 +1,6 @@
 """GPU parity at the full workload sizes, in the launch configuration the
-benchmark times, on sampled output blocks.
+benchmark times: the wave workloads on every cell, the others on sampled
+output blocks.
 
 The oracle computes a sampled block of the final state from a sub-box that
 extends R*T cells beyond it (T steps of a radius-R stencil move information
@@ -35,27 +36,41 @@ def _extract(a, lo, hi, periodic):
     return a[np.ix_(*idx)]
 
 
-def _sample_linear(case, got, starts, block):
-    """Check sampled blocks of a linear sweep's output against the oracle."""
+def _sample_linear(case, got, starts, block, storage=None):
+    """Check sampled blocks of a linear sweep's output against the oracle.
+    With `storage`, also returns the storage floor on the same blocks (the
+    oracle with every step rounded to that format; rounding is per cell, so
+    the dependency sub-box argument holds for it too)."""
     per = case.boundary == wl.PERIODIC
     m = case.radius * case.steps
-    errs = []
+    errs, floors = [], []
     for s0 in starts:
         if per:
             lo = [s - m for s in s0]
             hi = [s + b + m for s, b in zip(s0, block)]
             sub = _extract(case.u0, lo, hi, True)
-            ref = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps)
-            ref = ref[tuple(slice(m, m + b) for b in block)]
+            inner = tuple(slice(m, m + b) for b in block)
         else:
             lo = [max(0, s - m) for s in s0]
             hi = [min(n, s + b + m) for s, b, n in zip(s0, block, case.u0.shape)]
             sub = case.u0[tuple(slice(l, h) for l, h in zip(lo, hi))]
-            ref = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps)
-            ref = ref[tuple(slice(s - l, s - l + b) for s, l, b in zip(s0, lo, block))]
+            inner = tuple(slice(s - l, s - l + b) for s, l, b in zip(s0, lo, block))
+        ref = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps)[inner]
         g = got[tuple(slice(s, s + b) for s, b in zip(s0, block))]
         errs.append(rel_l2(g.astype(np.float64), ref))
+        if storage:
+            fl = oracle.sweep(sub, case.coeffs, case.shape, case.radius, wl.ZERO, case.steps,
+                              storage=storage)[inner]
+            floors.append(rel_l2(fl, ref))
+    if storage:
+        return max(errs), max(floors)
     return max(errs)
+
+
+def _check_fp16(tag, e, floor):
+    """fp16 gate: 2e-3 rel-L2, and within 5x of the binary16 storage floor."""
+    print(f"{tag} sampled rel-L2 {e:.3e}, binary16 floor {floor:.3e}, ratio {e / floor:.2f}")
+    assert e <= 2e-3 and e <= 5 * floor
 
 
 def test_fullsize_jacobi2d(st):
@@ -73,9 +88,12 @@ def test_fullsize_box3d(st, dtype):
     s = st.Stencil(case.n, "box", 1, case.coeffs, dtype=dt)
     got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
     starts = [(0, 0, 0), (507, 250, 480)]   # [z, y, x]: a corner (wraps) and a far face
+    if dtype == wl.F16:
+        _check_fp16("box3d f16 512^3 x50", *_sample_linear(case, got, starts, (5, 8, 8), "binary16"))
+        return
     e = _sample_linear(case, got, starts, (5, 8, 8))
     print(f"box3d {dt} 512^3 x50 sampled rel-L2 {e:.2e}")
-    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+    assert e <= 1e-5
 
 
 @pytest.mark.parametrize("dtype", [wl.F16, wl.F32, wl.F64])
@@ -86,9 +104,12 @@ def test_fullsize_star3d(st, dtype):
     s = st.Stencil(case.n, "star", 1, case.coeffs, dtype=dt)
     got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
     starts = [(0, 0, 0), (505, 250, 478)]
+    if dtype == wl.F16:
+        _check_fp16("star3d f16 512^3 x10", *_sample_linear(case, got, starts, (4, 6, 8), "binary16"))
+        return
     e = _sample_linear(case, got, starts, (4, 6, 8))
     print(f"star3d {dt} 512^3 x10 sampled rel-L2 {e:.2e}")
-    assert e <= {wl.F16: 2e-3, wl.F32: 1e-5, wl.F64: 1e-12}[dtype]
+    assert e <= {wl.F32: 1e-5, wl.F64: 1e-12}[dtype]
 
 
 @pytest.mark.parametrize("shape,r", [("star", 1), ("box", 1)])
@@ -129,9 +150,12 @@ def test_fullsize_box3d_r2(st, dtype):
     s = st.Stencil(case.n, "box", 2, case.coeffs, dtype=dt)
     got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
     starts = [(0, 0, 0), (505, 250, 478)]
+    if dtype == wl.F16:
+        _check_fp16("box3d r2 f16 512^3 x10", *_sample_linear(case, got, starts, (4, 6, 8), "binary16"))
+        return
     e = _sample_linear(case, got, starts, (4, 6, 8))
     print(f"box3d r2 {dt} 512^3 x10 sampled rel-L2 {e:.2e}")
-    assert e <= (2e-3 if dtype == wl.F16 else 1e-5)
+    assert e <= 1e-5
 
 
 @pytest.mark.parametrize("dtype", [wl.F16, wl.F32, wl.F64])
@@ -141,9 +165,12 @@ def test_fullsize_box2d(st, dtype):
     s = st.Stencil(case.n[:2], "box", 2, case.coeffs, dtype=dt)
     got = s.apply(torch.from_numpy(case.u0).cuda(), case.steps).cpu().numpy()
     starts = [(0, 0), (2000, 3001), (4080, 4080), (1234, 0)]
+    if dtype == wl.F16:
+        _check_fp16("box2d f16 4096^2 x100", *_sample_linear(case, got, starts, (16, 16), "binary16"))
+        return
     e = _sample_linear(case, got, starts, (16, 16))
     print(f"box2d {dt} 4096^2 x100 sampled rel-L2 {e:.2e}")
-    assert e <= {"f16": 2e-3, "f32": 1e-5, "f64": 1e-12}[dt]
+    assert e <= {"f32": 1e-5, "f64": 1e-12}[dt]
 
 
 def test_fullsize_varcoef2d(st):
@@ -173,31 +200,57 @@ def test_fullsize_varcoef2d(st):
 
 
 def test_fullsize_wave3d(st):
+    """The headline workload (512^3, 20 steps, zero frame) compared with the
+    oracle on every cell of u_T and u_{T-1}, with the margin printed beside
+    the binary32 storage floor of the same run."""
     case = wl.wave3d(n=512, steps=20)
     m = st.WaveModel(case.n, radius=4, boundary="zero")
     out, prev, _ = m.forward(torch.from_numpy(case.u0).cuda(), torch.from_numpy(case.u_prev).cuda(),
                              torch.from_numpy(case.kappa).cuda(), case.steps)
     got, gotp = out.cpu().numpy(), prev.cpu().numpy()
-    R, T = 4, case.steps
-    mg = R * T
-    errs = []
-    # [z, y, x]: the pulse centre, an off-centre block inside the pulse, and a
-    # corner block the pulse never reaches (must stay exactly zero)
-    for s0 in [(252, 250, 249), (270, 236, 262), (0, 0, 0)]:
-        block = (4, 4, 8)
-        lo = [max(0, s - mg) for s in s0]
-        hi = [min(512, s + b + mg) for s, b in zip(s0, block)]
-        sl = tuple(slice(l, h) for l, h in zip(lo, hi))
-        ra, rb, _ = oracle.wave_forward(case.u_prev[sl], case.u0[sl], case.kappa[sl], T)
-        inner = tuple(slice(s - l, s - l + b) for s, l, b in zip(s0, lo, block))
-        blk = tuple(slice(s, s + b) for s, b in zip(s0, block))
-        if np.linalg.norm(rb[inner]) > 0:
-            errs.append(rel_l2(got[blk], rb[inner]))
-            errs.append(rel_l2(gotp[blk], ra[inner]))
-        else:   # a block the pulse never reaches must be exactly zero
-            assert not np.any(got[blk]) and not np.any(gotp[blk])
-    print(f"wave 512^3 x20 sampled rel-L2 {max(errs):.2e}")
-    assert errs and max(errs) <= 1e-5
+    del out, prev
+    T = case.steps
+    ra, rb, _ = oracle.wave_forward(case.u_prev, case.u0, case.kappa, T)
+    e = max(rel_l2(got, rb), rel_l2(gotp, ra))
+    del got, gotp
+    fa, fb, _ = oracle.wave_forward(case.u_prev, case.u0, case.kappa, T, storage="binary32")
+    floor = max(rel_l2(fb, rb), rel_l2(fa, ra))
+    print(f"wave 512^3 x{T} all cells: rel-L2 {e:.3e} (gate 1e-5, margin {1e-5 / e:.1f}x; "
+          f"binary32 storage floor {floor:.3e}, ratio {e / floor:.2f})")
+    assert e <= 1e-5
+
+
+def test_fullsize_wave_gradient_vs_oracle(st):
+    """The gradient workload at its full size and law (256^3, 200 steps,
+    checkpoints every 20, Ricker source at z = 16, receivers on z = 8,
+    target from the +5% blob model): dkappa and J against the FP64 oracle.
+
+    The residual r = P u - d is a small difference of two wavefields, and
+    dkappa is linear in it, so an f32 wavefield error e moves dkappa by
+    about e * |d| / |r| relative (J, quadratic in r, by twice that).  The
+    gate is the f32 field gate 1e-5 scaled by that conditioning, both
+    norms taken from the oracle."""
+    case = wl.wavegrad3d()
+    T, n = case.steps, case.n
+    _, _, target = oracle.wave_forward(case.u_prev, case.u0, case.kappa_true, T, src=case.src,
+                                       wavelet=case.wavelet, rec_z=case.rec_z)
+    target = target.astype(np.float32)
+    dev = torch.device("cuda")
+    z = torch.from_numpy(case.u0).to(dev)
+    m = st.WaveModel(n, ckpt_every=case.ckpt_every)
+    dk, loss = m.gradient(z, z, torch.from_numpy(case.kappa).to(dev), T, case.src,
+                          torch.from_numpy(case.wavelet).to(dev), case.rec_z, torch.from_numpy(target).to(dev))
+    got, J = dk.cpu().numpy(), float(loss.item())
+    del dk, m, z
+    torch.cuda.empty_cache()
+    g_ref, J_ref = oracle.wave_gradient(case.u_prev, case.u0, case.kappa, T, case.src, case.wavelet,
+                                        case.rec_z, target, ckpt_every=case.ckpt_every)
+    cond = float(np.linalg.norm(target.astype(np.float64)) / np.sqrt(2 * J_ref))
+    eg = rel_l2(got, g_ref)
+    eJ = abs(J - J_ref) / J_ref
+    print(f"gradient 256^3 x{T}: dkappa rel-L2 {eg:.3e} (gate {1e-5 * cond:.3e}), loss rel {eJ:.3e} "
+          f"(gate {2e-5 * cond:.3e}); |d|/|r| = {cond:.1f}")
+    assert eg <= 1e-5 * cond and eJ <= 2e-5 * cond
 
 
 def test_fullsize_batch64_separate_launches(st):

@@ -542,19 +542,25 @@ def test_wave_gradient_vs_oracle(st, family):
     assert eJ <= 1e-5 and eg <= 1e-5
 
 
-def test_wave_gradient_small_residual_floor(st):
-    """+5% blob target: the residual is a small difference of f32 fields, so
-    the f32 path's floor is far above 1e-5.  The measured error is printed
-    and bounded loosely; the exact-arithmetic check is the zero-target test."""
+def test_wave_gradient_small_residual_conditioning(st):
+    """+5% blob target: the residual r = P u - d is a small difference of two
+    wavefields and dkappa is linear in it, so an f32 wavefield error e moves
+    dkappa by about e |d| / |r| relative (J, quadratic in r, by twice that).
+    The gate is the f32 field gate 1e-5 scaled by that conditioning, both
+    norms from the oracle; the binary32 storage floor of the same recursion
+    is printed beside the measured error."""
     kappa, zeros, src, wav, rec, target = _grad_case(blob=True)
     steps = 30
     m = st.WaveModel(kappa.shape[::-1], ckpt_every=7)
     dk, loss = m.gradient(_dev(zeros), _dev(zeros), _dev(kappa), steps, src, _dev(wav), rec, _dev(target))
     g_ref, J_ref = oracle.wave_gradient(zeros, zeros, kappa, steps, src, wav, rec, target, ckpt_every=0)
+    g_fl, _ = oracle.wave_gradient(zeros, zeros, kappa, steps, src, wav, rec, target, storage="binary32")
+    cond = float(np.linalg.norm(target.astype(np.float64)) / np.sqrt(2 * J_ref))
     eJ = abs(float(_host(loss)[0]) - J_ref) / abs(J_ref)
     eg = rel_l2(_host(dk), g_ref)
-    print(f"gradient (blob target): loss rel err {eJ:.3e}, dkappa rel-L2 {eg:.3e}")
-    assert eJ <= 1e-2 and eg <= 1e-2
+    print(f"gradient (blob target): loss rel err {eJ:.3e} (gate {2e-5 * cond:.2e}), dkappa rel-L2 {eg:.3e} "
+          f"(gate {1e-5 * cond:.2e}, binary32 floor {rel_l2(g_fl, g_ref):.2e}); |d|/|r| = {cond:.1f}")
+    assert eJ <= 2e-5 * cond and eg <= 1e-5 * cond
 
 
 def test_wave_gradient_checkpoints_bitwise_equal(st):
