@@ -53,6 +53,11 @@ def parse():
                          "then one 2-step pass of the headline workload")
     ap.add_argument("--shapes", action="store_true",
                     help="also sweep the 7- and 27-point 3D sweeps over cubes and slabs (f16/f32/f64)")
+    ap.add_argument("--summarize-trace", default="",
+                    help="instead of benchmarking: summarise a rocprofv3 kernel_trace.csv (durations of "
+                         "the launches of --kernel after the first --skip of them)")
+    ap.add_argument("--kernel", default="wave3d_ring_kernel", help="kernel name substring for --summarize-trace")
+    ap.add_argument("--skip", type=int, default=0, help="launches to skip (warm-up) for --summarize-trace")
     ap.add_argument("--stream-ceiling", action="store_true",
                     help="also measure plain streaming kernels (copy, read-3/write-1) as the "
                          "practical bandwidth ceiling")
@@ -232,22 +237,63 @@ def bench_jacobi(dev, st, wl, torch):
 ESIZE = {"f16": 2, "f32": 4, "f64": 8}
 
 
-def bench_linear(dev, st, wl, torch, case, reps=3):
+def fused_depth(desc, ndim):
+    """Time steps one launch of the dispatched kernel advances: the fused
+    depth of the 2D families, two for the 3D two-step kernel, else one."""
+    k = max(1, int(desc.get("tsteps") or 1))
+    if ndim == 3:
+        return 2 if k == 2 and desc.get("variant") == "zm3d" else 1
+    return k
+
+
+def linear_record(case, wl, desc, ms):
+    """GCells/s and roofline fractions of a linear sweep.  `hbm_frac` counts
+    the algorithmic HBM bytes of the launches as run: one read and one write
+    of the grid per launch, i.e. 2b/k bytes per cell-update with k fused
+    steps.  `equiv_frac_one_step` charges 2b per cell-update (what k
+    single-step launches would move) and can exceed the HBM roof."""
     dt = wl.DTYPE_TAGS[case.dtype]
-    shape = wl.SHAPE_NAMES[case.shape]
-    s = st.Stencil(case.n[:case.ndim], shape, case.radius, case.coeffs, dtype=dt)
-    u = torch.from_numpy(case.u0).to(dev)
-    out = torch.empty_like(u)
-    ms = timed(lambda: s.apply(u, case.steps, out=out), reps, 1, torch.cuda.synchronize)
     g = gcells(case.cells, case.steps, ms)
-    bpc = 2 * ESIZE[dt]
+    k = fused_depth(desc, case.ndim)
+    bpc = 2 * ESIZE[dt] / k
     taps = (2 * case.radius + 1) ** case.ndim if case.shape == wl.BOX else 1 + 2 * case.ndim * case.radius
     fpc = 2 * taps   # one multiply-add per tap (f32 arithmetic; f64 for f64 storage)
     return {"workload": f"{case.name}_{'x'.join(str(v) for v in case.n[:case.ndim])}_{case.steps}steps",
-            "ms": ms, "gcells_s": g, "eff_gbs": g * bpc, "hbm_frac": g * bpc / HBM_PEAK_GBS,
-            "bytes_per_cell_update": bpc, "flop_per_cell_update": fpc, "valu_tflops": g * fpc / 1e3,
+            "ms": ms, "gcells_s": g, "fused_steps_per_launch": k, "bytes_per_cell_update": bpc,
+            "eff_gbs": g * bpc, "hbm_frac": g * bpc / HBM_PEAK_GBS,
+            "equiv_frac_one_step": g * 2 * ESIZE[dt] / HBM_PEAK_GBS,
+            "flop_per_cell_update": fpc, "valu_tflops": g * fpc / 1e3,
             "valu_frac": g * fpc / 1e3 / (VALU_F64_PEAK_TFLOPS if dt == "f64" else VALU_PEAK_TFLOPS),
-            "dispatch": s.describe()}
+            "timing": f"median of {REPS} passes", "dispatch": desc}
+
+
+REPS = 7   # timed passes per workload (medians); twins are interleaved
+
+
+def bench_linear(dev, st, wl, torch, case):
+    dt = wl.DTYPE_TAGS[case.dtype]
+    s = st.Stencil(case.n[:case.ndim], wl.SHAPE_NAMES[case.shape], case.radius, case.coeffs, dtype=dt)
+    u = torch.from_numpy(case.u0).to(dev)
+    out = torch.empty_like(u)
+    ms = timed(lambda: s.apply(u, case.steps, out=out), REPS, 1, torch.cuda.synchronize)
+    return linear_record(case, wl, s.describe(), ms)
+
+
+def bench_linear_twins(dev, st, wl, torch, case_a, case_b):
+    """Two storage twins of one workload, timed in interleaved passes."""
+    runs, plans = [], []
+    for case in (case_a, case_b):
+        dt = wl.DTYPE_TAGS[case.dtype]
+        s = st.Stencil(case.n[:case.ndim], wl.SHAPE_NAMES[case.shape], case.radius, case.coeffs, dtype=dt)
+        u = torch.from_numpy(case.u0).to(dev)
+        out = torch.empty_like(u)
+        runs.append(lambda s=s, u=u, out=out, c=case: s.apply(u, c.steps, out=out))
+        plans.append(s)
+    ma, mb = timed_pair(runs[0], runs[1], REPS, 1, torch.cuda.synchronize)
+    ra = linear_record(case_a, wl, plans[0].describe(), ma)
+    rb = linear_record(case_b, wl, plans[1].describe(), mb)
+    ra["timing"] = rb["timing"] = f"median of {REPS} interleaved passes with its storage twin"
+    return ra, rb
 
 
 def bench_varcoef(dev, st, torch, shape, r, n=512, steps=10, ndim=3):
@@ -262,7 +308,7 @@ def bench_varcoef(dev, st, torch, shape, r, n=512, steps=10, ndim=3):
     u = torch.rand(grid, generator=g, device=dev)
     out = torch.empty_like(u)
     s = st.VarCoefStencil(grid, shape, r)
-    ms = timed(lambda: s.apply(u, f, steps, out=out), 3, 1, torch.cuda.synchronize)
+    ms = timed(lambda: s.apply(u, f, steps, out=out), REPS, 1, torch.cuda.synchronize)
     gc = gcells(n ** ndim, steps, ms)
     bpc = (ntap + 2) * 4
     return {"workload": f"varcoef_{shape}{r}_f32_{n}^{ndim}_{steps}steps", "ms": ms, "gcells_s": gc,
@@ -292,12 +338,16 @@ def bench_shapes(dev, st, wl, torch):
                 s = st.Stencil(n, sname, r, c, dtype=dt)
                 u = torch.rand((n[2], n[1], n[0]), device=dev, dtype=tdt)
                 o = torch.empty_like(u)
-                ms = timed(lambda: s.apply(u, 10, out=o), 3, 1, torch.cuda.synchronize)
+                ms = timed(lambda: s.apply(u, 10, out=o), REPS, 1, torch.cuda.synchronize)
                 cells = n[0] * n[1] * n[2]
                 g = gcells(cells, 10, ms)
+                desc = s.describe()
+                k = fused_depth(desc, 3)
                 out[f"{sname}1_{dt}_{tag}"] = {"grid": list(n), "ms": round(ms, 4), "gcells_s": round(g, 1),
-                                               "hbm_frac": round(g * 2 * ESIZE[dt] / HBM_PEAK_GBS, 3),
-                                               "dispatch": s.describe()}
+                                               "fused_steps_per_launch": k,
+                                               "hbm_frac": round(g * 2 * ESIZE[dt] / k / HBM_PEAK_GBS, 3),
+                                               "equiv_frac_one_step": round(g * 2 * ESIZE[dt] / HBM_PEAK_GBS, 3),
+                                               "dispatch": desc}
                 del u, o
                 torch.cuda.empty_cache()
     return out
@@ -316,13 +366,23 @@ def bench_batch(dev, st, wl, torch):
 
     bs = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
                             for c in cases])
+    t0 = time.perf_counter()
+    tune = bs.autotune(device=dev)
+    tune_s = time.perf_counter() - t0
+    desc = bs.describe()
+    k = max(1, desc["tsteps"])
     # Seven interleaved passes of the two variants, medians.
-    ms, bms = timed_pair(run, lambda: bs.apply(ins, 32, outs=outs), 7, 2, torch.cuda.synchronize)
+    ms, bms = timed_pair(run, lambda: bs.apply(ins, 32, outs=outs), REPS, 2, torch.cuda.synchronize)
     g = gcells(cells, 32, ms)
     bg = gcells(cells, 32, bms)
     return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms": bms, "gcells_s": bg,
-            "launches": "one per time block for all 64 grids", "eff_gbs": bg * 8,
-            "ms_separate_launches": ms, "gcells_s_separate": g}
+            "launches": f"one grouped launch per time block of {k} fused steps for all 64 grids "
+                        f"({-(-32 // k)} launches), autotuned",
+            "autotune": dict(tune, seconds=round(tune_s, 1)), "dispatch": desc,
+            "bytes_per_cell_update": 8 / k, "hbm_frac": bg * 8 / k / HBM_PEAK_GBS,
+            "equiv_frac_one_step": bg * 8 / HBM_PEAK_GBS,
+            "ms_separate_launches": ms, "gcells_s_separate": g,
+            "timing": f"median of {REPS} passes interleaved with the 64 separate plain launches"}
 
 
 def bench_grad(dev, st, wl, torch):
@@ -344,7 +404,7 @@ def bench_grad(dev, st, wl, torch):
 
     # Forward and forward + backward in seven interleaved passes, medians.
     fwd_ms, g_ms = timed_pair(lambda: model.forward(zeros, zeros, kap, case.steps, src=case.src, wavelet=wav,
-                                                    rec_z=case.rec_z, record=True), grad, 7, 1,
+                                                    rec_z=case.rec_z, record=True), grad, REPS, 1,
                               torch.cuda.synchronize)
     dk, loss = res["g"]
     return {"workload": "wavegrad3d_star4_256^3_200steps_ckpt20", "fwd_ms": fwd_ms, "fwd_bwd_ms": g_ms,
@@ -353,23 +413,116 @@ def bench_grad(dev, st, wl, torch):
             "loss": float(loss.item()), "grad_finite": bool(torch.isfinite(dk).all().item())}
 
 
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
+def _oracle_rate(fn, cell_updates):
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return {"gcells_s": cell_updates / dt / 1e9, "seconds": round(dt, 2)}
+
+
 def cpu_baseline(wl):
     """The FP64 oracle (unchanged, OpenMP over all host cores) on a bounded
-    sample of the headline workload: a 288^3 grid, 20 leapfrog steps."""
+    sample of the headline workload: a 384^3 grid, 20 leapfrog steps."""
     import oracle
     oracle.build(force=False)
-    n = 288
+    oracle.set_threads(0)
+    n = 384
     case = wl.wave3d(n=n, steps=20)
+    r = _oracle_rate(lambda: oracle.wave_forward(case.u_prev, case.u0, case.kappa, case.steps, r=4,
+                                                 boundary=wl.ZERO), n ** 3 * case.steps)
+    return dict({"value": r["gcells_s"], "unit": "GCells/s", "cores": oracle.max_threads(), "kind": "oracle",
+                 "sample": f"wave leapfrog r=4, {n}^3 cells x 20 steps (same law as the 512^3 workload), "
+                           f"FP64, {r['seconds']} s"}, **host_info())
+
+
+def cpu_per_config(wl):
+    """The FP64 oracle timed per workload on bounded samples of the same law
+    (all host threads; one thread as well for the 2D Jacobi and 2D box)."""
+    import oracle
+    oracle.build(force=False)
+    oracle.set_threads(0)
+    allt = oracle.max_threads()
+    res = {}
+
+    def linear(tag, case, sample_desc, threads=(None,)):
+        out = {"sample": sample_desc}
+        for th in threads:
+            oracle.set_threads(th or 0)
+            rr = _oracle_rate(lambda: oracle.sweep(case.u0, case.coeffs, case.shape, case.radius, case.boundary,
+                                                   case.steps), case.cells * case.steps)
+            out["gcells_s" if th is None else f"gcells_s_{th}_thread"] = rr["gcells_s"]
+        oracle.set_threads(0)
+        out["threads"] = allt
+        res[tag] = out
+
+    linear("jacobi2d", wl.jacobi2d(), "the full workload: 512^2 x 10 steps", (None, 1))
+    linear("box3d", wl.box3d(n=128, steps=5, dtype=wl.F16), "27-point box, 128^3 x 5 steps (fp16 inputs)")
+    linear("star3d", wl.star3d(n=(256, 256, 256), steps=5), "7-point star, 256^3 x 5 steps")
+    linear("box2d", wl.box2d(n=2048, steps=5, dtype=wl.F16), "25-point box, 2048^2 x 5 steps (fp16 inputs)",
+           (None, 1))
+    cases = wl.batch2d()[:8]
+    for c in cases:
+        c.steps = 4
     t0 = time.perf_counter()
-    oracle.wave_forward(case.u_prev, case.u0, case.kappa, case.steps, r=4, boundary=wl.ZERO)
+    for c in cases:
+        oracle.sweep(c.u0, c.coeffs, c.shape, c.radius, c.boundary, c.steps)
     dt = time.perf_counter() - t0
-    return {"value": gcells(n ** 3, case.steps, dt * 1e3), "unit": "GCells/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"wave leapfrog r=4, {n}^3 cells x 20 steps, FP64, {dt:.1f} s"}
+    res["batch64"] = {"sample": "the first 8 of the 64 grids x 4 steps", "threads": allt,
+                      "gcells_s": sum(c.cells for c in cases) * 4 / dt / 1e9}
+    g = wl.wavegrad3d(n=64)
+    _, _, tg = oracle.wave_forward(g.u_prev, g.u0, g.kappa_true, g.steps, src=g.src, wavelet=g.wavelet,
+                                   rec_z=g.rec_z)
+    rr = _oracle_rate(lambda: oracle.wave_gradient(g.u_prev, g.u0, g.kappa, g.steps, g.src, g.wavelet, g.rec_z,
+                                                   tg, ckpt_every=g.ckpt_every), g.cells * g.steps)
+    res["wavegrad"] = {"sample": "gradient law at 64^3 x 200 steps, K = 20", "threads": allt,
+                       "fwd_bwd_ms": rr["seconds"] * 1e3, "gcells_s_fwd_bwd": rr["gcells_s"]}
+    return res
+
+
+def summarize_trace(path, kernel, skip):
+    """Launch statistics of one kernel from a rocprofv3 kernel trace: the
+    launches whose name contains `kernel`, in dispatch order, after the first
+    `skip` (the warm-up passes).  Prints one JSON line (microseconds)."""
+    import csv
+    rows = []
+    with open(path, newline="") as f:
+        for rec in csv.DictReader(f):
+            if kernel in rec.get("Kernel_Name", ""):
+                rows.append((int(rec.get("Dispatch_Id") or 0), int(rec["Start_Timestamp"]),
+                             int(rec["End_Timestamp"]), rec["Kernel_Name"]))
+    rows.sort(key=lambda r: (r[1], r[0]))
+    names = sorted({r[3] for r in rows})
+    timed_rows = rows[skip:]
+    d = np.array([(e - b) / 1e3 for _, b, e, _ in timed_rows], dtype=np.float64)
+    out = {"trace": path, "kernel_filter": kernel, "kernels": names, "launches_total": len(rows),
+           "skipped": skip, "launches": int(d.size)}
+    if d.size:
+        out.update({"mean_us": round(float(d.mean()), 2), "median_us": round(float(np.median(d)), 2),
+                    "min_us": round(float(d.min()), 2), "max_us": round(float(d.max()), 2),
+                    "sum_ms": round(float(d.sum()) / 1e3, 3)})
+    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.kernel, args.skip)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the stencil library runs on one GPU; run with --gpus 1"}))
         sys.exit(2)
@@ -407,29 +560,31 @@ def main():
     if not args.quick:
         only = set(filter(None, args.only.split(",")))
         todo = [
-            ("jacobi2d", lambda: bench_jacobi(dev, st, wl, torch)),
-            ("box3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F16))),
-            ("box3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d(dtype=wl.F32))),
-            ("star3d_f16", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F16))),
-            ("star3d_f32", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F32))),
-            ("star3d_f64", lambda: bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F64))),
-            ("varcoef_star1", lambda: bench_varcoef(dev, st, torch, "star", 1)),
-            ("varcoef_box1", lambda: bench_varcoef(dev, st, torch, "box", 1)),
-            ("varcoef2d_star1", lambda: bench_varcoef(dev, st, torch, "star", 1, n=4096, steps=20, ndim=2)),
-            ("box2d_f64", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F64))),
-            ("box3d_r2_f16", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16))),
-            ("box3d_r2_f32", lambda: bench_linear(dev, st, wl, torch, wl.box3d_r2(dtype=wl.F32))),
-            ("box2d_f16", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F16))),
-            ("box2d_f32", lambda: bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F32))),
-            ("batch64", lambda: bench_batch(dev, st, wl, torch)),
-            ("wavegrad", lambda: bench_grad(dev, st, wl, torch)),
+            ("jacobi2d", lambda: {"jacobi2d": bench_jacobi(dev, st, wl, torch)}),
+            ("box3d", lambda: dict(zip(("box3d_f16", "box3d_f32"), bench_linear_twins(
+                dev, st, wl, torch, wl.box3d(dtype=wl.F16), wl.box3d(dtype=wl.F32))))),
+            ("star3d", lambda: dict(zip(("star3d_f16", "star3d_f32"), bench_linear_twins(
+                dev, st, wl, torch, wl.star3d(dtype=wl.F16), wl.star3d(dtype=wl.F32))))),
+            ("star3d_f64", lambda: {"star3d_f64": bench_linear(dev, st, wl, torch, wl.star3d(dtype=wl.F64))}),
+            ("varcoef_star1", lambda: {"varcoef_star1": bench_varcoef(dev, st, torch, "star", 1)}),
+            ("varcoef_box1", lambda: {"varcoef_box1": bench_varcoef(dev, st, torch, "box", 1)}),
+            ("varcoef2d_star1", lambda: {"varcoef2d_star1": bench_varcoef(dev, st, torch, "star", 1, n=4096,
+                                                                          steps=20, ndim=2)}),
+            ("box2d_f64", lambda: {"box2d_f64": bench_linear(dev, st, wl, torch, wl.box2d(dtype=wl.F64))}),
+            ("box3d_r2", lambda: dict(zip(("box3d_r2_f16", "box3d_r2_f32"), bench_linear_twins(
+                dev, st, wl, torch, wl.box3d_r2(dtype=wl.F16), wl.box3d_r2(dtype=wl.F32))))),
+            ("box2d", lambda: dict(zip(("box2d_f16", "box2d_f32"), bench_linear_twins(
+                dev, st, wl, torch, wl.box2d(dtype=wl.F16), wl.box2d(dtype=wl.F32))))),
+            ("batch64", lambda: {"batch64": bench_batch(dev, st, wl, torch)}),
+            ("wavegrad", lambda: {"wavegrad": bench_grad(dev, st, wl, torch)}),
         ]
         for name, fn in todo:
             if only and name not in only:
                 continue
             t0 = time.perf_counter()
-            extras[name] = fn()
-            log(f"{name}: {json.dumps(extras[name])} ({time.perf_counter() - t0:.1f} s)")
+            recs = fn()
+            extras.update(recs)
+            log(f"{name}: {json.dumps(recs)} ({time.perf_counter() - t0:.1f} s)")
             torch.cuda.empty_cache()
         line["per_config"] = extras
     if args.shapes:
@@ -443,6 +598,10 @@ def main():
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(wl)
         log(f"cpu baseline: {line['cpu_baseline']} ({time.perf_counter() - t0:.1f} s)")
+        if not args.quick:
+            t0 = time.perf_counter()
+            line["cpu_per_config"] = cpu_per_config(wl)
+            log(f"cpu per config: {json.dumps(line['cpu_per_config'])} ({time.perf_counter() - t0:.1f} s)")
     if not finite:
         line["error"] = "non-finite wave field"
     print(json.dumps(line), flush=True)
