@@ -172,6 +172,24 @@ st_status stencil_apply(const st_plan *plan, const void *u_in, void *u_out, int3
                         const st_wave_args *wave, void *workspace, size_t ws_bytes,
                         void *stream);
 
+/* stencil_apply for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweep, forward, for a single-grid ST_LINEAR or ST_WAVE plan, with the
+ * workspace taken from a fixed device array of this library instead of the
+ * caller.  The array holds stencil_noalloc_capacity() bytes (64 MiB) on each
+ * GPU the library runs on, for the life of the process; a call whose
+ * workspace (stencil_workspace_bytes(plan, steps, 0)) exceeds it returns
+ * ST_EWORKSPACE before any device work.  No allocation of any kind is made.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and must not be issued.
+ * Arguments, buffer rules and results are those of stencil_apply; ST_EINVAL
+ * for batched and variable-coefficient plans. */
+st_status stencil_apply_noalloc(const st_plan *plan, const void *u_in, void *u_out, int32_t steps,
+                                const st_wave_args *wave, void *stream);
+
+/* Bytes of the fixed scratch array of stencil_apply_noalloc. */
+size_t stencil_noalloc_capacity(void);
+
 /* Transposed sweep.
  *  ST_LINEAR: v_out = (A^T)^steps v_in, (A^T v)(x) = sum_d c_d v(B(x - d)).
  *  ST_WAVE:   transpose of the linear state map (u_{-1}, u_0) -> (u_{T-1}, u_T)

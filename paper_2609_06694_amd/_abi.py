@@ -31,7 +31,8 @@ EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",
             "stencil_plan_describe", "stencil_plan_coefficients", "stencil_apply", "stencil_apply_adjoint",
             "stencil_apply_varcoef", "stencil_apply_varcoef_adjoint",
             "stencil_wave_gradient", "stencil_plan_batched", "stencil_apply_batched",
-            "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version"]
+            "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version",
+            "stencil_apply_noalloc", "stencil_noalloc_capacity"]
 
 
 class StProblem(ctypes.Structure):
@@ -85,6 +86,10 @@ def lib():
     L.stencil_plan_coefficients.restype = ctypes.c_int
     L.stencil_apply.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P, sz, P]
     L.stencil_apply.restype = ctypes.c_int
+    L.stencil_apply_noalloc.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P]
+    L.stencil_apply_noalloc.restype = ctypes.c_int
+    L.stencil_noalloc_capacity.argtypes = []
+    L.stencil_noalloc_capacity.restype = sz
     L.stencil_apply_adjoint.argtypes = [P, P, P, i32, ctypes.POINTER(StWaveArgs), P, sz, P]
     L.stencil_apply_adjoint.restype = ctypes.c_int
     L.stencil_apply_varcoef.argtypes = [P, P, P, P, i32, P, sz, P]

@@ -1,0 +1,98 @@
+"""The allocation-free entry point (stencil_apply_noalloc) against the
+existing one (stencil_apply), called through the C ABI: same plan, same
+inputs, two or more calls in a row on one GPU with shrinking grids (the
+fixed scratch array keeps the previous call's contents), each result equal
+to stencil_apply's and within the oracle tolerance."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from mathref import rel_l2
+from paper_2609_06694_amd import _abi, stencil
+from paper_2609_06694_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return _abi.lib()
+
+
+def _stream():
+    return ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+
+
+def _linear_pair(L, ndim, n, shape, r, dtype, steps, inplace, seed):
+    rng = np.random.default_rng(seed)
+    c = wl.random_unit_sum_coeffs(rng, ndim, shape, r)
+    npdt = {"f32": np.float32, "f16": np.float16}[dtype]
+    u = wl.small_random_grid(rng, ndim, n, npdt, 0.0, 1.0)
+    s = stencil.Stencil(n, shape, r, c, dtype=dtype)
+    dev = torch.from_numpy(u).cuda()
+    ref_out = s.apply(dev, steps)                      # the existing entry point
+    a = dev.clone()
+    b = a if inplace else torch.empty_like(a)
+    st = L.stencil_apply_noalloc(s.handle, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                 steps, None, _stream())
+    assert st == _abi.ST_OK, L.stencil_last_error()
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    assert np.array_equal(got, ref_out.cpu().numpy())
+    ref = oracle.sweep(u, c, shape, r, wl.PERIODIC, steps)
+    assert rel_l2(got, ref) <= (1e-5 if dtype == "f32" else 2e-3)
+    return s
+
+
+def test_noalloc_matches_apply_on_shrinking_calls(L):
+    cap = L.stencil_noalloc_capacity()
+    assert cap == 64 << 20
+    keep = []
+    # first call: a large 2D grid (its ping-pong fills most of the array),
+    # then smaller ones, one of them in place with an odd launch count
+    keep.append(_linear_pair(L, 2, (4096, 3000), wl.STAR, 2, "f32", 7, False, 1))
+    keep.append(_linear_pair(L, 2, (300, 200), wl.BOX, 1, "f32", 5, True, 2))
+    keep.append(_linear_pair(L, 3, (96, 80, 64), wl.BOX, 1, "f16", 5, False, 3))
+    keep.append(_linear_pair(L, 3, (40, 33, 21), wl.STAR, 3, "f32", 3, True, 4))
+
+
+def test_noalloc_wave_in_place_matches_apply(L):
+    """Leapfrog in place (u_in == u_out, odd step count: the entry state is
+    staged in the scratch array), twice in a row with a smaller grid."""
+    for n, steps, seed in (((70, 52, 44), 5, 7), ((33, 30, 28), 3, 8)):
+        rng = np.random.default_rng(seed)
+        kappa = rng.uniform(0.05, 0.2, n[::-1]).astype(np.float32)
+        u0 = wl.gaussian_pulse(n, (n[0] // 2, n[1] // 2, n[2] // 2), 3.0)
+        up = rng.standard_normal(n[::-1]).astype(np.float32) * 0.01
+        m = stencil.WaveModel(n)
+        k = torch.from_numpy(kappa).cuda()
+        ro, rp, _ = m.forward(torch.from_numpy(u0).cuda(), torch.from_numpy(up).cuda(), k, steps)
+        a = torch.from_numpy(u0).cuda()
+        p = torch.from_numpy(up).cuda()
+        wa = _abi.StWaveArgs(ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                             (ctypes.c_int64 * 3)(-1, -1, -1), None, -1, None, None)
+        st = L.stencil_apply_noalloc(m.handle, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                     steps, ctypes.byref(wa), _stream())
+        assert st == _abi.ST_OK, L.stencil_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(a, ro) and torch.equal(p, rp)
+        ra, rb, _ = oracle.wave_forward(up, u0, kappa, steps)
+        assert rel_l2(a.cpu().numpy(), rb) <= 1e-5 and rel_l2(p.cpu().numpy(), ra) <= 1e-5
+
+
+def test_noalloc_rejects_oversized_and_batched_plans(L):
+    """A grid whose workspace exceeds the array is refused before any device
+    work, as are batched plans."""
+    s = stencil.Stencil((5000, 4000), "star", 1, np.array([0, .2, 0, .2, .2, .2, 0, .2, 0], np.float32))
+    fake = ctypes.c_void_p(0x1000)
+    assert L.stencil_apply_noalloc(s.handle, fake, fake, 3, None, _stream()) == _abi.ST_EWORKSPACE
+    assert b"64" in L.stencil_last_error() or b"67108864" in L.stencil_last_error()
+    assert L.stencil_apply_noalloc(None, fake, fake, 3, None, _stream()) == _abi.ST_EINVAL
+    bs = stencil.BatchedStencil([dict(n=(20, 16), shape="star", radius=1,
+                                      coeffs=np.array([0, .2, 0, .2, .2, .2, 0, .2, 0], np.float32))])
+    assert L.stencil_apply_noalloc(bs.handle, fake, fake, 3, None, _stream()) == _abi.ST_EINVAL
