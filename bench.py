@@ -48,9 +48,11 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--only", default="", help="comma list of extra workloads to run")
-    ap.add_argument("--pmc-target", action="store_true",
-                    help="run only the profiler target: a 512 MiB device copy (counter calibration) "
-                         "then one 2-step pass of the headline workload")
+    ap.add_argument("--pmc-target", nargs="?", const="wave", default="",
+                    help="run only a profiler target: a 512 MiB device copy (counter calibration), then "
+                         "a few launches of one workload: " + ", ".join(PMC_TARGETS))
+    ap.add_argument("--summarize-counters", nargs="*", default=None,
+                    help="instead of benchmarking: per-kernel means of rocprofv3 counter_collection.csv files")
     ap.add_argument("--shapes", action="store_true",
                     help="also sweep the 7- and 27-point 3D sweeps over cubes and slabs (f16/f32/f64)")
     ap.add_argument("--summarize-trace", default="",
@@ -64,23 +66,80 @@ def parse():
     return ap.parse_args()
 
 
-def pmc_target(dev, st, wl, torch):
-    """Profiler target: a device copy of known size (its FETCH_SIZE/WRITE_SIZE
-    calibrate the counters) followed by two leapfrog launches at 512^3."""
+PMC_TARGETS = ("wave", "box3d_f16", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16", "box2d_f32",
+               "batch64", "wavegrad")
+
+
+def pmc_target(name, dev, st, wl, torch):
+    """Profiler target: a device copy of known size (its FETCH_SIZE and
+    WRITE_SIZE calibrate the counters) followed by a few launches of one
+    workload at its full size."""
     a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     b.copy_(a)
     torch.cuda.synchronize()
-    case = wl.wave3d(n=512, steps=2)
-    u0 = torch.from_numpy(case.u0).to(dev)
-    prev = torch.from_numpy(case.u_prev).to(dev)
-    kap = torch.from_numpy(case.kappa).to(dev)
-    out = torch.empty_like(u0)
-    model = st.WaveModel(case.n, radius=4, boundary="zero")
-    model.forward(u0, prev, kap, 2, out=out, prev_inout=True)
+    del a, b
+    if name == "wave":
+        case = wl.wave3d(n=512, steps=2)
+        u0 = torch.from_numpy(case.u0).to(dev)
+        prev = torch.from_numpy(case.u_prev).to(dev)
+        kap = torch.from_numpy(case.kappa).to(dev)
+        out = torch.empty_like(u0)
+        model = st.WaveModel(case.n, radius=4, boundary="zero")
+        model.forward(u0, prev, kap, 2, out=out, prev_inout=True)
+    elif name in ("box3d_f16", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16", "box2d_f32"):
+        case = {"box3d_f16": lambda: wl.box3d(dtype=wl.F16), "box3d_f32": lambda: wl.box3d(dtype=wl.F32),
+                "box3d_f16_mfma": lambda: wl.box3d(dtype=wl.F16), "star3d_f16": lambda: wl.star3d(dtype=wl.F16),
+                "box2d_f16": lambda: wl.box2d(dtype=wl.F16), "box2d_f32": lambda: wl.box2d(dtype=wl.F32)}[name]()
+        opts = {"variant": 6} if name.endswith("mfma") else {}
+        s = st.Stencil(case.n[:case.ndim], wl.SHAPE_NAMES[case.shape], case.radius, case.coeffs,
+                       dtype=wl.DTYPE_TAGS[case.dtype], **opts)
+        u = torch.from_numpy(case.u0).to(dev)
+        k = fused_depth(s.describe(), case.ndim)
+        s.apply(u, 2 * k, out=torch.empty_like(u))   # two launches
+    elif name == "batch64":
+        cases = wl.batch2d()
+        bs = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
+                                for c in cases])
+        ins = [torch.from_numpy(c.u0).to(dev) for c in cases]
+        bs.apply(ins, 2 * max(1, bs.describe()["tsteps"]))
+    elif name == "wavegrad":
+        case = wl.wavegrad3d(steps=40)
+        n = case.n
+        z = torch.zeros(n[::-1], dtype=torch.float32, device=dev)
+        wav = torch.from_numpy(case.wavelet).to(dev)
+        model = st.WaveModel(n, ckpt_every=20)
+        _, _, target = model.forward(z, z, torch.from_numpy(case.kappa_true).to(dev), case.steps, src=case.src,
+                                     wavelet=wav, rec_z=case.rec_z, record=True)
+        model.gradient(z, z, torch.from_numpy(case.kappa).to(dev), case.steps, case.src, wav, case.rec_z,
+                       target.contiguous())
+    else:
+        raise SystemExit(f"unknown profiler target {name!r}; one of {PMC_TARGETS}")
     torch.cuda.synchronize()
-    log("pmc target done: copy 512 MiB, 2 wave launches")
+    log(f"pmc target {name} done")
+
+
+def summarize_counters(paths):
+    """Per-kernel means of the counters in rocprofv3 counter_collection.csv
+    files (one row per dispatch and counter).  Prints one JSON line."""
+    import csv
+    acc = {}
+    for path in paths:
+        with open(path, newline="") as f:
+            for rec in csv.DictReader(f):
+                k = rec.get("Kernel_Name", "")
+                c = rec.get("Counter_Name", "")
+                v = float(rec.get("Counter_Value") or 0)
+                d = rec.get("Dispatch_Id", "")
+                acc.setdefault(k, {}).setdefault(c, {}).setdefault(d, 0.0)
+                acc[k][c][d] += v   # counters reported per dimension instance are summed per dispatch
+    out = {}
+    for k, cs in acc.items():
+        out[k] = {c: {"dispatches": len(ds), "mean": float(np.mean(list(ds.values()))),
+                      "values": [round(v, 1) for v in ds.values()][:8]} for c, ds in cs.items()}
+    print(json.dumps(out), flush=True)
+    return out
 
 
 def stream_ceiling(dev, torch):
@@ -204,6 +263,31 @@ def bench_wave(args, dev, st, wl, torch):
     log(f"wave3d 512^3 x20: {ms_per_pass:.3f} ms/pass (events), wall {wall:.3f} ms/pass, "
         f"{launch_ms * 1e3:.1f} us/launch, finite={finite}")
     return case, ms_per_pass, launch_ms, model.describe(), finite
+
+
+SPONGE = (20, 0.5)   # absorbing layer of the sponge workload: width (cells), strength
+
+
+def bench_wave_sponge(dev, st, wl, torch):
+    """The headline wave workload with the absorbing layer fused into the
+    leapfrog kernel, against the plain leapfrog, interleaved passes."""
+    case = wl.wave3d(n=512, steps=20)
+    u0 = torch.from_numpy(case.u0).to(dev)
+    prev = torch.from_numpy(case.u_prev).to(dev)
+    kap = torch.from_numpy(case.kappa).to(dev)
+    out = torch.empty_like(u0)
+    plain = st.WaveModel(case.n, radius=4, boundary="zero")
+    damped = st.WaveModel(case.n, radius=4, boundary="zero", sponge=SPONGE)
+    pp, pd = prev.clone(), prev.clone()
+    ms_p, ms_d = timed_pair(lambda: plain.forward(u0, pp, kap, case.steps, out=out, prev_inout=True),
+                            lambda: damped.forward(u0, pd, kap, case.steps, out=out, prev_inout=True),
+                            REPS, 1, torch.cuda.synchronize)
+    g = gcells(case.cells, case.steps, ms_d)
+    return {"workload": f"wave3d_star4_512^3_20steps_sponge_w{SPONGE[0]}_s{SPONGE[1]}", "ms": ms_d,
+            "gcells_s": g, "bytes_per_cell_update": WAVE_BYTES_PER_CELL,
+            "hbm_frac": g * WAVE_BYTES_PER_CELL / HBM_PEAK_GBS, "ms_plain": ms_p,
+            "overhead_vs_plain": ms_d / ms_p, "dispatch": damped.describe(),
+            "timing": f"median of {REPS} passes interleaved with the plain leapfrog"}
 
 
 def bench_jacobi(dev, st, wl, torch):
@@ -523,6 +607,9 @@ def main():
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.kernel, args.skip)
         return
+    if args.summarize_counters is not None:
+        summarize_counters(args.summarize_counters)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the stencil library runs on one GPU; run with --gpus 1"}))
         sys.exit(2)
@@ -534,7 +621,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.pmc_target:
-        pmc_target(dev, st, wl, torch)
+        pmc_target(args.pmc_target, dev, st, wl, torch)
         return
 
     case, ms_pass, launch_ms, disp, finite = bench_wave(args, dev, st, wl, torch)
@@ -577,6 +664,7 @@ def main():
                 dev, st, wl, torch, wl.box2d(dtype=wl.F16), wl.box2d(dtype=wl.F32))))),
             ("batch64", lambda: {"batch64": bench_batch(dev, st, wl, torch)}),
             ("wavegrad", lambda: {"wavegrad": bench_grad(dev, st, wl, torch)}),
+            ("wave3d_sponge", lambda: {"wave3d_sponge": bench_wave_sponge(dev, st, wl, torch)}),
         ]
         for name, fn in todo:
             if only and name not in only:

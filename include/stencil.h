@@ -126,6 +126,21 @@ typedef struct {
     int64_t rec_z;         /* receiver plane z index, -1 = none */
     float *traces;         /* device, steps*ny*nx or NULL: traces[t] = plane rec_z of u_{t+1} */
     const float *target;   /* device, steps*ny*nx: observed traces d (gradient only) */
+    /* Absorbing layer (0 = none): a damping term gamma(x) u_t, from the
+     * damped wave equation u_tt + gamma u_t = c^2 Lap u with central
+     * differences in time, fused into the leapfrog (Section 4.3: stencils
+     * fused with the application's physics):
+     *   u_{t+1} = A (2 u_t + kappa L(u_t)) - B u_{t-1},
+     *   A = 1 / (1 + gamma/2),  B = (1 - gamma/2) / (1 + gamma/2),
+     * gamma(x) = sum over the three axes of s ((W - e) / W)^2 where the cell
+     * lies within W cells of a face, e its distance to the nearer face (0
+     * on a boundary cell), W = sponge_width, s = sponge_strength.  It needs
+     * the zero frame and the LDS-ring kernels (ST_EUNSUPPORTED otherwise);
+     * 0 <= W <= min(n) / 2 and 0 <= s <= 4, finite (ST_EINVAL otherwise).
+     * The same layer applies to stencil_apply, stencil_apply_adjoint (the
+     * transpose of the damped state map) and stencil_wave_gradient. */
+    int32_t sponge_width;
+    float sponge_strength;
 } st_wave_args;
 
 /* Create a plan.  Validates the problem (ST_EINVAL / ST_ESHAPE /

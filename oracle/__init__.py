@@ -58,6 +58,14 @@ def _load():
                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.oracle_wave_forward_stored.argtypes = lib.oracle_wave_forward.argtypes + [ctypes.c_int]
     lib.oracle_wave_gradient_stored.argtypes = lib.oracle_wave_gradient.argtypes + [ctypes.c_int]
+    lib.oracle_sponge_profile.argtypes = [_i64p, ctypes.c_int, ctypes.c_double, _dp]
+    lib.oracle_wave_forward_damped.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                               _dp, _dp, _dp, _dp, _i64p, _dp, ctypes.c_int64, _dp]
+    lib.oracle_wave_adjoint_damped.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                               _dp, _dp, _dp, _dp]
+    lib.oracle_wave_gradient_damped.argtypes = [_i64p, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                                _dp, _dp, _dp, _dp, _i64p, _dp, ctypes.c_int64, _dp,
+                                                ctypes.c_int, _dp, _dp]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -234,4 +242,66 @@ def wave_gradient(u_prev0, u0, kappa, steps: int, src, wavelet, rec_z: int, targ
         _check(lib.oracle_wave_gradient(*args), "wave_gradient")
     else:
         _check(lib.oracle_wave_gradient_stored(*args, _storage(storage)), "wave_gradient_stored")
+    return grad, float(loss.value)
+
+
+def sponge_profile(shape, width: int, strength: float) -> np.ndarray:
+    """Damping field gamma of the absorbing layer on a grid of array shape
+    (nz, ny, nx): a quadratic ramp of `width` cells along every face."""
+    g = np.empty(tuple(shape), dtype=np.float64)
+    _check(_load().oracle_sponge_profile(_n3(g.shape), int(width), float(strength), _ptr(g)), "sponge_profile")
+    return g
+
+
+def wave_forward_damped(u_prev, u0, kappa, gamma, steps: int, r: int = 4, boundary: int = 1,
+                        lap: Optional[np.ndarray] = None, src=None, wavelet=None, rec_z: int = -1):
+    """Damped leapfrog (absorbing layer with damping field gamma).  Returns
+    (u_{T-1}, u_T, traces or None)."""
+    lib = _load()
+    a = _f64(u_prev).copy()
+    b = _f64(u0).copy()
+    k = _f64(kappa)
+    gm = _f64(gamma)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    nz, ny, nx = b.shape
+    srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
+    wv = _f64(wavelet) if wavelet is not None else None
+    traces = np.zeros((steps, ny, nx), dtype=np.float64) if rec_z >= 0 else None
+    _check(lib.oracle_wave_forward_damped(_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k), _ptr(gm),
+                                          _ptr(a), _ptr(b), srcp, _ptr(wv) if wv is not None else None, rec_z,
+                                          _ptr(traces) if traces is not None else None), "wave_forward_damped")
+    return a, b, traces
+
+
+def wave_adjoint_damped(a_in, b_in, kappa, gamma, steps: int, r: int = 4, boundary: int = 1,
+                        lap: Optional[np.ndarray] = None):
+    """Transpose of the damped state map (u_{-1}, u_0) -> (u_{T-1}, u_T)."""
+    lib = _load()
+    a = _f64(a_in).copy()
+    b = _f64(b_in).copy()
+    k = _f64(kappa)
+    gm = _f64(gamma)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    _check(lib.oracle_wave_adjoint_damped(_n3(b.shape), r, _ptr(lp), boundary, steps, _ptr(k), _ptr(gm),
+                                          _ptr(a), _ptr(b)), "wave_adjoint_damped")
+    return a, b
+
+
+def wave_gradient_damped(u_prev0, u0, kappa, gamma, steps: int, src, wavelet, rec_z: int, target,
+                         ckpt_every: int = 0, r: int = 4, boundary: int = 1, lap: Optional[np.ndarray] = None):
+    """(dJ/dkappa, J) for the damped leapfrog."""
+    lib = _load()
+    k = _f64(kappa)
+    gm = _f64(gamma)
+    up = _f64(u_prev0)
+    u = _f64(u0)
+    lp = _f64(laplacian3d(r) if lap is None else lap)
+    tg = _f64(target)
+    wv = _f64(wavelet)
+    grad = np.empty_like(k)
+    loss = ctypes.c_double(0.0)
+    srcp = (ctypes.c_int64 * 3)(*src) if src is not None else None
+    _check(lib.oracle_wave_gradient_damped(_n3(k.shape), r, _ptr(lp), boundary, steps, _ptr(k), _ptr(gm), _ptr(up),
+                                           _ptr(u), srcp, _ptr(wv), rec_z, _ptr(tg), ckpt_every, _ptr(grad),
+                                           ctypes.byref(loss)), "wave_gradient_damped")
     return grad, float(loss.value)

@@ -22,6 +22,9 @@
  *    with its own checkpoint/recompute loop.
  *  - Central second-difference weights of order 2r from the Taylor moment
  *    conditions.
+ *  - An absorbing layer for the leapfrog (a damping term gamma(x) u_t in a
+ *    band of cells along the faces, the stencil fused with the boundary
+ *    physics, Section 4.3), its transposed state map and its kappa-gradient.
  *  - A diagnostic of the numerical floor: the same sweeps with every stored
  *    state rounded to binary32 or binary16 (FP64 arithmetic otherwise), to
  *    set a storage format's measured error against the error that format
@@ -352,16 +355,55 @@ int oracle_laplacian3d(int r, double *dense) {
     return 0;
 }
 
-/* One leapfrog step: next = 2 cur - prev + kappa * L(cur); then the source. */
+/*
+ * Absorbing layer.  The damped wave equation u_tt + gamma u_t = c^2 Lap u,
+ * with u_tt by the central second difference and u_t by the central first
+ * difference (u_{t+1} - u_{t-1}) / 2, gives the step
+ *     (1 + gamma/2) u_{t+1} = 2 u_t - (1 - gamma/2) u_{t-1} + kappa L(u_t),
+ * i.e. u_{t+1} = A (2 u_t + kappa L(u_t)) - B u_{t-1} with
+ * A = 1 / (1 + gamma/2), B = (1 - gamma/2) / (1 + gamma/2); gamma = 0 is the
+ * plain leapfrog.  The damping field is a sum over the axes of a quadratic
+ * ramp in the band of `width` cells along each face:
+ *     gamma(x) = sum_a s ((W - e_a) / W)^2 over axes with e_a < W,
+ * e_a = min(i_a, n_a - 1 - i_a) the distance of the cell from the nearer
+ * face (0 on a boundary cell), W = width, s = strength.
+ */
+int oracle_sponge_profile(const int64_t n[3], int width, double strength, double *gamma) {
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || width < 0 || !(strength >= 0.0)) return -12;
+    for (int64_t z = 0; z < n[2]; ++z)
+        for (int64_t y = 0; y < n[1]; ++y)
+            for (int64_t x = 0; x < n[0]; ++x) {
+                const int64_t idx[3] = {x, y, z};
+                double g = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t e = idx[a] < n[a] - 1 - idx[a] ? idx[a] : n[a] - 1 - idx[a];
+                    if (e < width) {
+                        const double q = (double)(width - e) / (double)width;
+                        g += strength * q * q;
+                    }
+                }
+                gamma[(z * n[1] + y) * n[0] + x] = g;
+            }
+    return 0;
+}
+
+/* One leapfrog step: next = 2 cur - prev + kappa * L(cur), or with a damping
+ * field (gamma != NULL) next = (2 cur - (1 - gamma/2) prev + kappa L(cur)) /
+ * (1 + gamma/2); then the source. */
 static void wave_step(const int64_t n[3], int r, const double *lap, int boundary,
-                      const double *kappa, const double *prev, const double *cur,
-                      double *next, double *scratch, const int64_t *src, double amp,
-                      int storage) {
+                      const double *kappa, const double *gamma, const double *prev,
+                      const double *cur, double *next, double *scratch, const int64_t *src,
+                      double amp, int storage) {
     const int64_t cells = cells_of(n);
     apply_once(3, n, OR_STAR, r, lap, boundary, +1, cur, scratch);
 #pragma omp parallel for schedule(static) num_threads(oracle_max_threads())
-    for (int64_t i = 0; i < cells; ++i)
-        next[i] = 2.0 * cur[i] - prev[i] + kappa[i] * scratch[i];
+    for (int64_t i = 0; i < cells; ++i) {
+        if (gamma)
+            next[i] = (2.0 * cur[i] - (1.0 - 0.5 * gamma[i]) * prev[i] + kappa[i] * scratch[i]) /
+                      (1.0 + 0.5 * gamma[i]);
+        else
+            next[i] = 2.0 * cur[i] - prev[i] + kappa[i] * scratch[i];
+    }
     if (src) next[(src[2] * n[1] + src[1]) * n[0] + src[0]] += amp;
     store_round_all(next, cells, storage);
 }
@@ -383,8 +425,8 @@ static int check_wave(const int64_t n[3], int r, int boundary, const int64_t *sr
  * lap is the dense (2r+1)^3 star coefficient array of L.
  */
 static int wave_forward_common(const int64_t n[3], int r, const double *lap, int boundary,
-                               int steps, const double *kappa, double *u_prev, double *u_cur,
-                               const int64_t *src, const double *wavelet, int64_t rec_z,
+                               int steps, const double *kappa, const double *gamma, double *u_prev,
+                               double *u_cur, const int64_t *src, const double *wavelet, int64_t rec_z,
                                double *traces, int storage) {
     int e = check_wave(n, r, boundary, src, rec_z);
     if (e) return e;
@@ -399,7 +441,7 @@ static int wave_forward_common(const int64_t n[3], int r, const double *lap, int
     memcpy(a, u_prev, sizeof(double) * (size_t)cells);
     memcpy(b, u_cur, sizeof(double) * (size_t)cells);
     for (int t = 0; t < steps; ++t) {
-        wave_step(n, r, lap, boundary, kappa, a, b, c, s, src, src ? wavelet[t] : 0.0, storage);
+        wave_step(n, r, lap, boundary, kappa, gamma, a, b, c, s, src, src ? wavelet[t] : 0.0, storage);
         if (rec_z >= 0) memcpy(traces + (int64_t)t * plane, c + rec_z * plane, sizeof(double) * (size_t)plane);
         double *tmp = a; a = b; b = c; c = tmp;
     }
@@ -413,7 +455,17 @@ int oracle_wave_forward(const int64_t n[3], int r, const double *lap, int bounda
                         int steps, const double *kappa, double *u_prev, double *u_cur,
                         const int64_t *src, const double *wavelet, int64_t rec_z,
                         double *traces) {
-    return wave_forward_common(n, r, lap, boundary, steps, kappa, u_prev, u_cur, src, wavelet,
+    return wave_forward_common(n, r, lap, boundary, steps, kappa, NULL, u_prev, u_cur, src, wavelet,
+                               rec_z, traces, OR_STORE_EXACT);
+}
+
+/* The leapfrog with the absorbing layer's damping field gamma (cells). */
+int oracle_wave_forward_damped(const int64_t n[3], int r, const double *lap, int boundary,
+                               int steps, const double *kappa, const double *gamma, double *u_prev,
+                               double *u_cur, const int64_t *src, const double *wavelet, int64_t rec_z,
+                               double *traces) {
+    if (!gamma) return -12;
+    return wave_forward_common(n, r, lap, boundary, steps, kappa, gamma, u_prev, u_cur, src, wavelet,
                                rec_z, traces, OR_STORE_EXACT);
 }
 
@@ -423,7 +475,7 @@ int oracle_wave_forward_stored(const int64_t n[3], int r, const double *lap, int
                                int steps, const double *kappa, double *u_prev, double *u_cur,
                                const int64_t *src, const double *wavelet, int64_t rec_z,
                                double *traces, int storage) {
-    return wave_forward_common(n, r, lap, boundary, steps, kappa, u_prev, u_cur, src, wavelet,
+    return wave_forward_common(n, r, lap, boundary, steps, kappa, NULL, u_prev, u_cur, src, wavelet,
                                rec_z, traces, storage);
 }
 
@@ -464,6 +516,48 @@ int oracle_wave_adjoint(const int64_t n[3], int r, const double *lap, int bounda
 }
 
 /*
+ * Transpose of the damped state map (u_{-1}, u_0) -> (u_{T-1}, u_T) (no
+ * source).  One damped step is the block matrix [[0, I], [-B, A (2I + K L)]]
+ * on (previous, current), A = diag(1 / (1 + gamma/2)), B = diag((1 - gamma/2)
+ * / (1 + gamma/2)), K = diag(kappa); its transpose [[0, -B], [I,
+ * (2I + L^T K) A]] maps the co-states (alpha, beta) of (u_t, u_{t+1}) to
+ * those of (u_{t-1}, u_t):
+ *     (alpha, beta) <- (-B beta, alpha + 2 A beta + L^T(kappa (.) A beta)),
+ * applied T times.  On entry a, b are the co-states of u_{T-1}, u_T; on exit
+ * those of u_{-1}, u_0.
+ */
+int oracle_wave_adjoint_damped(const int64_t n[3], int r, const double *lap, int boundary,
+                               int steps, const double *kappa, const double *gamma, double *a,
+                               double *b) {
+    int e = check_wave(n, r, boundary, NULL, -1);
+    if (e) return e;
+    if (steps < 0) return -6;
+    if (!gamma) return -12;
+    const int64_t cells = cells_of(n);
+    double *ab = (double *)malloc(sizeof(double) * (size_t)cells);   /* A beta */
+    double *kab = (double *)malloc(sizeof(double) * (size_t)cells);  /* kappa A beta */
+    double *s = (double *)malloc(sizeof(double) * (size_t)cells);
+    double *na = (double *)malloc(sizeof(double) * (size_t)cells);
+    if (!ab || !kab || !s || !na) { free(ab); free(kab); free(s); free(na); return -7; }
+    for (int t = steps - 1; t >= 0; --t) {
+        for (int64_t i = 0; i < cells; ++i) {
+            const double A = 1.0 / (1.0 + 0.5 * gamma[i]);
+            const double B = (1.0 - 0.5 * gamma[i]) / (1.0 + 0.5 * gamma[i]);
+            ab[i] = A * b[i];
+            kab[i] = kappa[i] * ab[i];
+            na[i] = -B * b[i];
+        }
+        apply_once(3, n, OR_STAR, r, lap, boundary, -1, kab, s);
+        for (int64_t i = 0; i < cells; ++i) {
+            b[i] = a[i] + 2.0 * ab[i] + s[i];
+            a[i] = na[i];
+        }
+    }
+    free(ab); free(kab); free(s); free(na);
+    return 0;
+}
+
+/*
  * Gradient of J(kappa) = 1/2 sum_{t=1..T} || P u_t - d_t ||^2, P = restriction
  * to the plane z = rec_z, d_t = target[t-1], with respect to kappa, at the
  * given (u_{-1}, u_0), source and wavelet.  Lagrangian of the leapfrog
@@ -476,7 +570,8 @@ int oracle_wave_adjoint(const int64_t n[3], int r, const double *lap, int bounda
  * *loss.
  */
 static int wave_gradient_common(const int64_t n[3], int r, const double *lap, int boundary,
-                                int steps, const double *kappa, const double *u_prev0,
+                                int steps, const double *kappa, const double *gamma,
+                                const double *u_prev0,
                                 const double *u0, const int64_t *src, const double *wavelet,
                                 int64_t rec_z, const double *target, int ckpt_every,
                                 double *grad, double *loss, int storage) {
@@ -515,7 +610,7 @@ static int wave_gradient_common(const int64_t n[3], int r, const double *lap, in
             memcpy(ck + (size_t)cells * 2 * (size_t)(t / K), p0, sizeof(double) * (size_t)cells);
             memcpy(ck + (size_t)cells * (2 * (size_t)(t / K) + 1), p1, sizeof(double) * (size_t)cells);
         }
-        wave_step(n, r, lap, boundary, kappa, p0, p1, p2, s, src, src ? wavelet[t] : 0.0, storage);
+        wave_step(n, r, lap, boundary, kappa, gamma, p0, p1, p2, s, src, src ? wavelet[t] : 0.0, storage);
         const double *d = target + (int64_t)t * plane;
         const double *pl = p2 + rec_z * plane;
         for (int64_t i = 0; i < plane; ++i) J += 0.5 * (pl[i] - d[i]) * (pl[i] - d[i]);
@@ -534,20 +629,33 @@ static int wave_gradient_common(const int64_t n[3], int r, const double *lap, in
         memcpy(states + cells, ck + (size_t)cells * (2 * (size_t)seg + 1), sizeof(double) * (size_t)cells);
         for (int t = t0; t < t1; ++t) {
             const int j = t - t0 + 1;
-            wave_step(n, r, lap, boundary, kappa, states + (size_t)cells * (j - 1),
+            wave_step(n, r, lap, boundary, kappa, gamma, states + (size_t)cells * (j - 1),
                       states + (size_t)cells * j, states + (size_t)cells * (j + 1), s,
                       src, src ? wavelet[t] : 0.0, storage);
         }
         const int tstart = (seg == nseg - 1) ? T : t1 - 1;
         for (int t = tstart; t >= t0; --t) {
             const double *ut = states + (size_t)cells * (t - t0 + 1);
-            /* gradient term lambda_{t+1} (.) L(u_t) */
+            /* gradient term lambda_{t+1} (.) L(u_t); damped: (A lambda_{t+1}) (.) L(u_t) */
             apply_once(3, n, OR_STAR, r, lap, boundary, +1, ut, s);
-            for (int64_t i = 0; i < cells; ++i) grad[i] = store_round(grad[i] + l1[i] * s[i], storage);
+            for (int64_t i = 0; i < cells; ++i) {
+                const double w = gamma ? l1[i] / (1.0 + 0.5 * gamma[i]) : l1[i];
+                grad[i] = store_round(grad[i] + w * s[i], storage);
+            }
             if (t >= 1) {
-                for (int64_t i = 0; i < cells; ++i) kl[i] = kappa[i] * l1[i];
+                /* damped: lambda_t = 2 A lambda_{t+1} + L^T(kappa A lambda_{t+1}) - B lambda_{t+2} + ... */
+                for (int64_t i = 0; i < cells; ++i)
+                    kl[i] = kappa[i] * (gamma ? l1[i] / (1.0 + 0.5 * gamma[i]) : l1[i]);
                 apply_once(3, n, OR_STAR, r, lap, boundary, -1, kl, s);
-                for (int64_t i = 0; i < cells; ++i) l0[i] = 2.0 * l1[i] - l2[i] + s[i];
+                for (int64_t i = 0; i < cells; ++i) {
+                    if (gamma) {
+                        const double A = 1.0 / (1.0 + 0.5 * gamma[i]);
+                        const double B = (1.0 - 0.5 * gamma[i]) * A;
+                        l0[i] = 2.0 * A * l1[i] - B * l2[i] + s[i];
+                    } else {
+                        l0[i] = 2.0 * l1[i] - l2[i] + s[i];
+                    }
+                }
                 const double *d = target + (int64_t)(t - 1) * plane;
                 const double *pl = ut + rec_z * plane;
                 double *lp = l0 + rec_z * plane;
@@ -567,7 +675,22 @@ int oracle_wave_gradient(const int64_t n[3], int r, const double *lap, int bound
                          const double *u0, const int64_t *src, const double *wavelet,
                          int64_t rec_z, const double *target, int ckpt_every,
                          double *grad, double *loss) {
-    return wave_gradient_common(n, r, lap, boundary, steps, kappa, u_prev0, u0, src, wavelet,
+    return wave_gradient_common(n, r, lap, boundary, steps, kappa, NULL, u_prev0, u0, src, wavelet,
+                                rec_z, target, ckpt_every, grad, loss, OR_STORE_EXACT);
+}
+
+/* The gradient of the misfit of the damped leapfrog (damping field gamma):
+ * with the step u_{t+1} = A (2 u_t + kappa L(u_t)) - B u_{t-1} + source, the
+ * Lagrangian gives lambda_t = 2 A lambda_{t+1} + L^T(kappa (.) A lambda_{t+1})
+ * - B lambda_{t+2} + P^T (P u_t - d_t) and dJ/dkappa = sum_t (A lambda_{t+1})
+ * (.) L(u_t). */
+int oracle_wave_gradient_damped(const int64_t n[3], int r, const double *lap, int boundary,
+                                int steps, const double *kappa, const double *gamma,
+                                const double *u_prev0, const double *u0, const int64_t *src,
+                                const double *wavelet, int64_t rec_z, const double *target,
+                                int ckpt_every, double *grad, double *loss) {
+    if (!gamma) return -12;
+    return wave_gradient_common(n, r, lap, boundary, steps, kappa, gamma, u_prev0, u0, src, wavelet,
                                 rec_z, target, ckpt_every, grad, loss, OR_STORE_EXACT);
 }
 
@@ -579,6 +702,6 @@ int oracle_wave_gradient_stored(const int64_t n[3], int r, const double *lap, in
                                 const double *u0, const int64_t *src, const double *wavelet,
                                 int64_t rec_z, const double *target, int ckpt_every,
                                 double *grad, double *loss, int storage) {
-    return wave_gradient_common(n, r, lap, boundary, steps, kappa, u_prev0, u0, src, wavelet,
+    return wave_gradient_common(n, r, lap, boundary, steps, kappa, NULL, u_prev0, u0, src, wavelet,
                                 rec_z, target, ckpt_every, grad, loss, storage);
 }

@@ -49,7 +49,7 @@ class StPlanOpts(ctypes.Structure):
 class StWaveArgs(ctypes.Structure):
     _fields_ = [("u_prev", ctypes.c_void_p), ("kappa", ctypes.c_void_p), ("src", ctypes.c_int64 * 3),
                 ("wavelet", ctypes.c_void_p), ("rec_z", ctypes.c_int64), ("traces", ctypes.c_void_p),
-                ("target", ctypes.c_void_p)]
+                ("target", ctypes.c_void_p), ("sponge_width", ctypes.c_int32), ("sponge_strength", ctypes.c_float)]
 
 
 class StencilError(RuntimeError):

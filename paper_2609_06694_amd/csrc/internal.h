@@ -49,7 +49,22 @@ struct WaveLaunch {
     float* lap_out;         // fwd (ring kernel): receives L(u_t) at every cell, or null
     const float* lap;       // gradPt: L(u_t), or null (no gradient update this step)
     const float* trace_res; // gradPt: u_t on plane rec_z (ny*nx), used with target_t
+    // Absorbing layer (sp_w > 0): damping gamma(x) = sum over axes of
+    // sp_s ((W - e) / W)^2 within W = sp_w cells of a face (e = distance to
+    // the nearer face); step u_{t+1} = A (2 u_t + kappa L u_t) - B u_{t-1},
+    // A = 1 / (1 + gamma/2), B = (1 - gamma/2) A.  Ring kernels only.
+    int sp_w;
+    float sp_s, sp_invw;
+    bool prev_damped;       // adj: the prev term carries B (false on the first transposed step)
+    bool exact_update;      // fwd (ring kernel): state update in FP64, rounded once
 };
+
+// Damping ramp of the absorbing layer along one axis at index i of n cells.
+__device__ __forceinline__ float sponge_ramp(int i, int n, int w, float s, float invw) {
+    const int e = min(i, n - 1 - i);
+    const float q = (float)max(w - e, 0) * invw;
+    return s * q * q;
+}
 
 // Two fused forward leapfrog steps: (u_{t-1}, u_t) -> (u_{t+1}, u_{t+2}).
 // out1/out2 must not alias prev/cur (other workgroups read their halos).
@@ -132,6 +147,8 @@ inline hipError_t launch_wave_adjoint(const Geom& g, const LaunchCfg& cfg, const
     return launch_wave3d(g, cfg, taps, taps_fwd, mode, w, stream);
 }
 hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hipStream_t stream);
+// dst = alpha * B(x) * dst with B the absorbing layer's damping of u_{t-1}.
+hipError_t launch_sponge_scale(const Geom& g, float* dst, float alpha, int w, float s, hipStream_t stream);
 hipError_t launch_fill(float* dst, float v, size_t n, hipStream_t stream);
 // loss = 1/2 sum (traces - target)^2 in double, two fixed-order passes
 // through `parts` (kLossParts doubles of scratch): deterministic.

@@ -290,6 +290,29 @@ hipError_t launch_scale(float* dst, const float* src, float alpha, size_t n, hip
     return hipGetLastError();
 }
 
+// dst = alpha * B(x) * dst, B = (1 - gamma/2) / (1 + gamma/2) of the
+// absorbing layer (one thread per cell of an x row; grid: rows).
+__global__ void sponge_scale_kernel(float* dst, float alpha, int nx, int ny, int nz, int w, float s, float invw) {
+    const int row = blockIdx.x;   // y + ny * z
+    const int y = row % ny, z = row / ny;
+    const float gyz = sponge_ramp(y, ny, w, s, invw) + sponge_ramp(z, nz, w, s, invw);
+    float* p = dst + (size_t)row * nx;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        const float gm = gyz + sponge_ramp(x, nx, w, s, invw);
+        const float A = __builtin_amdgcn_rcpf(1.f + 0.5f * gm);
+        p[x] = alpha * ((1.f - 0.5f * gm) * A) * p[x];
+    }
+}
+
+hipError_t launch_sponge_scale(const Geom& g, float* dst, float alpha, int w, float s, hipStream_t stream) {
+    const size_t rows = (size_t)g.ny * g.nz;
+    if (rows == 0 || g.nx == 0) return hipSuccess;
+    if (rows > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sponge_scale_kernel, dim3((unsigned)rows), dim3(kThreads), 0, stream, dst, alpha, g.nx,
+                       g.ny, g.nz, w, s, w > 0 ? 1.f / (float)w : 0.f);
+    return hipGetLastError();
+}
+
 __global__ void fill_kernel(float* dst, float v, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;

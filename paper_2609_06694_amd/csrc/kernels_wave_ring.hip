@@ -17,7 +17,7 @@
 
 namespace stk {
 
-template <int R, int BC, int RY, int NW, int D, bool ISO, bool LAP = false>
+template <int R, int BC, int RY, int NW, int D, bool ISO, bool LAP = false, bool SP = false>
 __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
                                                                  int zc, int tiles_x, int tiles_y,
                                                                  Taps tp) {
@@ -51,6 +51,14 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
 
     // In-plane addressing, the same for every plane of the march.
     const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, float, NW>(nx, ny, x0, y0);
+    // Absorbing layer: the x and y part of the damping at this thread's
+    // cells, fixed for the march (the z part is uniform per plane).
+    float gxy[RY];
+#pragma unroll
+    for (int i = 0; i < RY; ++i)
+        gxy[i] = SP ? sponge_ramp(gx, nx, w.sp_w, w.sp_s, w.sp_invw) +
+                          sponge_ramp(y0 + ty * RY + i, ny, w.sp_w, w.sp_s, w.sp_invw)
+                    : 0.f;
 
     // Unconditional loads (clamped to the chunk; the interior offsets of
     // pidx are valid addresses, and values at cells outside the grid are
@@ -127,8 +135,37 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
                     const int gy = y0 + ty * RY + i;
                     if (gy >= ny) continue;
                     const uint32_t o = (uint32_t)(gy * nx + gx);
-                    float v = 2.f * uo - pv[d][i] + kv[d][i] * a;
-                    if (zo == w.src_z && gy == w.src_y && gx == w.src_x) v += amp;
+                    // The state update.  With w.exact_update (the gradient's
+                    // forward and recompute steps) it is evaluated in FP64 and
+                    // rounded once: the misfit gradient is linear in the
+                    // small residual P u - d and amplifies the state's error
+                    // by about |d| / |r|, and f32 arithmetic would round
+                    // 2u - u_prev and then the sum.  The source cell always
+                    // takes that path: its large value radiates its rounding.
+                    const bool at_src = zo == w.src_z && gy == w.src_y && gx == w.src_x;
+                    float v;
+                    if constexpr (SP) {
+                        // Damped step A (2u + kappa L u) - B u_prev.
+                        const float gm = gxy[i] + sponge_ramp(zo, nz, w.sp_w, w.sp_s, w.sp_invw);
+                        const float A = __builtin_amdgcn_rcpf(1.f + 0.5f * gm);
+                        const float B = (1.f - 0.5f * gm) * A;
+                        if (w.exact_update || at_src) {
+                            double vd = fma((double)A, fma((double)kv[d][i], (double)a, 2.0 * (double)uo),
+                                            -(double)B * (double)pv[d][i]);
+                            if (at_src) vd += (double)amp;
+                            v = (float)vd;
+                        } else {
+                            v = fmaf(A, fmaf(kv[d][i], a, 2.f * uo), -B * pv[d][i]);
+                        }
+                    } else {
+                        if (w.exact_update || at_src) {
+                            double vd = fma((double)kv[d][i], (double)a, 2.0 * (double)uo - (double)pv[d][i]);
+                            if (at_src) vd += (double)amp;
+                            v = (float)vd;
+                        } else {
+                            v = fmaf(kv[d][i], a, 2.f * uo - pv[d][i]);
+                        }
+                    }
                     if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
                     if constexpr (LAP) __builtin_nontemporal_store(a, &w.lap_out[zoff + o]);
                     __builtin_nontemporal_store(v, &np_[o]);
@@ -146,7 +183,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
 
 bool wave3d_ring_supported(int r) { return r >= 1 && r <= 4; }
 
-template <int R, int BC, int RY, int NW>
+template <int R, int BC, int RY, int NW, bool SP>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
     using G = PlaneGeom<R, RY, NW>;
     constexpr int D = 2;
@@ -155,20 +192,32 @@ static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w,
     const dim3 grid(tiles_x * tiles_y * nchunks), block(G::NT);
     if (w.lap_out) {   // also write L(u_t) (gradient recompute)
         if (g.iso)
-            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, true>), grid, block, 0, s, w, g.nx,
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, true, SP>), grid, block, 0, s, w, g.nx,
                                g.ny, g.nz, zc, tiles_x, tiles_y, tp);
         else
-            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, true>), grid, block, 0, s, w, g.nx,
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, true, SP>), grid, block, 0, s, w, g.nx,
                                g.ny, g.nz, zc, tiles_x, tiles_y, tp);
         return hipGetLastError();
     }
     if (g.iso)
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true>), grid, block, 0, s, w, g.nx,
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, false, SP>), grid, block, 0, s, w, g.nx,
                            g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     else
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false>), grid, block, 0, s, w, g.nx,
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, false, SP>), grid, block, 0, s, w, g.nx,
                            g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     return hipGetLastError();
+}
+
+// The absorbing layer is provided with the zero frame only (its damping band
+// lines the faces of a bounded domain).
+template <int R, int BC, int RY, int NW>
+static hipError_t go_sp(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
+    if constexpr (BC == kZero) {
+        if (w.sp_w > 0) return go<R, BC, RY, NW, true>(g, zc, tp, w, s);
+    } else {
+        if (w.sp_w > 0) return hipErrorInvalidValue;
+    }
+    return go<R, BC, RY, NW, false>(g, zc, tp, w, s);
 }
 
 template <int R, int BC>
@@ -178,9 +227,9 @@ static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const
     // Two rows per thread at every tile height: taller tiles add waves (up
     // to 16, a 1024-thread workgroup) rather than registers, so occupancy
     // stays at four waves per SIMD while the halo share of each plane falls.
-    if (c.tile_y >= 32) return go<R, BC, 2, 16>(g, zc, tp, w, s);
-    if (c.tile_y >= 16) return go<R, BC, 2, 8>(g, zc, tp, w, s);
-    return go<R, BC, 2, 4>(g, zc, tp, w, s);
+    if (c.tile_y >= 32) return go_sp<R, BC, 2, 16>(g, zc, tp, w, s);
+    if (c.tile_y >= 16) return go_sp<R, BC, 2, 8>(g, zc, tp, w, s);
+    return go_sp<R, BC, 2, 4>(g, zc, tp, w, s);
 }
 
 template <int R>

@@ -23,7 +23,13 @@ namespace stk {
 // weights) v(x), so the reverse sweep applies exactly the transpose of the
 // operator the forward sweep applies (a direct weighted sum with an f32
 // centre weight would differ from it by up to half an ulp of that weight).
-template <int MODE, int R, int BC, int RY, int NW, int D, bool ISO>
+//
+// With the absorbing layer (SP) the step is u_{t+1} = A (2 u_t + kappa L u_t)
+// - B u_{t-1}, and the transposed step becomes
+//   l_t = 2 A l_{t+1} + L^T(kappa (.) A l_{t+1}) - B l_{t+2} (+ residual),
+//   g  += (A l_{t+1}) (.) L(u_t):
+// the staged field is kappa A l_{t+1} (A at every staged cell, halo included).
+template <int MODE, int R, int BC, int RY, int NW, int D, bool ISO, bool SP = false>
 __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 1) void wave3d_ring_adj_kernel(WaveLaunch w, int nx, int ny,
                                                                      int nz, int zc, int tiles_x,
                                                                      int tiles_y, Taps tp, Taps tp2) {
@@ -64,6 +70,23 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
 
     // In-plane addressing, the same for every plane and field of the march.
     const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, float, NW>(nx, ny, x0, y0);
+    // Absorbing layer: the x and y part of the damping at this thread's
+    // interior and halo cells, fixed for the march.
+    float gin[SP ? RY : 1], ghalo[SP ? G::HT : 1];
+    if constexpr (SP) {
+#pragma unroll
+        for (int i = 0; i < RY; ++i)
+            gin[i] = sponge_ramp(gx, nx, w.sp_w, w.sp_s, w.sp_invw) +
+                     sponge_ramp(y0 + ty * RY + i, ny, w.sp_w, w.sp_s, w.sp_invw);
+#pragma unroll
+        for (int j = 0; j < G::HT; ++j) {
+            const int h = threadIdx.x + j * G::NT;
+            int ly, lx;
+            halo_coord<R, RY, NW>(h < G::NH ? h : 0, ly, lx);
+            ghalo[j] = sponge_ramp(x0 - R + lx, nx, w.sp_w, w.sp_s, w.sp_invw) +
+                       sponge_ramp(y0 - R + ly, ny, w.sp_w, w.sp_s, w.sp_invw);
+        }
+    }
     auto issue_plane = [&](int slot, int zp) __attribute__((always_inline)) {
         zp = min(zp, zend - 1);
         vm[slot] = load_plane_at<R, RY, BC, float, NW>(w.cur, nx, ny, nz, zp, pidx, vin[slot], vhalo[slot]);
@@ -97,6 +120,13 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int zp = zs + d;   // planes past zend: clamped loads, no output
+            if constexpr (SP) {   // kappa -> kappa A on plane zp
+                const float gz = sponge_ramp(zp, nz, w.sp_w, w.sp_s, w.sp_invw);
+#pragma unroll
+                for (int i = 0; i < RY; ++i) kin[d][i] *= __builtin_amdgcn_rcpf(1.f + 0.5f * (gin[i] + gz));
+#pragma unroll
+                for (int j = 0; j < G::HT; ++j) khalo[d][j] *= __builtin_amdgcn_rcpf(1.f + 0.5f * (ghalo[j] + gz));
+            }
             float* t1 = tile[0][zp & 1];
             store_plane<R, RY, BC, true, float, NW>(t1, vin[d], vhalo[d], vm[d], kin[d], khalo[d]);
 #pragma unroll
@@ -155,14 +185,23 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
                     const int gy = y0 + ty * RY + i;
                     if (gy >= ny) continue;
                     const uint32_t o = (uint32_t)(gy * nx + gx);
+                    // Damping of the output cell: l_{t+1} enters as A l_{t+1}
+                    // and l_{t+2} as B l_{t+2} (1 and 1 without the layer).
+                    float Al = lq[0][i], Bp = p2v[d][i];
+                    if constexpr (SP) {
+                        const float gm = gin[i] + sponge_ramp(zo, nz, w.sp_w, w.sp_s, w.sp_invw);
+                        const float A = __builtin_amdgcn_rcpf(1.f + 0.5f * gm);
+                        Al *= A;
+                        if (MODE != kWaveAdj || w.prev_damped) Bp *= (1.f - 0.5f * gm) * A;
+                    }
                     float v;
                     if constexpr (MODE == kWaveAdj) {
-                        v = 2.f * lq[0][i] - w.prev_sign * p2v[d][i] + a;
+                        v = 2.f * Al - w.prev_sign * Bp + a;
                     } else if constexpr (PT) {
-                        v = 2.f * lq[0][i] - p2v[d][i] + a;
+                        v = 2.f * Al - Bp + a;
                         if (w.target_t != nullptr && zo == w.rec_z) v += w.trace_res[o] - w.target_t[o];
                         if (w.lap != nullptr)
-                            __builtin_nontemporal_store(fmaf(lq[0][i], luv[d][i], gv[d][i]), &w.grad[zoff + o]);
+                            __builtin_nontemporal_store(fmaf(Al, luv[d][i], gv[d][i]), &w.grad[zoff + o]);
                     } else {
                         const float uo = ring[1][sl[R]][cell];
                         float a2 = pq2[0][i];
@@ -176,9 +215,9 @@ __global__ __launch_bounds__(NW * kWave, (MODE == kWaveGradPt && NW == 8) ? 4 : 
                             }
                         }
                         a2 = fmaf(tp2.sum, uo, a2);
-                        v = 2.f * lq[0][i] - p2v[d][i] + a;
+                        v = 2.f * Al - Bp + a;
                         if (w.target_t != nullptr && zo == w.rec_z) v += ring[1][sl[R]][cell] - w.target_t[o];
-                        __builtin_nontemporal_store(fmaf(lq[0][i], a2, gv[d][i]), &w.grad[zoff + o]);
+                        __builtin_nontemporal_store(fmaf(Al, a2, gv[d][i]), &w.grad[zoff + o]);
                     }
                     __builtin_nontemporal_store(v, &w.next[zoff + o]);
                 }
@@ -204,12 +243,26 @@ static hipError_t go_adj(const Geom& g, int zc, const Taps& tp, const Taps& tp2,
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = MODE == kWaveGradPt ? 1 : 2;   // planes in flight (registers: see the kernel)
+    const dim3 grid(tiles_x * tiles_y * nchunks), block(G::NT);
+    // The absorbing layer lines the faces of a bounded domain: zero frame only.
+    if (w.sp_w > 0) {
+        if constexpr (BC == kZero && MODE != kWaveGrad) {
+            if (g.iso)
+                hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, true, true>), grid, block, 0, s, w,
+                                   g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+            else
+                hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, false, true>), grid, block, 0, s, w,
+                                   g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (g.iso)
-        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, true>), dim3(tiles_x * tiles_y * nchunks),
-                           dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, true>), grid, block, 0, s, w, g.nx, g.ny,
+                           g.nz, zc, tiles_x, tiles_y, tp, tp2);
     else
-        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, false>), dim3(tiles_x * tiles_y * nchunks),
-                           dim3(G::NT), 0, s, w, g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp, tp2);
+        hipLaunchKernelGGL((wave3d_ring_adj_kernel<MODE, R, BC, 2, NW, D, false>), grid, block, 0, s, w, g.nx, g.ny,
+                           g.nz, zc, tiles_x, tiles_y, tp, tp2);
     return hipGetLastError();
 }
 

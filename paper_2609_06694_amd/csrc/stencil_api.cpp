@@ -285,14 +285,22 @@ st_status run_linear(const st_plan* pl, const Taps& taps, const void* u_in, void
     return ST_OK;
 }
 
-WaveLaunch wave_base() {
+WaveLaunch wave_base(const st_wave_args* wa = nullptr) {
     WaveLaunch w;
     memset(&w, 0, sizeof w);
     w.src_x = -1;
     w.rec_z = -1;
     w.prev_sign = 1.f;
+    w.prev_damped = true;
+    if (wa && wa->sponge_width > 0) {
+        w.sp_w = wa->sponge_width;
+        w.sp_s = wa->sponge_strength;
+        w.sp_invw = 1.f / (float)wa->sponge_width;
+    }
     return w;
 }
+
+bool has_sponge(const st_wave_args* wa) { return wa && wa->sponge_width > 0; }
 
 bool use_tb2(const st_plan* pl) {
     return pl->cfg.variant == ST_VARIANT_WAVE3D && pl->cfg.tsteps == 2 &&
@@ -394,7 +402,7 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
         if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
         return ST_OK;
     }
-    if (!adjoint && steps >= 2 && use_tb2(pl))
+    if (!adjoint && steps >= 2 && use_tb2(pl) && !has_sponge(wa))
         return run_wave_tb2(pl, u_in, u_out, steps, wa, ws, ws_bytes, s);
     if (u_in == u_out && (steps % 2) == 1) {
         if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
@@ -406,7 +414,7 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
     const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1];
     for (int t = 0; t < steps; ++t) {
         float* next = ((steps - (t + 1)) % 2 == 0) ? O : P;
-        WaveLaunch w = wave_base();
+        WaveLaunch w = wave_base(wa);
         w.prev = prev;
         w.cur = cur;
         w.next = next;
@@ -424,7 +432,10 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
             }
             HIP_TRY(wave_forward_launch(pl, w, s));
         } else {
+            // The first transposed step takes the co-state of u_{T-1} as is;
+            // later ones take B l_{t+2} (damped layer).
             w.prev_sign = t == 0 ? -1.f : 1.f;
+            w.prev_damped = t != 0;
             HIP_TRY(launch_wave_adjoint(g, pl->adj_cfg, pl->taps_t, pl->taps, kWaveAdj, w, s));
         }
         prev = cur;
@@ -432,7 +443,11 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
     }
     // u_{T-1} (or lambda_1) must end in the caller's prev buffer.
     if (prev != P) HIP_TRY(hipMemcpyAsync(P, prev, gb, hipMemcpyDeviceToDevice, s));
-    if (adjoint) HIP_TRY(launch_scale(P, P, -1.f, cells_of(pl->prob), s));
+    // Co-state of u_{-1}: -l_1, or -B l_1 with the absorbing layer.
+    if (adjoint && has_sponge(wa))
+        HIP_TRY(launch_sponge_scale(g, P, -1.f, wa->sponge_width, wa->sponge_strength, s));
+    else if (adjoint)
+        HIP_TRY(launch_scale(P, P, -1.f, cells_of(pl->prob), s));
     return ST_OK;
 }
 
@@ -446,6 +461,18 @@ st_status check_wave_args(const st_plan* pl, const st_wave_args* wa, bool need_k
             if (wa->src[a] < 0 || wa->src[a] >= p.n[a]) ST_FAIL(ST_EINVAL, "source outside the grid");
     }
     if (wa->rec_z >= p.n[2] || wa->rec_z < -1) ST_FAIL(ST_EINVAL, "receiver plane outside the grid");
+    if (wa->sponge_width != 0 || wa->sponge_strength != 0.f) {
+        const int64_t nmin = std::min(p.n[0], std::min(p.n[1], p.n[2]));
+        if (wa->sponge_width < 0 || wa->sponge_width > nmin / 2)
+            ST_FAIL(ST_EINVAL, "sponge_width must lie in 0..min(n)/2");
+        if (!(wa->sponge_strength >= 0.f && wa->sponge_strength <= 4.f))
+            ST_FAIL(ST_EINVAL, "sponge_strength must lie in [0, 4]");
+    }
+    if (wa->sponge_width > 0) {
+        if (p.boundary != ST_ZERO) ST_FAIL(ST_EUNSUPPORTED, "the absorbing layer needs the zero frame");
+        if (pl->cfg.variant != ST_VARIANT_WAVE3D_LDS || pl->adj_cfg.variant != ST_VARIANT_WAVE3D_LDS)
+            ST_FAIL(ST_EUNSUPPORTED, "the absorbing layer is fused into the LDS-ring kernels only");
+    }
     return ST_OK;
 }
 
@@ -691,7 +718,11 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
 
     auto fwd_step = [&](const float* prev, const float* cur, float* next, int t, bool record,
                         float* lap_out = nullptr) {
-        WaveLaunch w = wave_base();
+        WaveLaunch w = wave_base(wave);
+        // The misfit gradient is linear in the small residual P u - d, which
+        // amplifies the states' rounding by |d| / |r|: the gradient's forward
+        // and recompute steps round each state once (FP64 update).
+        w.exact_update = true;
         w.prev = prev;
         w.cur = cur;
         w.next = next;
@@ -767,7 +798,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
         }
         const int tstart = (seg == S - 1) ? T : t1 - 1;
         for (int t = tstart; t >= t0; --t) {
-            WaveLaunch w = wave_base();
+            WaveLaunch w = wave_base(wave);
             w.prev = l_next2;
             w.cur = l_next;
             w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place

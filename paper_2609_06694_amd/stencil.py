@@ -252,10 +252,17 @@ def sweep(u: torch.Tensor, stencil: Stencil, steps: int) -> torch.Tensor:
 
 class WaveModel(_Plan):
     """3D leapfrog u_{t+1} = 2u_t - u_{t-1} + kappa * L(u_t), L a radius-r star
-    (default: the order-2r central second-difference Laplacian)."""
+    (default: the order-2r central second-difference Laplacian).
 
-    def __init__(self, n: Sequence[int], radius: int = 4, boundary="zero", coeffs=None, **opts):
+    sponge=(width, strength) adds the absorbing layer: a damping field
+    gamma = sum over axes of strength ((width - e) / width)^2 within `width`
+    cells of each face, and the step u_{t+1} = A (2u_t + kappa L u_t) -
+    B u_{t-1} with A = 1/(1 + gamma/2), B = (1 - gamma/2) A; it applies to
+    the forward, adjoint and gradient calls alike."""
+
+    def __init__(self, n: Sequence[int], radius: int = 4, boundary="zero", coeffs=None, sponge=None, **opts):
         super().__init__()
+        self.sponge = (0, 0.0) if sponge is None else (int(sponge[0]), float(sponge[1]))
         self.n = tuple(int(v) for v in n)
         keep: list = []
         prob = _problem(3, self.n, _abi.ST_STAR, radius, coeffs, _abi.ST_F32, _enum(_BC, boundary),
@@ -297,7 +304,7 @@ class WaveModel(_Plan):
             raise ValueError("kappa is required")
         s = (-1, -1, -1) if src is None else tuple(int(v) for v in src)
         return _abi.StWaveArgs(_ptr(u_prev), _ptr(kappa), (ctypes.c_int64 * 3)(*s), _ptr(wavelet),
-                               int(rec_z), _ptr(traces), _ptr(target))
+                               int(rec_z), _ptr(traces), _ptr(target), self.sponge[0], self.sponge[1])
 
     def _workspace(self, device, nbytes):
         if self._ws is None:

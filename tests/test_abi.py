@@ -333,3 +333,34 @@ def test_binding_rejects_misshaped_wave_and_batch_operands(L):
         bs.apply([torch.zeros((16, 20))], 2)   # host tensor
     with pytest.raises(ValueError, match="one output"):
         bs.apply([torch.zeros((16, 20))], 2, outs=[])
+
+
+def test_sponge_argument_checks_before_device(L):
+    """The absorbing layer needs the zero frame and the LDS-ring kernels;
+    width and strength are range-checked on the host."""
+    fake = ctypes.c_void_p(0x1000)
+
+    def wa(width, strength):
+        return _abi.StWaveArgs(ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), (ctypes.c_int64 * 3)(-1, 0, 0),
+                               None, -1, None, None, width, strength)
+
+    p, keep = _prob(ndim=3, n=(32, 24, 20), update=1, coeffs=None, bc=1, r=4)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    for width, strength in ((11, 0.5), (-1, 0.5), (4, -0.1), (4, float("nan")), (4, 5.0)):
+        assert L.stencil_apply(h, fake, ctypes.c_void_p(0x2000), 2, ctypes.byref(wa(width, strength)), None, 0,
+                               None) == _abi.ST_EINVAL, (width, strength)
+        assert L.stencil_apply_adjoint(h, fake, ctypes.c_void_p(0x2000), 2, ctypes.byref(wa(width, strength)),
+                                       None, 0, None) == _abi.ST_EINVAL
+    L.stencil_plan_destroy(h)
+    p, keep = _prob(ndim=3, n=(32, 24, 20), update=1, coeffs=None, bc=0, r=4)   # periodic
+    st, h = _plan(L, p)
+    assert L.stencil_apply(h, fake, ctypes.c_void_p(0x2000), 2, ctypes.byref(wa(4, 0.5)), None, 0,
+                           None) == _abi.ST_EUNSUPPORTED
+    L.stencil_plan_destroy(h)
+    p, keep = _prob(ndim=3, n=(32, 24, 20), update=1, coeffs=None, bc=1, r=4)
+    st, h = _plan(L, p, _abi.StPlanOpts(_abi.ST_VARIANT_WAVE3D, 0, 0, 0, 0, 0))   # partial-sum family
+    assert st == _abi.ST_OK
+    assert L.stencil_apply(h, fake, ctypes.c_void_p(0x2000), 2, ctypes.byref(wa(4, 0.5)), None, 0,
+                           None) == _abi.ST_EUNSUPPORTED
+    L.stencil_plan_destroy(h)

@@ -493,3 +493,149 @@ def test_stored_gradient_exact_mode_and_floor_size(oracle_lib):
     assert 0 < e < 1e-3
     with pytest.raises(ValueError):
         oracle_lib.wave_gradient(zeros, zeros, kappa, T, src, wav, rec, target, storage="binary8")
+
+
+# ---- Absorbing layer: damped leapfrog, its transpose and its gradient ----
+
+def test_sponge_profile_shape(oracle_lib):
+    """Zero away from the faces, the full strength on a face cell, the sum of
+    the axes' ramps on edges and corners, symmetric about each mid-plane."""
+    W, s = 3, 0.7
+    g = oracle_lib.sponge_profile((9, 10, 12), W, s)   # (nz, ny, nx)
+    assert np.all(g[W:-W, W:-W, W:-W] == 0)
+    assert g[5, 5, 0] == s and g[5, 5, 11] == s
+    assert abs(g[5, 5, 1] - s * (2 / 3) ** 2) < 1e-15 and abs(g[5, 5, 2] - s * (1 / 3) ** 2) < 1e-15
+    assert abs(g[0, 0, 0] - 3 * s) < 1e-15
+    assert np.array_equal(g, g[::-1, ::-1, ::-1])
+    assert np.all(oracle_lib.sponge_profile((9, 10, 12), 0, s) == 0)
+
+
+def _damped_case(rng, n, W=2, s=0.9):
+    kappa = rng.uniform(0.05, 0.2, n)
+    gamma = oracle_lib_profile(n, W, s)
+    return kappa, gamma
+
+
+def oracle_lib_profile(n, W, s):
+    import oracle
+    return oracle.sponge_profile(n, W, s)
+
+
+def test_damped_forward_brute_force_and_zero_damping(oracle_lib):
+    """The damped step against dense matrices, u_{t+1} = A(2u + K M u) - B u_prev
+    (A = 1/(1+gamma/2), B = (1-gamma/2)/(1+gamma/2)), with source and receiver;
+    a zero damping field gives the plain leapfrog bit for bit."""
+    rng = np.random.default_rng(81)
+    n = (6, 7, 5)
+    kappa, gamma = _damped_case(rng, n)
+    up, u0 = rng.standard_normal(n), rng.standard_normal(n)
+    M = mr.operator_matrix(n, mr.laplacian_dense_fd8(), STAR, 4, ZERO)
+    g = gamma.ravel()
+    A, B = 1 / (1 + g / 2), (1 - g / 2) / (1 + g / 2)
+    src, wav = (2, 3, 1), rng.standard_normal(5)
+    a, b = up.ravel().copy(), u0.ravel().copy()
+    traces = []
+    for t in range(5):
+        c = A * (2 * b + kappa.ravel() * (M @ b)) - B * a
+        c[(src[2] * n[1] + src[1]) * n[2] + src[0]] += wav[t]
+        traces.append(c.reshape(n)[3].copy())
+        a, b = b, c
+    ga, gb, tr = oracle_lib.wave_forward_damped(up, u0, kappa, gamma, 5, src=src, wavelet=wav, rec_z=3)
+    assert np.max(np.abs(gb.ravel() - b)) < 1e-11 * np.max(np.abs(b))
+    assert np.max(np.abs(ga.ravel() - a)) < 1e-11 * np.max(np.abs(a))
+    assert np.max(np.abs(tr - np.array(traces))) < 1e-11 * np.max(np.abs(traces))
+    za, zb, ztr = oracle_lib.wave_forward_damped(up, u0, kappa, np.zeros(n), 5, src=src, wavelet=wav, rec_z=3)
+    pa, pb, ptr = oracle_lib.wave_forward(up, u0, kappa, 5, src=src, wavelet=wav, rec_z=3)
+    assert np.array_equal(za, pa) and np.array_equal(zb, pb) and np.array_equal(ztr, ptr)
+
+
+def test_damped_energy_decreases_by_the_damping_work(oracle_lib):
+    """With a symmetric L the damped step loses exactly
+    E_{t-1/2} - E_{t+1/2} = 1/2 sum gamma/kappa (u_{t+1} - u_{t-1})^2 >= 0 of
+    the leapfrog energy E = ||u_{t+1} - u_t||^2_{1/kappa} - <u_{t+1}, L u_t>."""
+    rng = np.random.default_rng(83)
+    n = (16, 14, 15)
+    kappa = rng.uniform(0.05, 0.2, n)
+    gamma = oracle_lib.sponge_profile(n, 5, 0.6)
+    u0 = wl.gaussian_pulse((15, 14, 16), (3, 7, 8), 2.0).astype(np.float64)   # pulse inside the layer
+    up = u0 * 0.97
+
+    def energy(prev, cur):
+        return np.sum((cur - prev) ** 2 / kappa) - np.sum(cur * mr.lap_zero_numpy(prev))
+
+    a, b = up, u0
+    e_prev = energy(a, b)
+    e0 = e_prev
+    for _ in range(12):
+        na, nb, _ = oracle_lib.wave_forward_damped(a, b, kappa, gamma, 1)
+        e = energy(na, nb)
+        work = 0.5 * np.sum(gamma / kappa * (nb - a) ** 2)
+        assert work > 0
+        assert abs((e_prev - e) - work) <= 1e-12 * abs(e0)
+        a, b, e_prev = na, nb, e
+    assert e_prev < 0.999 * e0
+
+
+def test_damped_adjoint_brute_force_transpose_and_dot(oracle_lib):
+    """The damped adjoint equals the transpose of the dense damped state map,
+    satisfies the dot-product identity on a larger grid, and with a zero
+    damping field agrees with the plain adjoint."""
+    rng = np.random.default_rng(87)
+    n = (4, 5, 4)
+    size = 80
+    kappa, gamma = _damped_case(rng, n, W=2, s=1.3)
+    M = mr.operator_matrix(n, mr.laplacian_dense_fd8(), STAR, 4, ZERO)
+    g = gamma.ravel()
+    A, B = np.diag(1 / (1 + g / 2)), np.diag((1 - g / 2) / (1 + g / 2))
+    step = np.block([[np.zeros((size, size)), np.eye(size)], [-B, A @ (2 * np.eye(size) + np.diag(kappa.ravel()) @ M)]])
+    F = np.linalg.matrix_power(step, 4)
+    a, b = rng.standard_normal(n), rng.standard_normal(n)
+    ref = F.T @ np.concatenate([a.ravel(), b.ravel()])
+    ta, tb = oracle_lib.wave_adjoint_damped(a, b, kappa, gamma, 4)
+    got = np.concatenate([ta.ravel(), tb.ravel()])
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+
+    n = (11, 9, 10)
+    kappa, gamma = _damped_case(rng, n, W=3, s=0.8)
+    p, q, a, b = (rng.standard_normal(n) for _ in range(4))
+    fp, fq, _ = oracle_lib.wave_forward_damped(p, q, kappa, gamma, 7)
+    ta, tb = oracle_lib.wave_adjoint_damped(a, b, kappa, gamma, 7)
+    lhs = np.sum(fp * a) + np.sum(fq * b)
+    rhs = np.sum(p * ta) + np.sum(q * tb)
+    scale = np.sqrt(np.sum(fp ** 2) + np.sum(fq ** 2)) * np.sqrt(np.sum(a ** 2) + np.sum(b ** 2))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    za, zb = oracle_lib.wave_adjoint_damped(a, b, kappa, np.zeros(n), 7)
+    pa, pb = oracle_lib.wave_adjoint(a, b, kappa, 7)
+    assert np.max(np.abs(za - pa)) <= 1e-12 * np.max(np.abs(pa))
+    assert np.max(np.abs(zb - pb)) <= 1e-12 * np.max(np.abs(pb))
+
+
+def test_damped_gradient_full_jacobian_fd(oracle_lib):
+    """Every component of dJ/dkappa of the damped model against a central
+    difference of its loss (6^3, 5 steps); the loss is the trace misfit;
+    checkpointing leaves the gradient bitwise unchanged; a zero damping field
+    gives the plain gradient."""
+    rng = np.random.default_rng(89)
+    n = (6, 6, 6)
+    T = 5
+    kappa, zeros, src, wav, rec, target = _grad_problem(rng, n, T)
+    gamma = oracle_lib.sponge_profile(n, 2, 1.1)
+    g, J = oracle_lib.wave_gradient_damped(zeros, zeros, kappa, gamma, T, src, wav, rec, target)
+
+    def loss(k):
+        _, _, tr = oracle_lib.wave_forward_damped(zeros, zeros, k, gamma, T, src=src, wavelet=wav, rec_z=rec)
+        return 0.5 * np.sum((tr - target) ** 2)
+
+    assert abs(J - loss(kappa)) < 1e-14 * J
+    eps = 1e-6
+    fd = np.zeros(n)
+    for idx in np.ndindex(*n):
+        kp = kappa.copy(); kp[idx] += eps
+        km = kappa.copy(); km[idx] -= eps
+        fd[idx] = (loss(kp) - loss(km)) / (2 * eps)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * np.max(np.abs(fd)) + 1e-14
+    gk, Jk = oracle_lib.wave_gradient_damped(zeros, zeros, kappa, gamma, T, src, wav, rec, target, ckpt_every=2)
+    assert np.array_equal(gk, g) and Jk == J
+    gz, Jz = oracle_lib.wave_gradient_damped(zeros, zeros, kappa, np.zeros(n), T, src, wav, rec, target)
+    gp, Jp = oracle_lib.wave_gradient(zeros, zeros, kappa, T, src, wav, rec, target)
+    assert np.array_equal(gz, gp) and Jz == Jp
