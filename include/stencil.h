@@ -83,7 +83,9 @@ typedef enum {
     ST_VARIANT_WAVE3D_LDS = 4, /* 3D leapfrog forward with z-neighbours in an LDS ring */
     ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
     ST_VARIANT_ZM3D_MFMA = 6, /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
-    ST_VARIANT_VC3D = 7   /* variable-coefficient plane march (ST_VARCOEF plans, 2D and 3D) */
+    ST_VARIANT_VC3D = 7,  /* variable-coefficient plane march (ST_VARCOEF plans, 2D and 3D) */
+    ST_VARIANT_ZM3D_H2 = 8 /* 3D 27-point box, fp16 storage, even nx: two cells per lane,
+                              packed-half dot products with f32 accumulation */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */

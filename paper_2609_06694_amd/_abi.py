@@ -23,8 +23,9 @@ ST_LINEAR, ST_WAVE, ST_VARCOEF = 0, 1, 2
 ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D, ST_VARIANT_WAVE3D_LDS = 0, 1, 2, 3, 4
 ST_VARIANT_YM2D = 5
 ST_VARIANT_ZM3D_MFMA = 6
+ST_VARIANT_ZM3D_H2 = 8
 VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma",
-                 7: "vc3d"}
+                 7: "vc3d", 8: "zm3d_h2"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",

@@ -146,6 +146,7 @@ LaunchCfg variant_default(const st_problem& p, int variant) {
         case ST_VARIANT_YM2D: c.tile_x = 256; c.tile_y = 0; c.tsteps = default_cfg(k).tsteps; break;
         case ST_VARIANT_ZM3D: c.tile_y = 16; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_ZM3D_MFMA: c.tile_y = 64; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_ZM3D_H2: c.tile_y = 16; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D_LDS: c.tile_y = 32; c.zchunk = kAutoChunk; break;
         default: break;
@@ -253,7 +254,8 @@ static int device_cus() {
 // round's time), with chunks of at least 16 planes.
 int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident) {
     const int rows = c.tile_y >= 64 ? 64 : (c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8));
-    int64_t tiles = ((p.n[0] + kWave - 1) / kWave) * ((p.n[1] + rows - 1) / rows);
+    const int64_t tile_w = c.variant == ST_VARIANT_ZM3D_H2 ? 2 * kWave : kWave;   // H2: two cells per lane
+    int64_t tiles = ((p.n[0] + tile_w - 1) / tile_w) * ((p.n[1] + rows - 1) / rows);
     if (p.update == ST_LINEAR && p.ndim == 3 && c.tsteps == 2)   // two-step tiles: 62 x (tile_y - 2) outputs
         tiles = ((p.n[0] + 61) / 62) * ((p.n[1] + rows - 3) / (rows - 2));
     const int64_t target = (int64_t)device_cus() * (resident > 0 ? resident : resident_wgs(p, c));
@@ -280,6 +282,9 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         if (c.variant == ST_VARIANT_ZM3D_MFMA)
             return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 8 == 0 &&
                    c.tile_y == 64 && c.zchunk >= 0;
+        if (c.variant == ST_VARIANT_ZM3D_H2)
+            return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 2 == 0 &&
+                   (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1;
         if (c.variant == ST_VARIANT_ZM3D && c.tsteps == 2 &&
             (!zm3d_tb2_supported(p.radius, p.shape) || (c.tile_y != 16 && c.tile_y != 32)))
             return false;

@@ -108,6 +108,9 @@ hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
 hipError_t launch_zm3d_mfma(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                             void* out, hipStream_t stream);
 bool zm3d_mfma_supported(const Geom& g);
+hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
+                          hipStream_t stream);
+bool zm3d_h2_supported(const Geom& g);
 hipError_t launch_zm3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                            void* out, hipStream_t stream);
 bool zm3d_tb2_supported(int r, int shape);
@@ -123,6 +126,7 @@ inline hipError_t launch_linear3d(const Geom& g, const LaunchCfg& cfg, const Tap
                                   const void* in, void* out, int k, hipStream_t stream) {
     if (k == 2) return launch_zm3d_tb2(g, cfg, taps, in, out, stream);
     if (cfg.variant == 6) return launch_zm3d_mfma(g, cfg, taps, in, out, stream);
+    if (cfg.variant == 8) return launch_zm3d_h2(g, cfg, taps, in, out, stream);
     return launch_zm3d(g, cfg, taps, in, out, stream);
 }
 hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,

@@ -1,0 +1,271 @@
+// 3D box sweep (radius 1) with fp16 storage on packed-half dot products.
+//
+// Each lane owns two adjacent cells of a row (one 32-bit pair of binary16
+// values), so a wave moves 256 contiguous bytes per row and a plane enters
+// LDS as 32-bit pairs.  The contraction uses v_dot2 (two binary16 products
+// added to an f32 accumulator; the products are exact in f32) and the
+// mixed-precision fma (binary16 operand, f32 weight and sum): for the output
+// pair (x, x+1) and one (dz, dy) row of weights w_-1, w_0, w_1,
+//   out(x)   += dot2((u_x, u_x+1), (w_0, w_1))  + w_-1 * u_x-1
+//   out(x+1) += dot2((u_x, u_x+1), (w_-1, w_0)) + w_1  * u_x+2,
+// four instructions for six multiply-adds.  The packed weights are the
+// binary16 roundings w_hi of the f32 weights; their residuals w - w_hi (at
+// most 2^-12 |w|) enter through one extra multiply-add per cell,
+// (sum of residuals) * u(x): the part of the residual sum that acts on the
+// local mean, so the sweep's action on slowly varying data (and its sum
+// for a periodic grid) keeps the f32 weights' value.  What is left,
+// sum (w - w_hi)(u(x+d) - u(x)), is below 2^-12 of the local variation and
+// well under the binary16 rounding of every step.
+//
+// Layout and march follow the z-march of zmarch.h: a workgroup owns a
+// column of 128 x BY cells, stages every plane once (with a one-pair halo
+// in x and an R-row halo in y) and adds the plane's contributions to the
+// 2R+1 output planes it touches into a register queue of partial sums.
+// Requires an even nx (whole pairs in every row).
+#include "internal.h"
+#include "zmarch.h"
+
+namespace stk {
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// Weights of a radius-1 box in the form the kernel consumes, per (dz, dy)
+// row k = (dz+1)*3 + (dy+1): packed (w_0, w_1) and (w_-1, w_0) binary16
+// pairs, the binary16 values of w_-1 and w_1 widened to f32, and the sum of
+// all residuals w - w_hi.
+struct H2Taps {
+    uint32_t p01[9], pm0[9];
+    float wm[9], wp[9];
+    float res;
+};
+
+template <int RY, int NW>
+struct H2Geom {
+    static constexpr int NT = NW * kWave;
+    static constexpr int BXP = kWave;          // pairs per tile row
+    static constexpr int BY = NW * RY;
+    static constexpr int WP = BXP + 2;         // one halo pair on each side
+    static constexpr int H = BY + 2;           // one halo row above and below (radius 1)
+    static constexpr int NH = WP * H - BXP * BY;
+    static constexpr int HT = (NH + NT - 1) / NT;
+};
+
+__device__ __forceinline__ half2_t as_h2(uint32_t v) { return __builtin_bit_cast(half2_t, v); }
+
+template <int BC, int RY, int NW, int D>
+__global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __restrict__ in,
+                                                             uint32_t* __restrict__ out, int nxp, int ny,
+                                                             int nz, int zc, int tiles_x, int tiles_y,
+                                                             H2Taps tp) {
+    using G = H2Geom<RY, NW>;
+    __shared__ uint32_t tile[2][G::H * G::WP];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % tiles_x;
+    const int rest = b / tiles_x;
+    const int tyi = rest % tiles_y, zci = rest / tiles_y;
+    const int x0 = txi * G::BXP, y0 = tyi * G::BY;   // x0 in pairs
+    const int z0 = zci * zc, z1 = min(z0 + zc, nz);
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const int gx = x0 + tx;
+    const int zbeg = z0 - 1, zend = z1 + 1;
+
+    // In-plane addressing (pair offsets after the boundary rule) and x/y
+    // validity, the same for every plane.
+    uint32_t off[RY + G::HT];
+    uint32_t mxy = 0;
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        int px = gx, py = y0 + ty * RY + i;
+        const bool okx = fix_coord<BC>(px, nxp), oky = fix_coord<BC>(py, ny);
+        off[i] = (uint32_t)(py * nxp + px) * 4u;
+        mxy |= (uint32_t)(okx && oky) << i;
+    }
+#pragma unroll
+    for (int j = 0; j < G::HT; ++j) {
+        const int h = threadIdx.x + j * G::NT;
+        const bool hv = h < G::NH;
+        const int hh = hv ? h : 0;
+        int ly, lx;
+        if (hh < 2 * G::WP) {   // top row, then bottom row
+            ly = hh < G::WP ? 0 : G::H - 1;
+            lx = hh < G::WP ? hh : hh - G::WP;
+        } else {                // side pairs of the interior rows
+            const int q = hh - 2 * G::WP;
+            ly = 1 + (q >> 1);
+            lx = (q & 1) ? G::WP - 1 : 0;
+        }
+        int px = x0 - 1 + lx, py = y0 - 1 + ly;
+        const bool okx = fix_coord<BC>(px, nxp), oky = fix_coord<BC>(py, ny);
+        off[RY + j] = (uint32_t)(py * nxp + px) * 4u;
+        mxy |= (uint32_t)(hv && okx && oky) << (RY + j);
+    }
+
+    float ax[3][RY], ay[3][RY];   // partial sums of output planes zp-1, zp, zp+1 (cells x, x+1)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) ax[q][i] = ay[q][i] = 0.f;
+
+    uint32_t vin[D][RY + G::HT];
+    uint32_t vm[D];
+    const size_t plane_sz = (size_t)nxp * ny;
+    auto load = [&](int slot, int zp) {
+        int gz = min(zp, zend - 1);
+        const bool zin = fix_coord<BC>(gz, nz);
+        const char* base = reinterpret_cast<const char*>(in + (size_t)gz * plane_sz);
+#pragma unroll
+        for (int k = 0; k < RY + G::HT; ++k) vin[slot][k] = load_at<uint32_t>(base, off[k]);
+        vm[slot] = zin ? mxy : 0u;
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(d, zbeg + d);
+
+    for (int zb = zbeg; zb < zend; zb += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int zp = zb + d;
+            uint32_t* t = tile[zp & 1];
+            // Stage the plane (cells outside a zero frame are zero).
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                const uint32_t v = BC == kPeriodic || ((vm[d] >> i) & 1u) ? vin[d][i] : 0u;
+                t[(1 + ty * RY + i) * G::WP + 1 + tx] = v;
+            }
+#pragma unroll
+            for (int j = 0; j < G::HT; ++j) {
+                const int h = threadIdx.x + j * G::NT;
+                if (h < G::NH) {
+                    int ly, lx;
+                    if (h < 2 * G::WP) {
+                        ly = h < G::WP ? 0 : G::H - 1;
+                        lx = h < G::WP ? h : h - G::WP;
+                    } else {
+                        const int q = h - 2 * G::WP;
+                        ly = 1 + (q >> 1);
+                        lx = (q & 1) ? G::WP - 1 : 0;
+                    }
+                    const uint32_t v = BC == kPeriodic || ((vm[d] >> (RY + j)) & 1u) ? vin[d][RY + j] : 0u;
+                    t[ly * G::WP + lx] = v;
+                }
+            }
+            load(d, zp + D);
+            __syncthreads();
+
+            // Rows -1 .. RY of this thread's column of pairs: the pair to
+            // the left, its own pair and the pair to the right.
+            uint32_t pm[RY + 2], p0[RY + 2], pp[RY + 2];
+            const uint32_t* rb = t + (ty * RY) * G::WP + tx;
+#pragma unroll
+            for (int j = 0; j < RY + 2; ++j) {
+                pm[j] = rb[j * G::WP];
+                p0[j] = rb[j * G::WP + 1];
+                pp[j] = rb[j * G::WP + 2];
+            }
+            // Plane zp feeds output plane zp - dz with the weights of dz.
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int q = 1 - dz;
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int k = (dz + 1) * 3 + (dy + 1);
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        const int j = i + 1 + dy;
+                        ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.p01[k]), ax[q][i], false);
+                        ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
+                        ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.pm0[k]), ay[q][i], false);
+                        ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
+                    }
+                }
+            }
+            // The weight residuals, applied to the centre value.
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                ax[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).x, ax[1][i]);
+                ay[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+            }
+
+            // Output plane zp - 1 has received all three planes.
+            const int zo = zp - 1;
+            if (zo >= z0 && zo < z1 && gx < nxp) {
+                char* o = reinterpret_cast<char*>(out + (size_t)zo * plane_sz);
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    const int gy = y0 + ty * RY + i;
+                    if (gy < ny) {
+                        half2_t h;
+                        h.x = (_Float16)ax[0][i];   // round to nearest even
+                        h.y = (_Float16)ay[0][i];
+                        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, h),
+                                                    reinterpret_cast<uint32_t*>(o + (uint32_t)(gy * nxp + gx) * 4u));
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RY; ++i) {
+                ax[0][i] = ax[1][i];
+                ay[0][i] = ay[1][i];
+                ax[1][i] = ax[2][i];
+                ay[1][i] = ay[2][i];
+                ax[2][i] = 0.f;
+                ay[2][i] = 0.f;
+            }
+        }
+    }
+}
+
+bool zm3d_h2_supported(const Geom& g) {
+    return g.ndim == 3 && g.shape == kBox && g.r == 1 && g.dtype == 1 && g.nx % 2 == 0;
+}
+
+// Host-side weight preparation (dense (dz,dy,dx) box weights, f32).
+static H2Taps pack_h2(const Taps& t) {
+    H2Taps h;
+    double res = 0.0;
+    auto hi = [](float w) { return (_Float16)w; };
+    for (int k = 0; k < 9; ++k) {
+        const float wm = t.c[k * 3 + 0], w0 = t.c[k * 3 + 1], wp = t.c[k * 3 + 2];
+        const _Float16 hm = hi(wm), h0 = hi(w0), hp = hi(wp);
+        half2_t a, c;
+        a.x = h0; a.y = hp;
+        c.x = hm; c.y = h0;
+        h.p01[k] = __builtin_bit_cast(uint32_t, a);
+        h.pm0[k] = __builtin_bit_cast(uint32_t, c);
+        h.wm[k] = (float)hm;
+        h.wp[k] = (float)hp;
+        res += ((double)wm - (double)(float)hm) + ((double)w0 - (double)(float)h0) + ((double)wp - (double)(float)hp);
+    }
+    h.res = (float)res;
+    return h;
+}
+
+template <int BC, int RY, int NW>
+static hipError_t go(const Geom& g, int zc, const H2Taps& tp, const void* in, void* out, hipStream_t s) {
+    using G = H2Geom<RY, NW>;
+    const int nxp = g.nx / 2;
+    const int tiles_x = (nxp + G::BXP - 1) / G::BXP, tiles_y = (g.ny + G::BY - 1) / G::BY;
+    const int nchunks = (g.nz + zc - 1) / zc;
+    constexpr int D = 2;
+    hipLaunchKernelGGL((zm3d_h2_kernel<BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks), dim3(G::NT), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, nxp, g.ny, g.nz, zc, tiles_x, tiles_y, tp);
+    return hipGetLastError();
+}
+
+// tile_y: 8, 16 or 32 rows per workgroup (4 waves of 2, 4 or 8 rows).
+hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
+                          hipStream_t s) {
+    if (!zm3d_h2_supported(g)) return hipErrorInvalidValue;
+    const H2Taps tp = pack_h2(taps);
+    const int zc = cfg.zchunk > 0 ? cfg.zchunk : g.nz;
+    const int rows = cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8);
+    if (g.boundary == kPeriodic) {
+        if (rows == 8) return go<kPeriodic, 2, 4>(g, zc, tp, in, out, s);
+        if (rows == 16) return go<kPeriodic, 4, 4>(g, zc, tp, in, out, s);
+        return go<kPeriodic, 8, 4>(g, zc, tp, in, out, s);
+    }
+    if (rows == 8) return go<kZero, 2, 4>(g, zc, tp, in, out, s);
+    if (rows == 16) return go<kZero, 4, 4>(g, zc, tp, in, out, s);
+    return go<kZero, 8, 4>(g, zc, tp, in, out, s);
+}
+
+}  // namespace stk
