@@ -66,8 +66,8 @@ def parse():
     return ap.parse_args()
 
 
-PMC_TARGETS = ("wave", "box3d_f16", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16", "box2d_f32",
-               "batch64", "wavegrad")
+PMC_TARGETS = ("wave", "box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
+               "box2d_f32", "batch64", "wavegrad")
 
 
 def pmc_target(name, dev, st, wl, torch):
@@ -88,11 +88,14 @@ def pmc_target(name, dev, st, wl, torch):
         out = torch.empty_like(u0)
         model = st.WaveModel(case.n, radius=4, boundary="zero")
         model.forward(u0, prev, kap, 2, out=out, prev_inout=True)
-    elif name in ("box3d_f16", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16", "box2d_f32"):
+    elif name in ("box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
+                  "box2d_f32"):
         case = {"box3d_f16": lambda: wl.box3d(dtype=wl.F16), "box3d_f32": lambda: wl.box3d(dtype=wl.F32),
+                "box3d_f16_zm": lambda: wl.box3d(dtype=wl.F16),
                 "box3d_f16_mfma": lambda: wl.box3d(dtype=wl.F16), "star3d_f16": lambda: wl.star3d(dtype=wl.F16),
                 "box2d_f16": lambda: wl.box2d(dtype=wl.F16), "box2d_f32": lambda: wl.box2d(dtype=wl.F32)}[name]()
-        opts = {"variant": 6} if name.endswith("mfma") else {}
+        opts = {"variant": 6} if name.endswith("mfma") else \
+            ({"variant": 2, "tile_y": 16, "zchunk": 64} if name.endswith("_zm") else {})
         s = st.Stencil(case.n[:case.ndim], wl.SHAPE_NAMES[case.shape], case.radius, case.coeffs,
                        dtype=wl.DTYPE_TAGS[case.dtype], **opts)
         u = torch.from_numpy(case.u0).to(dev)
@@ -454,19 +457,39 @@ def bench_batch(dev, st, wl, torch):
     tune = bs.autotune(device=dev)
     tune_s = time.perf_counter() - t0
     desc = bs.describe()
-    k = max(1, desc["tsteps"])
+    own = desc["tsteps"] == -1   # the tuner chose each member's own map depth
     # Seven interleaved passes of the two variants, medians.
     ms, bms = timed_pair(run, lambda: bs.apply(ins, 32, outs=outs), REPS, 2, torch.cuda.synchronize)
     g = gcells(cells, 32, ms)
     bg = gcells(cells, 32, bms)
+    # The other grouping: each member at its own map depth (members finish
+    # after different launch counts; later launches re-divide the device),
+    # or the tuned uniform depth if the tuner chose the former.
+    alt = st.BatchedStencil([dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs)
+                             for c in cases], tsteps=3 if own else -1)
+    bms2, ams = timed_pair(lambda: bs.apply(ins, 32, outs=outs), lambda: alt.apply(ins, 32, outs=outs), REPS, 2,
+                           torch.cuda.synchronize)
+    # Map depths the members of `alt` read (the tuner updated the map in process).
+    depths = sorted(st.Stencil(c.n[:2], wl.SHAPE_NAMES[c.shape], c.radius, c.coeffs).describe()["tsteps"]
+                    for c in cases)
+    if own:
+        launches = "one grouped launch per time block for the grids that have blocks left, each grid at its own map depth"
+        bpc = None
+    else:
+        k = max(1, desc["tsteps"])
+        launches = f"one grouped launch per time block of {k} fused steps for all 64 grids ({-(-32 // k)} launches)"
+        bpc = 8 / k
     return {"workload": "batch64_2d_mixed_32steps_f32", "cells": cells, "ms": bms, "gcells_s": bg,
-            "launches": f"one grouped launch per time block of {k} fused steps for all 64 grids "
-                        f"({-(-32 // k)} launches), autotuned",
+            "launches": launches + ", autotuned",
             "autotune": dict(tune, seconds=round(tune_s, 1)), "dispatch": desc,
-            "bytes_per_cell_update": 8 / k, "hbm_frac": bg * 8 / k / HBM_PEAK_GBS,
+            "bytes_per_cell_update": bpc, "hbm_frac": None if bpc is None else bg * bpc / HBM_PEAK_GBS,
             "equiv_frac_one_step": bg * 8 / HBM_PEAK_GBS,
             "ms_separate_launches": ms, "gcells_s_separate": g,
-            "timing": f"median of {REPS} passes interleaved with the 64 separate plain launches"}
+            "other_grouping": {"kind": "uniform batch depth 3" if own else "each grid at its own map depth",
+                               "ms": ams, "gcells_s": gcells(cells, 32, ams), "ms_tuned_same_passes": bms2,
+                               "member_map_depths": {str(d): depths.count(d) for d in sorted(set(depths))}},
+            "timing": f"median of {REPS} passes interleaved with the 64 separate plain launches "
+                      f"(and, separately, with the other grouping)"}
 
 
 def bench_grad(dev, st, wl, torch):

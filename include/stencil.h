@@ -84,8 +84,10 @@ typedef enum {
     ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
     ST_VARIANT_ZM3D_MFMA = 6, /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
     ST_VARIANT_VC3D = 7,  /* variable-coefficient plane march (ST_VARCOEF plans, 2D and 3D) */
-    ST_VARIANT_ZM3D_H2 = 8 /* 3D 27-point box, fp16 storage, even nx: two cells per lane,
+    ST_VARIANT_ZM3D_H2 = 8, /* 3D 27-point box, fp16 storage, even nx: two cells per lane,
                               packed-half dot products with f32 accumulation */
+    ST_VARIANT_YM2D_H2 = 9 /* 2D box r = 1..2, fp16 storage, even nx: the row march on
+                              packed-half dot products */
 } st_variant;
 
 typedef struct st_plan st_plan;   /* opaque; immutable after creation */
@@ -109,7 +111,9 @@ typedef struct {
 typedef struct {
     int32_t variant;       /* st_variant */
     int32_t tile_x;        /* TB2D: output tile width (8..512);
-                              YM2D: window width = threads per workgroup (256 or 512) */
+                              YM2D: window width = threads per workgroup (256 or 512);
+                              WAVE3D_LDS: planes staged per barrier (1, or 2 = the two
+                              planes of a march step under one barrier) */
     int32_t tile_y;        /* TB2D: output tile height; YM2D: rows per chunk (0 = automatic);
                               ZM3D/WAVE3D: rows per workgroup */
     int32_t tsteps;        /* TB2D/YM2D: time steps fused per launch (1..16);
@@ -165,6 +169,14 @@ size_t stencil_workspace_bytes(const st_plan *plan, int32_t steps, int32_t mode)
  * may be NULL).  Host only. */
 st_status stencil_plan_describe(const st_plan *plan, int32_t *variant, int32_t *tile_x,
                                 int32_t *tile_y, int32_t *tsteps, int32_t *zchunk);
+
+/* The configuration of a wave plan's reverse step (the adjoint and gradient
+ * launches of stencil_apply_adjoint and stencil_wave_gradient), which has a
+ * dispatch-map cell of its own (Section 4.2's operator map, one more update
+ * kind).  Any pointer may be NULL.  ST_EINVAL for a NULL, batched or non-wave
+ * plan.  Host only. */
+st_status stencil_plan_describe_reverse(const st_plan *plan, int32_t *variant, int32_t *tile_x,
+                                        int32_t *tile_y, int32_t *tsteps, int32_t *zchunk);
 
 /* The coefficients a plan applies (Section 2.1: the case's weights c_d).
  * `dense` (HOST, may be NULL) receives min(count, (2r+1)^ndim) floats in the
@@ -254,29 +266,48 @@ st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wa
 /* Batched plan over `count` independent 2D ST_LINEAR problems of one storage
  * type and boundary rule (shapes, radii, extents and coefficients may
  * differ).  opts->tsteps (0 = 3) is the fused depth of the batch, the same
- * for every member (clamped per member to what its radius allows); the other
- * option fields apply to each member's own plan.  *out owns the plan. */
+ * for every member (clamped per member to what its radius allows); -1 asks
+ * for each member's own depth (the fused depth of its own map entry, within
+ * the same limits); below -1 is ST_EINVAL.  The other option fields apply to
+ * each member's own plan.  *out owns the plan. */
 st_status stencil_plan_batched(const st_problem *problems, int32_t count,
                                const st_plan_opts *opts, st_plan **out);
 
 /* All members advanced `steps` steps, one launch per time block for the
  * whole batch: each launch runs one block of k fused steps (the batch
- * depth) of every member, ceil(steps / k) launches in all instead of one
- * series per member.  Workgroups never wait on each other.  u_in / u_out are
+ * depth, or the member's own) of every member that has blocks left,
+ * max ceil(steps / k) launches in all instead of one series per member; a
+ * launch divides the device among the members it carries (launch fusion,
+ * one of the application-level wins of Section 5).  Workgroups never wait
+ * on each other.  u_in / u_out are
  * HOST arrays of `count` device pointers (u_in[i] == u_out[i] allowed).
  * Workspace from stencil_workspace_bytes(batched_plan, steps, 0): a partner
- * grid per member plus the member table.  Asynchronous on `stream`; ST_EHIP
+ * grid per member plus the member tables (one per distinct set of running
+ * members).  Asynchronous on `stream`; ST_EHIP
  * if a launch fails. */
 st_status stencil_apply_batched(const st_plan *plan, const void *const *u_in,
                                 void *const *u_out, int32_t steps, void *workspace,
                                 size_t ws_bytes, void *stream);
+
+/* The launch schedule stencil_apply_batched would run for `steps` (>= 1)
+ * steps on a device of `cus` compute units (0: the current device's):
+ * *launches grouped launches, *tables member tables (a new one wherever the
+ * set of running members changes), *workgroups in all.  Builds and checks
+ * the same tables as the apply (every running member's workgroup range
+ * inside its launch, the ranges contiguous), with stand-in buffer
+ * addresses; ST_EINVAL if a check fails.  Any output pointer may be NULL.
+ * Host only (no device work unless cus is 0). */
+st_status stencil_plan_describe_batched(const st_plan *plan, int32_t steps, int32_t cus,
+                                        int32_t *launches, int32_t *tables, int64_t *workgroups);
 
 /* Autotune: for every distinct case of the plan (one, or each batch
  * member), time the legal candidates (tile shape, fused time steps, rows per
  * workgroup, plane chunk), reject any candidate whose output differs from
  * the plain single-step kernel on a probe grid, keep the fastest, write it
  * into the plan and into the dispatch map, and append it to the tuning cache
- * file when STENCIL_TUNE_CACHE is set.  `scratch` (device) must hold
+ * file when STENCIL_TUNE_CACHE is set.  A wave plan whose forward step runs
+ * the LDS-ring kernel then tunes its reverse step the same way (the
+ * pointwise gradient step: lambda_t and the dkappa update, both checked).  `scratch` (device) must hold
  * stencil_workspace_bytes(plan, 0, 2) bytes.  Synchronises `stream`.
  * Setting STENCIL_TUNE_FAULT=1 deliberately perturbs the coefficients of part
  * of the candidates (fused-step or 32-row ones) so tests can check that the

@@ -24,12 +24,14 @@ ST_VARIANT_AUTO, ST_VARIANT_TB2D, ST_VARIANT_ZM3D, ST_VARIANT_WAVE3D, ST_VARIANT
 ST_VARIANT_YM2D = 5
 ST_VARIANT_ZM3D_MFMA = 6
 ST_VARIANT_ZM3D_H2 = 8
+ST_VARIANT_YM2D_H2 = 9
 VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma",
-                 7: "vc3d", 8: "zm3d_h2"}
+                 7: "vc3d", 8: "zm3d_h2", 9: "ym2d_h2"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",
-            "stencil_plan_describe", "stencil_plan_coefficients", "stencil_apply", "stencil_apply_adjoint",
+            "stencil_plan_describe", "stencil_plan_describe_reverse", "stencil_plan_describe_batched",
+            "stencil_plan_coefficients", "stencil_apply", "stencil_apply_adjoint",
             "stencil_apply_varcoef", "stencil_apply_varcoef_adjoint",
             "stencil_wave_gradient", "stencil_plan_batched", "stencil_apply_batched",
             "stencil_autotune", "stencil_autotune_stats", "stencil_last_error", "stencil_version",
@@ -82,6 +84,11 @@ def lib():
     ip = ctypes.POINTER(i32)
     L.stencil_plan_describe.argtypes = [P, ip, ip, ip, ip, ip]
     L.stencil_plan_describe.restype = ctypes.c_int
+    L.stencil_plan_describe_reverse.argtypes = [P, ip, ip, ip, ip, ip]
+    L.stencil_plan_describe_reverse.restype = ctypes.c_int
+    L.stencil_plan_describe_batched.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ip, ip,
+                                                ctypes.POINTER(ctypes.c_int64)]
+    L.stencil_plan_describe_batched.restype = ctypes.c_int
     L.stencil_plan_coefficients.argtypes = [P, ctypes.POINTER(ctypes.c_float), i32,
                                             ctypes.POINTER(ctypes.c_double)]
     L.stencil_plan_coefficients.restype = ctypes.c_int

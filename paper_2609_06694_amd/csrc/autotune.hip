@@ -123,14 +123,17 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
         // Chunks of 8 planes only on small grids (up to 2^22 cells), where
         // they give enough workgroups to fill the chip.
         const bool small = (double)p.n[0] * p.n[1] * p.n[2] <= (double)(1 << 22);
+        // Wave: one or two planes staged per barrier (tile_x 0 or 2).
         for (int var : vars)
-            for (int ty : {8, 16, 32})
-                for (int zc : {8, 16, 32, 64, 128, 256, 0}) {
-                    if (zc != 0 && zc >= p.n[2]) continue;
-                    if (zc == 8 && !small) continue;
-                    LaunchCfg c{var, 0, ty, 1, zc};
-                    if (cfg_legal(p, c)) out.push_back(c);
-                }
+            for (int pb : {0, 2})
+                for (int ty : {8, 16, 32})
+                    for (int zc : {8, 16, 32, 64, 128, 256, 0}) {
+                        if (zc != 0 && zc >= p.n[2]) continue;
+                        if (zc == 8 && !small) continue;
+                        if (pb != 0 && p.update != ST_WAVE) continue;
+                        LaunchCfg c{var, pb, ty, 1, zc};
+                        if (cfg_legal(p, c)) out.push_back(c);
+                    }
         // Two fused steps (radius 1: 62 x (tile_y - 2) output tiles).
         for (int ty : {16, 32})
             for (int zc : {8, 16, 32, 64, 128, 0}) {
@@ -171,6 +174,14 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
             LaunchCfg c{ST_VARIANT_TB2D, bx, by, k, h / 4};
             if (cfg_legal(p, c)) out.push_back(c);
         }
+    // Packed-half row march (fp16 boxes, even nx).
+    for (int nt : {256, 512})
+        for (int k : {1, 2, 3, 4, 8})
+            for (int ych : {0, 32, 64, 128}) {
+                if (2 * nt > 2 * p.n[0] + 512 || (ych != 0 && ych >= p.n[1])) continue;
+                LaunchCfg c{ST_VARIANT_YM2D_H2, nt, ych, k, 0};
+                if (cfg_legal(p, c)) out.push_back(c);
+            }
     // Row march: window width, fused depth, rows per chunk (0 = automatic).
     for (int nt : {256, 512})
         for (int k : {1, 2, 4, 8, 10, 16})
@@ -356,15 +367,183 @@ st_status tune_one(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, Tune
     return ST_OK;
 }
 
+// Reverse-step candidates of a wave case: the LDS-ring kernel (the one the
+// pointwise gradient step runs) by tile height and plane chunk.
+std::vector<LaunchCfg> reverse_candidates(const st_problem& p) {
+    std::vector<LaunchCfg> out;
+    for (int ty : {32, 16, 8})
+        for (int zc : {0, 16, 32, 64, 128, 256}) {
+            if (zc != 0 && zc >= p.n[2]) continue;
+            LaunchCfg c{ST_VARIANT_WAVE3D_LDS, 0, ty, 1, zc};
+            if (adj_cfg_legal(p, c)) out.push_back(c);
+        }
+    return out;
+}
+
+size_t plane_bytes_of(const st_problem& p) { return ((size_t)p.n[0] * p.n[1] * 4 + 255) / 256 * 256; }
+
+// Bytes tune_reverse needs beyond tune_one's scratch: L(u_t), the reference
+// gradient, and two planes (the target and the recorded trace).
+size_t reverse_extra_bytes(const st_problem& p) {
+    const size_t gb = (grid_bytes_of(p) + 255) / 256 * 256;
+    return 2 * gb + 2 * plane_bytes_of(p);
+}
+
+// Tunes the reverse step of a wave plan whose forward runs the LDS-ring
+// kernel: the pointwise gradient step (lambda_t and the dkappa update from
+// L(u_t), with the receiver-plane residual).  Every candidate's lambda_t and
+// dkappa are checked against the 32-row, unchunked launch on random fields;
+// the fastest passing candidate (median of five) goes into the plan and the
+// map cell of the reverse key.
+st_status tune_reverse(st_plan* pl, char* scratch, size_t bytes, hipStream_t s, TuneStats& st) {
+    const st_problem& p = pl->prob;
+    if (p.update != ST_WAVE || pl->cfg.variant != ST_VARIANT_WAVE3D_LDS) return ST_OK;
+    const size_t cells = (size_t)p.n[0] * p.n[1] * p.n[2];
+    const size_t plane = (size_t)p.n[0] * p.n[1];
+    const size_t gb = (cells * 4 + 255) / 256 * 256;
+    const size_t need = 5 * gb + 64 + reverse_extra_bytes(p);
+    if (bytes < need) {
+        set_error("autotune scratch of %zu bytes needed", need);
+        return ST_EWORKSPACE;
+    }
+    // tune_one's layout (in, out, tmp, ref, kappa, counters), then the rest.
+    float* lam1 = (float*)scratch;              // lambda_{t+1}
+    float* grad = (float*)(scratch + gb);       // dkappa accumulator
+    float* lam2 = (float*)(scratch + 2 * gb);   // lambda_{t+2}, overwritten by lambda_t
+    float* ref = (float*)(scratch + 3 * gb);
+    const float* kappa = (const float*)(scratch + 4 * gb);
+    unsigned* cnt = (unsigned*)(scratch + 5 * gb);
+    char* extra = scratch + 5 * gb + 64;
+    float* lap = (float*)extra;
+    float* ref_grad = (float*)(extra + gb);
+    float* target = (float*)(extra + 2 * gb);
+    float* trace = (float*)(extra + 2 * gb + plane_bytes_of(p));
+#define R_TRY(e)                                                                         \
+    do {                                                                                 \
+        hipError_t e_ = (e);                                                             \
+        if (e_ != hipSuccess) {                                                          \
+            set_error("autotune: %s: %s", #e, hipGetErrorString(e_));                    \
+            return ST_EHIP;                                                              \
+        }                                                                                \
+    } while (0)
+    st_problem f32 = p;
+    f32.dtype = ST_F32;
+    R_TRY(fill(lam1, f32, cells, 21u, -1.f, 1.f, s));
+    R_TRY(fill(lap, f32, cells, 22u, -1.f, 1.f, s));
+    R_TRY(fill(target, f32, plane, 23u, -1.f, 1.f, s));
+    R_TRY(fill(trace, f32, plane, 24u, -1.f, 1.f, s));
+    const Geom g = plan_geom(pl);
+    // A planted fault (16-row candidates) shifts the centre weight of L^T.
+    Taps bad = pl->taps_t;
+    bad.c[0] += 0.25f;
+    bad.sum += 0.25f;
+    auto run = [&](const LaunchCfg& c) -> hipError_t {
+        WaveLaunch w;
+        memset(&w, 0, sizeof w);
+        w.src_x = -1;
+        w.prev_sign = 1.f;
+        w.prev_damped = true;
+        w.prev = lam2;
+        w.cur = lam1;
+        w.next = lam2;
+        w.kappa = kappa;
+        w.grad = grad;
+        w.lap = lap;
+        w.rec_z = (int)(p.n[2] / 2);
+        w.target_t = target;
+        w.trace_res = trace;
+        return launch_wave_adjoint(g, c, faulty(p, c) ? bad : pl->taps_t, pl->taps, kWaveGradPt, w, s);
+    };
+    auto reset = [&]() -> hipError_t {
+        hipError_t e = fill(lam2, f32, cells, 25u, -1.f, 1.f, s);
+        return e != hipSuccess ? e : fill(grad, f32, cells, 26u, -1.f, 1.f, s);
+    };
+    const LaunchCfg plain{ST_VARIANT_WAVE3D_LDS, 0, 32, 1, 0};
+    R_TRY(reset());
+    R_TRY(run(plain));
+    R_TRY(hipMemcpyAsync(ref, lam2, cells * 4, hipMemcpyDeviceToDevice, s));
+    R_TRY(hipMemcpyAsync(ref_grad, grad, cells * 4, hipMemcpyDeviceToDevice, s));
+
+    hipEvent_t e0, e1;
+    R_TRY(hipEventCreate(&e0));
+    R_TRY(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    LaunchCfg best = pl->adj_cfg;
+    bool any = false;
+    for (const LaunchCfg& c : reverse_candidates(p)) {
+        ++st.tried;
+        R_TRY(reset());
+        R_TRY(run(c));
+        unsigned h[4] = {0u, 0u, 0u, 0u};
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, cnt, 4);
+        launch_max_diff(ST_F32, lam2, ref, cells, cnt, s);
+        launch_max_diff(ST_F32, grad, ref_grad, cells, cnt + 2, s);
+        R_TRY(hipGetLastError());
+        R_TRY(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+        R_TRY(hipStreamSynchronize(s));
+        float v[4];
+        memcpy(v, h, sizeof v);
+        const float tol = parity_tol(ST_F32);
+        if (!(v[0] <= tol * std::max(v[1], 1e-30f)) || !(v[2] <= tol * std::max(v[3], 1e-30f))) {
+            ++st.rejected;
+            continue;
+        }
+        // Two launches per sample: lambda alternates between two states, so
+        // the repeated in-place step stays bounded.
+        std::vector<float> ms;
+        for (int rep = 0; rep < 6; ++rep) {
+            R_TRY(hipEventRecord(e0, s));
+            R_TRY(run(c));
+            R_TRY(run(c));
+            R_TRY(hipEventRecord(e1, s));
+            R_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            R_TRY(hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+            any = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+#undef R_TRY
+    if (!any) {
+        set_error("autotune: no reverse-step candidate passed parity");
+        return ST_ETUNE;
+    }
+    pl->adj_cfg = best;
+    dispatch_store(reverse_key(p), best, true);
+    return ST_OK;
+}
+
 // Steps of the grouped-launch probe: a multiple of every candidate depth
 // but 8, so most candidates run whole blocks.
 constexpr int kBatchProbeSteps = 12;
 
+// Batch depths the grouped launch is timed at (kMemberDepths: each member
+// its own map depth).
+constexpr int kBatchDepths[] = {1, 2, 3, 4, 6, 8, kMemberDepths};
+
+// Workspace of a grouped launch of the probe at any candidate depth: the
+// partner grids plus the largest member-table set.
+size_t batch_probe_ws(const st_plan* plan) {
+    size_t grids = 0, meta = 0;
+    for (const st_plan* m : plan->members) grids += (grid_bytes_of(m->prob) + 255) / 256 * 256;
+    for (int k : kBatchDepths) meta = std::max(meta, batched_meta_bytes(plan, kBatchProbeSteps, k));
+    return grids + meta;
+}
+
 
 // Fused depth of the grouped batched launch, measured on the member grids:
-// each candidate depth runs the whole batch, every member's output is
-// checked against depth 1, and the fastest passing depth (median of five)
-// becomes the plan's batch depth.
+// each candidate depth (one depth for all members, or each member's own map
+// depth) runs the whole batch, every member's output is checked against
+// depth 1, and the fastest passing candidate (median of five) becomes the
+// plan's batch depth.
 st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream_t s, TuneStats& st) {
     const size_t need = batch_tune_bytes(plan);
     if (bytes < need) {
@@ -393,7 +572,7 @@ st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream
         p += 3 * gb;
         B_TRY(fill(in[g], pr, cells[g], 11u + g, 0.f, 1.f, s));
     }
-    const size_t wsb = stencil_workspace_bytes(plan, kBatchProbeSteps, 0);
+    const size_t wsb = batch_probe_ws(plan);
     void* ws = p;
     unsigned* cnt = (unsigned*)(p + (wsb + 255) / 256 * 256);
     const int keep = plan->cfg.tsteps;
@@ -408,7 +587,7 @@ st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream
     B_TRY(hipEventCreate(&e1));
     float best_ms = INFINITY;
     int best = keep;
-    for (int k : {1, 2, 3, 4, 6, 8}) {
+    for (int k : kBatchDepths) {
         ++st.tried;
         plan->cfg.tsteps = k;
         r = stencil_apply_batched(plan, in.data(), out.data(), kBatchProbeSteps, ws, wsb, s);
@@ -459,10 +638,12 @@ st_status tune_batch_depth(st_plan* plan, char* scratch, size_t bytes, hipStream
 
 namespace stk {
 
+size_t reverse_tune_bytes(const st_problem& p) { return reverse_extra_bytes(p); }
+
 size_t batch_tune_bytes(const st_plan* plan) {
     size_t g = 0;
     for (const st_plan* m : plan->members) g += 3 * ((grid_bytes_of(m->prob) + 255) / 256 * 256);
-    return g + stencil_workspace_bytes(plan, kBatchProbeSteps, 0) + 256;
+    return g + batch_probe_ws(plan) + 256;
 }
 
 }  // namespace stk
@@ -483,6 +664,7 @@ st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, v
     TuneStats st;
     if (!plan->batched) {
         st_status r = tune_one(plan, (char*)scratch, scratch_bytes, s, st);
+        if (r == ST_OK) r = tune_reverse(plan, (char*)scratch, scratch_bytes, s, st);
         plan->tune_tried = st.tried;
         plan->tune_rejected = st.rejected;
         return r;

@@ -11,12 +11,15 @@
 // geometry, buffers and coefficients), written from pinned host staging.
 //
 // Members keep their own stencil (shape, radius, coefficients) and extent;
-// they share storage type, boundary rule and fused depth k (one depth for
-// all, so that every launch carries every member: with per-member depths
-// the deep members finish early and the last launches leave the device
-// mostly idle).  Blocks ping-pong
+// they share storage type and boundary rule.  The fused depth k is one batch
+// depth for all members (every launch carries every member), or, on request,
+// each member's own depth from its map entry: then the deep members finish
+// in fewer launches, and every launch re-divides the device among the
+// members still running (a table per distinct set of running members), so
+// the last launches are not left mostly idle.  Blocks ping-pong
 // between the caller's output and a workspace partner so that the last
 // block of every member lands in its output.
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -124,10 +127,12 @@ size_t member_grid_bytes(const st_plan* m) {
     return (size_t)m->prob.n[0] * m->prob.n[1] * storage_bytes(m->prob.dtype);
 }
 
-// Fused depth of member m in a grouped launch: the batch depth, within the
-// limits of a 256-column window (at least 64 output columns) and of LDS.
+// Fused depth of member m in a grouped launch: the batch depth (kbatch =
+// kMemberDepths: the member's own map depth), within the limits of a
+// 256-column window (at least 64 output columns) and of LDS.
 int member_depth(const st_plan* m, int kbatch) {
     const int r = m->prob.radius;
+    if (kbatch == kMemberDepths) kbatch = m->cfg.tsteps;
     int k = std::min(16, std::max(1, kbatch));
     while (k > 1 && (kGroupThreads - 2 * k * r < kWave ||
                      ring_bytes(m->prob.dtype) * k * ym2d_ring_rows(4, r) * (kGroupThreads + 2 * r) > ym2d_max_lds_bytes()))
@@ -141,15 +146,15 @@ struct Layout {
     size_t lds = 0;
 };
 
-// Geometry of one grouped launch: chunks sized so that every member gets
-// workgroups in proportion to its cells, about eight per CU in total (two
-// and four per CU measured 40 % and 5 % slower on the 64-grid workload).
-Layout layout(const st_plan* plan, int steps, int cus) {
+// Geometry of the grouped launches from launch `round` on: chunks sized so
+// that every member still running gets workgroups in proportion to its
+// cells, about eight per CU in total (two and four per CU measured 40 % and
+// 5 % slower on the 64-grid workload); finished members get none.  The row
+// count per iteration and the LDS reservation cover every member, so all
+// launches share one kernel.
+Layout layout(const st_plan* plan, int steps, int cus, int round = 0) {
     Layout lay;
     const int nm = (int)plan->members.size();
-    double total = 0;
-    for (const st_plan* m : plan->members) total += (double)m->prob.n[0] * m->prob.n[1];
-    const double target = 8.0 * cus;
     int need8 = 0;
     for (int g = 0; g < nm; ++g) {
         const st_plan* m = plan->members[g];
@@ -163,16 +168,15 @@ Layout layout(const st_plan* plan, int steps, int cus) {
         b.L = steps > 0 ? (steps + b.k - 1) / b.k : 0;
         b.ow = kGroupThreads - 2 * b.k * b.r;
         b.strips = (b.nx + b.ow - 1) / b.ow;
-        const double share = target * ((double)b.nx * b.ny / std::max(1.0, total));
-        const int chunks = std::max(1, (int)(share / b.strips + 0.5));
-        int ych = (b.ny + chunks - 1) / chunks;
-        ych = std::max(ych, std::max(16, 4 * b.k * b.r));
-        b.ych = std::min(ych, b.ny);
         b.taps = m->taps;
         lay.rounds = std::max(lay.rounds, b.L);
         if (ring_bytes(m->prob.dtype) * b.k * ym2d_ring_rows(8, b.r) * (kGroupThreads + 2 * b.r) > 64 * 1024) need8 = 1;
         lay.members.push_back(b);
     }
+    double total = 0;
+    for (const GMember& b : lay.members)
+        if (b.L > round) total += (double)b.nx * b.ny;
+    const double target = 8.0 * cus;
     // Eight input rows per iteration unless a member's rings would outgrow
     // 64 KiB; the launch reserves the largest member's rings.
     lay.ry = need8 ? 4 : 8;
@@ -180,21 +184,99 @@ Layout layout(const st_plan* plan, int steps, int cus) {
     // the workgroup ranges follow.
     lay.grid = 0;
     for (GMember& b : lay.members) {
-        b.ych = ym2d_fill_chunk(b.ych, b.k * b.r, lay.ry, b.ny);
+        const double share = target * ((double)b.nx * b.ny / std::max(1.0, total));
+        const int chunks = std::max(1, (int)(share / b.strips + 0.5));
+        int ych = (b.ny + chunks - 1) / chunks;
+        ych = std::max(ych, std::max(16, 4 * b.k * b.r));
+        b.ych = ym2d_fill_chunk(std::min(ych, b.ny), b.k * b.r, lay.ry, b.ny);
         b.first = lay.grid;
-        lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
+        if (b.L > round) lay.grid += b.strips * ((b.ny + b.ych - 1) / b.ych);
         lay.lds = std::max(lay.lds, (size_t)ring_bytes(plan->prob.dtype) * b.k * ym2d_ring_rows(lay.ry, b.r) *
                                         (kGroupThreads + 2 * b.r));
     }
     return lay;
 }
 
+// Launches at which the set of running members changes (0 first): each
+// starts a new member table.
+std::vector<int> table_starts(const st_plan* plan, int steps, int kbatch) {
+    std::vector<int> ends;   // distinct block counts
+    for (const st_plan* m : plan->members) {
+        const int k = member_depth(m, kbatch);
+        ends.push_back(steps > 0 ? (steps + k - 1) / k : 0);
+    }
+    std::sort(ends.begin(), ends.end());
+    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    std::vector<int> starts{0};
+    for (int e : ends)
+        if (e > 0 && e < ends.back()) starts.push_back(e);
+    return starts;
+}
+
+// The whole launch schedule of a batched apply, built on the host before
+// any device work: one member table per distinct set of running members,
+// every table carrying the members' buffers.
+struct Schedule {
+    std::vector<int> starts;    // first launch of each table
+    std::vector<Layout> tabs;   // tabs[i].members: geometry and buffers of table i
+    std::vector<int> copy_in;   // members whose input is first copied to their partner (ws)
+    int rounds = 0;
+};
+
+// Builds the schedule for buffers u_in / u_out (per member) and the
+// workspace base ws (partner grids first), then checks it: every buffer
+// set, and in every table the running members' workgroup ranges tile
+// [0, grid) in order with at least one workgroup each.  Returns NULL, or
+// what is wrong.
+const char* build_schedule(const st_plan* plan, int steps, int cus, const void* const* u_in,
+                           void* const* u_out, char* ws, Schedule& sc) {
+    const int nm = (int)plan->members.size();
+    sc.starts = table_starts(plan, steps, plan->cfg.tsteps);
+    sc.tabs.clear();
+    sc.copy_in.clear();
+    for (int start : sc.starts) sc.tabs.push_back(layout(plan, steps, cus, start));
+    sc.rounds = sc.tabs[0].rounds;
+    size_t off = 0;
+    for (int g = 0; g < nm; ++g) {
+        const GMember& b0 = sc.tabs[0].members[g];
+        void* partner = ws + off;
+        off += align256(member_grid_bytes(plan->members[g]));
+        // In place with an odd block count: block 1 would write the grid it
+        // reads, so it reads a copy in the partner instead (block 2 writes
+        // the partner only after block 1's launch has completed).
+        const bool copy = u_in[g] == u_out[g] && (b0.L % 2) == 1;
+        if (copy) sc.copy_in.push_back(g);
+        for (Layout& t : sc.tabs) {
+            GMember& b = t.members[g];
+            b.in = copy ? partner : u_in[g];
+            b.out = u_out[g];
+            b.ws = partner;
+        }
+    }
+    for (size_t i = 0; i < sc.tabs.size(); ++i) {
+        const Layout& t = sc.tabs[i];
+        int next = 0;
+        for (int g = 0; g < nm; ++g) {
+            const GMember& b = t.members[g];
+            if (!b.in || !b.out || !b.ws) return "a member table entry has no buffer";
+            if (b.first != next) return "member workgroup ranges are not contiguous";
+            if (b.L <= sc.starts[i]) continue;   // finished: no workgroups
+            if (b.k < 1 || b.ow < kWave || b.strips < 1 || b.ych < 1) return "member geometry out of range";
+            next += b.strips * ((b.ny + b.ych - 1) / b.ych);
+        }
+        if (next != t.grid || t.grid < 1) return "launch size does not match the member ranges";
+        if (t.ry != sc.tabs[0].ry || t.lds != sc.tabs[0].lds) return "tables disagree on the launch shape";
+    }
+    return nullptr;
+}
+
 }  // namespace
 
 namespace stk {
 
-size_t batched_meta_bytes(const st_plan* plan, int /*steps*/) {
-    return align256(sizeof(GMember) * plan->members.size());
+size_t batched_meta_bytes(const st_plan* plan, int steps, int kbatch) {
+    if (kbatch == 0) kbatch = plan->cfg.tsteps;
+    return align256(sizeof(GMember) * plan->members.size() * table_starts(plan, steps, kbatch).size());
 }
 
 }  // namespace stk
@@ -228,7 +310,12 @@ st_status stencil_plan_batched(const st_problem* problems, int32_t count, const 
     pl->cfg.tile_x = kGroupThreads;
     // Three fused steps measured fastest for the 64-grid workload (k = 1, 2,
     // 4: 47 %, 5 %, 32 % slower; deeper rings of wide stencils cut occupancy).
-    pl->cfg.tsteps = (opts && opts->tsteps > 0) ? opts->tsteps : 3;
+    // opts->tsteps = -1 (kMemberDepths): each member's own map depth.
+    if (opts && opts->tsteps < kMemberDepths) {
+        delete pl;
+        B_FAIL(ST_EINVAL, "batched tsteps must be >= -1");
+    }
+    pl->cfg.tsteps = (opts && (opts->tsteps > 0 || opts->tsteps == kMemberDepths)) ? opts->tsteps : 3;
     // Member plans carry the stencils; the batch depth is not theirs to check.
     st_plan_opts mopts;
     if (opts) {
@@ -281,32 +368,23 @@ st_status stencil_apply_batched(const st_plan* plan, const void* const* u_in, vo
     int dev = 0, cus = 0;
     B_HIP(hipGetDevice(&dev));
     B_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    Layout lay = layout(plan, steps, std::max(1, cus));
-    if (lay.lds > (size_t)ym2d_max_lds_bytes()) B_FAIL(ST_EUNSUPPORTED, "member rings exceed LDS");
-
+    Schedule sc;
     char* ws = (char*)workspace;
-    size_t off = 0;
-    for (int g = 0; g < nm; ++g) {
-        const st_plan* m = plan->members[g];
-        GMember& b = lay.members[g];
-        void* partner = ws + off;
-        off += align256(member_grid_bytes(m));
-        b.in = u_in[g];
-        b.out = u_out[g];
-        b.ws = partner;
-        // In place with an odd block count: block 1 would write the grid it
-        // reads, so it reads a copy in the partner instead (block 2 writes
-        // the partner only after block 1's launch has completed).
-        if (u_in[g] == u_out[g] && (b.L % 2) == 1) {
-            B_HIP(hipMemcpyAsync(partner, u_in[g], member_grid_bytes(m), hipMemcpyDeviceToDevice, s));
-            b.in = partner;
-        }
-    }
-    GMember* d_members = (GMember*)(ws + off);
+    const char* bad = build_schedule(plan, steps, std::max(1, cus), u_in, u_out, ws, sc);
+    if (bad) B_FAIL(ST_EINVAL, "batched schedule: %s", bad);
+    const Layout& lay = sc.tabs[0];
+    if (lay.lds > (size_t)ym2d_max_lds_bytes()) B_FAIL(ST_EUNSUPPORTED, "member rings exceed LDS");
+    size_t grids = 0;
+    for (int g = 0; g < nm; ++g) grids += align256(member_grid_bytes(plan->members[g]));
+    GMember* d_members = (GMember*)(ws + grids);
+    for (int g : sc.copy_in)
+        B_HIP(hipMemcpyAsync(sc.tabs[0].members[g].ws, u_in[g], member_grid_bytes(plan->members[g]),
+                             hipMemcpyDeviceToDevice, s));
 
-    // Upload the member table from plan-owned pinned staging; the previous
+    // Upload the member tables from plan-owned pinned staging; the previous
     // upload must have left the staging before it is rewritten.
-    const size_t mb = sizeof(GMember) * nm;
+    const size_t tb = sizeof(GMember) * nm;
+    const size_t mb = tb * sc.tabs.size();
     if (!plan->stage_event) B_HIP(hipEventCreateWithFlags(&plan->stage_event, hipEventDisableTiming));
     else B_HIP(hipEventSynchronize(plan->stage_event));
     if (plan->stage_cap < mb) {
@@ -316,18 +394,59 @@ st_status stencil_apply_batched(const st_plan* plan, const void* const* u_in, vo
         B_HIP(hipHostMalloc(&plan->stage, mb, hipHostMallocDefault));
         plan->stage_cap = mb;
     }
-    memcpy(plan->stage, lay.members.data(), mb);
+    for (size_t i = 0; i < sc.tabs.size(); ++i)
+        memcpy((char*)plan->stage + i * tb, sc.tabs[i].members.data(), tb);
     B_HIP(hipMemcpyAsync(d_members, plan->stage, mb, hipMemcpyHostToDevice, s));
     B_HIP(hipEventRecord(plan->stage_event, s));
 
     const int bc = plan->prob.boundary;
-    for (int round = 0; round < lay.rounds; ++round) {
+    size_t ti = 0;
+    for (int round = 0; round < sc.rounds; ++round) {
+        while (ti + 1 < sc.starts.size() && sc.starts[ti + 1] <= round) ++ti;
+        const GMember* tab = d_members + ti * nm;
+        const int grid = sc.tabs[ti].grid;
         const int dt = plan->prob.dtype;
-        hipError_t e = dt == ST_F16   ? launch_round_t<_Float16>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
-                       : dt == ST_F64 ? launch_round_t<double>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s)
-                                      : launch_round_t<float>(bc, lay.ry, d_members, nm, round, steps, lay.grid, lay.lds, s);
+        hipError_t e = dt == ST_F16   ? launch_round_t<_Float16>(bc, lay.ry, tab, nm, round, steps, grid, lay.lds, s)
+                       : dt == ST_F64 ? launch_round_t<double>(bc, lay.ry, tab, nm, round, steps, grid, lay.lds, s)
+                                      : launch_round_t<float>(bc, lay.ry, tab, nm, round, steps, grid, lay.lds, s);
         if (e != hipSuccess) B_FAIL(ST_EHIP, "batched launch %d failed: %s", round, hipGetErrorString(e));
     }
+    return ST_OK;
+}
+
+st_status stencil_plan_describe_batched(const st_plan* plan, int32_t steps, int32_t cus, int32_t* launches,
+                                        int32_t* tables, int64_t* workgroups) {
+    stk::set_error("%s", "");
+    if (!plan || !plan->batched) B_FAIL(ST_EINVAL, "not a batched plan");
+    if (steps < 1) B_FAIL(ST_EINVAL, "steps must be >= 1");
+    if (cus < 0) B_FAIL(ST_EINVAL, "cus must be >= 0");
+    if (cus == 0) {
+        int dev = 0;
+        B_HIP(hipGetDevice(&dev));
+        B_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    // Stand-in buffer addresses (never dereferenced): distinct inputs and
+    // outputs, workspace partners after them.
+    const int nm = (int)plan->members.size();
+    std::vector<const void*> in(nm);
+    std::vector<void*> out(nm);
+    for (int g = 0; g < nm; ++g) {
+        in[g] = (const void*)(uintptr_t)(((uint64_t)2 * g + 1) << 32);
+        out[g] = (void*)(uintptr_t)(((uint64_t)2 * g + 2) << 32);
+    }
+    Schedule sc;
+    const char* bad = build_schedule(plan, steps, std::max(1, (int)cus), in.data(), out.data(),
+                                     (char*)(uintptr_t)((uint64_t)(2 * nm + 2) << 32), sc);
+    if (bad) B_FAIL(ST_EINVAL, "batched schedule: %s", bad);
+    int64_t wg = 0;
+    size_t ti = 0;
+    for (int round = 0; round < sc.rounds; ++round) {
+        while (ti + 1 < sc.starts.size() && sc.starts[ti + 1] <= round) ++ti;
+        wg += sc.tabs[ti].grid;
+    }
+    if (launches) *launches = sc.rounds;
+    if (tables) *tables = (int32_t)sc.tabs.size();
+    if (workgroups) *workgroups = wg;
     return ST_OK;
 }
 

@@ -80,17 +80,33 @@ CaseKey classify(const st_problem& p) {
     return k;
 }
 
+CaseKey reverse_key(const st_problem& p) {
+    CaseKey k = classify(p);
+    k.update = kKeyWaveReverse;
+    return k;
+}
+
 std::string key_string(const CaseKey& k) {
     char buf[128];
     snprintf(buf, sizeof buf, "%dd %s%d %s %s %s c%d%s", k.ndim, k.shape == kStar ? "star" : "box",
              k.r, k.dtype == 0 ? "f32" : (k.dtype == 1 ? "f16" : "f64"), k.boundary == kPeriodic ? "periodic" : "zero",
-             k.update == 0 ? "linear" : (k.update == 1 ? "wave" : "varcoef"), k.size_class,
+             k.update == 0 ? "linear" : (k.update == 1 ? "wave" : (k.update == 2 ? "varcoef" : "wave-reverse")), k.size_class,
              k.slab == 0 ? "" : (k.slab == 1 ? " slab-few-planes" : (k.slab == 2 ? " slab-long-march" : " slab-across")));
     return buf;
 }
 
 static LaunchCfg default_cfg(const CaseKey& k) {
     LaunchCfg c{};
+    if (k.update == kKeyWaveReverse) {
+        // LDS-ring reverse kernel with 64 x 32 tiles (16 waves, one
+        // workgroup per CU): measured best for the pointwise gradient step,
+        // 43.0 against 44.6 ms with 64 x 16 tiles on the 256^3 x 200 case.
+        c.variant = ST_VARIANT_WAVE3D_LDS;
+        c.tile_y = 32;
+        c.tsteps = 1;
+        c.zchunk = kAutoChunk;
+        return c;
+    }
     if (k.update == ST_WAVE) {
         c.variant = ST_VARIANT_WAVE3D_LDS;
         c.tile_y = 32;
@@ -147,6 +163,7 @@ LaunchCfg variant_default(const st_problem& p, int variant) {
         case ST_VARIANT_ZM3D: c.tile_y = 16; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_ZM3D_MFMA: c.tile_y = 64; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_ZM3D_H2: c.tile_y = 16; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_YM2D_H2: c.tile_x = 256; c.tile_y = 0; c.tsteps = 2; break;
         case ST_VARIANT_WAVE3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D_LDS: c.tile_y = 32; c.zchunk = kAutoChunk; break;
         default: break;
@@ -267,11 +284,18 @@ int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident) {
     return zc >= p.n[2] ? 0 : (int)zc;
 }
 
+// The reverse step runs one step per launch in either wave kernel family.
+bool adj_cfg_legal(const st_problem& p, const LaunchCfg& c) {
+    return p.update == ST_WAVE && (c.variant == ST_VARIANT_WAVE3D_LDS || c.variant == ST_VARIANT_WAVE3D) &&
+           (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 1;
+}
+
 bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
     if (p.update == ST_WAVE) {
         if (c.tsteps == 2 && !wave3d_tb2_supported(p.radius)) return false;
-        if (c.variant == ST_VARIANT_WAVE3D_LDS)
-            return (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1;
+        if (c.variant == ST_VARIANT_WAVE3D_LDS)   // tile_x: planes staged per barrier (0 or 1: one, 2: two)
+            return (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1 &&
+                   c.tile_x >= 0 && c.tile_x <= 2;
         return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
     }
@@ -293,6 +317,12 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
                    c.tsteps >= 0 && c.tsteps <= 1;
         return c.variant == ST_VARIANT_ZM3D && (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) &&
                c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 2;
+    }
+    if (c.variant == ST_VARIANT_YM2D_H2) {
+        if (p.shape != ST_BOX || p.radius > 2 || p.dtype != ST_F16 || p.n[0] % 2 != 0) return false;
+        if (c.tile_x != 256 && c.tile_x != 512) return false;
+        if (c.tile_y < 0 || c.tsteps < 1 || c.tsteps > 16 || c.tile_x - 2 * c.tsteps < kWave) return false;
+        return ym2d_h2_lds_bytes(c.tile_x, c.tsteps, p.radius) <= ym2d_max_lds_bytes();
     }
     if (c.variant == ST_VARIANT_YM2D) {
         if (c.tile_x != 256 && c.tile_x != 512) return false;

@@ -111,6 +111,10 @@ bool zm3d_mfma_supported(const Geom& g);
 hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
                           hipStream_t stream);
 bool zm3d_h2_supported(const Geom& g);
+hipError_t launch_ym2d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out, int k,
+                          hipStream_t stream);
+bool ym2d_h2_supported(const Geom& g);
+int ym2d_h2_lds_bytes(int nt, int k, int R);
 hipError_t launch_zm3d_tb2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in,
                            void* out, hipStream_t stream);
 bool zm3d_tb2_supported(int r, int shape);
@@ -177,6 +181,7 @@ int ym2d_auto_chunk(int nx, int ny, int nt, int k, int R);
 inline hipError_t launch_linear2d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
                                   const void* in, void* out, int k, hipStream_t stream) {
     if (cfg.variant == 5) return launch_ym2d(g, cfg, taps, in, out, k, stream);
+    if (cfg.variant == 9) return launch_ym2d_h2(g, cfg, taps, in, out, k, stream);
     return launch_tb2d(g, cfg, taps, in, out, k, stream);
 }
 

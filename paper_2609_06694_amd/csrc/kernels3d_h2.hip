@@ -15,7 +15,9 @@
 // local mean, so the sweep's action on slowly varying data (and its sum
 // for a periodic grid) keeps the f32 weights' value.  What is left,
 // sum (w - w_hi)(u(x+d) - u(x)), is below 2^-12 of the local variation and
-// well under the binary16 rounding of every step.
+// well under the binary16 rounding of every step.  Under a zero frame the
+// taps that leave the grid read zero rather than the centre value, so there
+// the residual sum runs over the taps inside the grid only.
 //
 // Layout and march follow the z-march of zmarch.h: a workgroup owns a
 // column of 128 x BY cells, stages every plane once (with a one-pair halo
@@ -31,13 +33,31 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 // Weights of a radius-1 box in the form the kernel consumes, per (dz, dy)
 // row k = (dz+1)*3 + (dy+1): packed (w_0, w_1) and (w_-1, w_0) binary16
-// pairs, the binary16 values of w_-1 and w_1 widened to f32, and the sum of
-// all residuals w - w_hi.
+// pairs, the binary16 values of w_-1 and w_1 widened to f32, the sum of
+// all residuals w - w_hi, and each residual in (dz, dy, dx) order.
 struct H2Taps {
     uint32_t p01[9], pm0[9];
     float wm[9], wp[9];
     float res;
+    float rr[27];
 };
+
+// Sum of the residuals rr (27, in LDS) of the taps of cell (cx, cy, cz)
+// that land inside an nx x ny x nz grid (with all_z, every plane counts as
+// inside).  A rolled loop: it runs once per thread and on the two face
+// planes only.
+__device__ __forceinline__ float h2_inner_res(const float* rr, int cx, int cy, int cz, int nx, int ny, int nz,
+                                              bool all_z) {
+    float r = 0.f;
+#pragma unroll 1
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const bool in = (all_z || (unsigned)(cz + dz) < (unsigned)nz) && (unsigned)(cy + dy) < (unsigned)ny &&
+                        (unsigned)(cx + dx) < (unsigned)nx;
+        r += in ? rr[t] : 0.f;
+    }
+    return r;
+}
 
 template <int RY, int NW>
 struct H2Geom {
@@ -98,6 +118,22 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
         const bool okx = fix_coord<BC>(px, nxp), oky = fix_coord<BC>(py, ny);
         off[RY + j] = (uint32_t)(py * nxp + px) * 4u;
         mxy |= (uint32_t)(hv && okx && oky) << (RY + j);
+    }
+
+    // Zero frame: residual sums over the in-grid taps of each cell of the
+    // thread's pairs, for planes away from the z faces (the face planes
+    // recompute theirs).
+    __shared__ float rrs[27];
+    float ria[RY], rib[RY];
+    if constexpr (BC == kZero) {
+        if (threadIdx.x < 27) rrs[threadIdx.x] = tp.rr[threadIdx.x];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            const int cy = y0 + ty * RY + i;
+            ria[i] = h2_inner_res(rrs, 2 * gx, cy, 0, 2 * nxp, ny, nz, true);
+            rib[i] = h2_inner_res(rrs, 2 * gx + 1, cy, 0, 2 * nxp, ny, nz, true);
+        }
     }
 
     float ax[3][RY], ay[3][RY];   // partial sums of output planes zp-1, zp, zp+1 (cells x, x+1)
@@ -179,10 +215,25 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                 }
             }
             // The weight residuals, applied to the centre value.
+            if constexpr (BC == kPeriodic) {
 #pragma unroll
-            for (int i = 0; i < RY; ++i) {
-                ax[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).x, ax[1][i]);
-                ay[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+                for (int i = 0; i < RY; ++i) {
+                    ax[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).x, ax[1][i]);
+                    ay[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+                }
+            } else {
+                const bool zface = zp < 1 || zp > nz - 2;   // uniform over the workgroup
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    float ra = ria[i], rb = rib[i];
+                    if (zface) {
+                        const int cy = y0 + ty * RY + i;
+                        ra = h2_inner_res(rrs, 2 * gx, cy, zp, 2 * nxp, ny, nz, false);
+                        rb = h2_inner_res(rrs, 2 * gx + 1, cy, zp, 2 * nxp, ny, nz, false);
+                    }
+                    ax[1][i] = fmaf(ra, (float)as_h2(p0[i + 1]).x, ax[1][i]);
+                    ay[1][i] = fmaf(rb, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+                }
             }
 
             // Output plane zp - 1 has received all three planes.
@@ -233,7 +284,12 @@ static H2Taps pack_h2(const Taps& t) {
         h.pm0[k] = __builtin_bit_cast(uint32_t, c);
         h.wm[k] = (float)hm;
         h.wp[k] = (float)hp;
-        res += ((double)wm - (double)(float)hm) + ((double)w0 - (double)(float)h0) + ((double)wp - (double)(float)hp);
+        const double rm = (double)wm - (double)(float)hm, r0 = (double)w0 - (double)(float)h0,
+                     rp = (double)wp - (double)(float)hp;
+        h.rr[k * 3 + 0] = (float)rm;
+        h.rr[k * 3 + 1] = (float)r0;
+        h.rr[k * 3 + 2] = (float)rp;
+        res += rm + r0 + rp;
     }
     h.res = (float)res;
     return h;

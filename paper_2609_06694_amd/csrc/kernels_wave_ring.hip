@@ -17,14 +17,20 @@
 
 namespace stk {
 
-template <int R, int BC, int RY, int NW, int D, bool ISO, bool LAP = false, bool SP = false>
+// PB planes are staged per barrier (1, or 2 = the D planes of one march
+// step).  The next group's staging may run while slower waves still read
+// the current group, so the halo tiles rotate over 2 PB buffers and the
+// ring holds the 2R + PB planes the current group's outputs read plus the
+// PB planes the next group writes: 2R+2 slots for PB = 1, 2R+4 for PB = 2.
+template <int R, int BC, int RY, int NW, int D, bool ISO, bool LAP = false, bool SP = false, int PB = 1>
 __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, int nx, int ny, int nz,
                                                                  int zc, int tiles_x, int tiles_y,
                                                                  Taps tp) {
+    static_assert(PB == 1 || PB == D, "one plane, or one march step of D planes, per barrier");
     using G = PlaneGeom<R, RY, NW>;
-    constexpr int NR = 2 * R + 2;          // ring depth: one spare slot separates writers and readers
+    constexpr int NR = 2 * R + 2 * PB;     // ring depth (see above)
     constexpr int IP = G::BX * G::BY;      // interior cells per plane
-    __shared__ float tile[2][G::H * G::W];
+    __shared__ float tile[2 * PB][G::H * G::W];
     __shared__ float ring[NR][IP];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int txi = b % tiles_x;
@@ -79,27 +85,43 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
         issue_point(d, zbeg + d - R);
     }
 
-    int slot = 0;   // ring slot of plane zp
+    // Stage plane zp (arrived in slot d of the prefetch) into halo tile t
+    // and ring slot sl, then issue the loads of plane zp + D.  The wave
+    // issues those loads at raised priority, so they leave before the other
+    // waves' arithmetic (1 % faster on the 512^3 radius-4 workload; raising
+    // it for the pointwise loads too gained less).
+    auto stage = [&](int d, int zp, float* t, int sl) {
+        store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) ring[sl][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
+        __builtin_amdgcn_s_setprio(3);
+        vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
+        __builtin_amdgcn_s_setprio(0);
+    };
+
+    int slot = 0;   // ring slot of plane zs
     for (int zs = zbeg; zs < zend; zs += D) {
+        // The march runs in whole groups of D planes: up to D-1 planes past
+        // zend are clamped loads that emit no output.  (A uniform early exit
+        // here would let the compiler assume fewer loads in flight at the
+        // loop head and wait for all of them.)
+        if constexpr (PB == D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int sl = slot + d >= NR ? slot + d - NR : slot + d;
+                stage(d, zs + d, tile[(zs - zbeg + d) & (2 * PB - 1)], sl);
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int zp = zs + d;
-            // The march runs in whole groups of D planes: up to D-1 planes
-            // past zend are clamped loads that emit no output.  (A uniform
-            // early exit here would let the compiler assume fewer loads in
-            // flight at the loop head and wait for all of them.)
-            float* t = tile[zp & 1];
-            store_plane<R, RY, BC, float, NW>(t, vin[d], vhalo[d], vm[d]);
-#pragma unroll
-            for (int i = 0; i < RY; ++i) ring[slot][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
-            // The wave issues the next plane's loads at raised priority, so
-            // they leave before the other waves' arithmetic (1 % faster on
-            // the 512^3 radius-4 workload; raising it for the pointwise
-            // loads too gained less).
-            __builtin_amdgcn_s_setprio(3);
-            vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
-            __builtin_amdgcn_s_setprio(0);
-            __syncthreads();
+            const int sd = slot + d >= NR ? slot + d - NR : slot + d;   // ring slot of plane zp
+            float* t = tile[(zp - zbeg) & (2 * PB - 1)];
+            if constexpr (PB == 1) {
+                stage(d, zp, t, sd);
+                __syncthreads();
+            }
 
             float p[RY], uc[RY];
             star_plane_diff<R, RY, ISO, NW>(t, tp, p, uc);
@@ -114,7 +136,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
                 int sl[2 * R + 1];
 #pragma unroll
                 for (int j = 0; j <= 2 * R; ++j) {
-                    const int s2 = slot - 2 * R + j;
+                    const int s2 = sd - 2 * R + j;
                     sl[j] = s2 < 0 ? s2 + NR : s2;
                 }
 #pragma unroll
@@ -176,14 +198,14 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
             for (int q = 0; q < R; ++q)
 #pragma unroll
                 for (int i = 0; i < RY; ++i) pq[q][i] = pq[q + 1][i];
-            slot = slot + 1 == NR ? 0 : slot + 1;
         }
+        slot = slot + D >= NR ? slot + D - NR : slot + D;
     }
 }
 
 bool wave3d_ring_supported(int r) { return r >= 1 && r <= 4; }
 
-template <int R, int BC, int RY, int NW, bool SP>
+template <int R, int BC, int RY, int NW, bool SP, int PB>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
     using G = PlaneGeom<R, RY, NW>;
     constexpr int D = 2;
@@ -192,32 +214,42 @@ static hipError_t go(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w,
     const dim3 grid(tiles_x * tiles_y * nchunks), block(G::NT);
     if (w.lap_out) {   // also write L(u_t) (gradient recompute)
         if (g.iso)
-            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, true, SP>), grid, block, 0, s, w, g.nx,
-                               g.ny, g.nz, zc, tiles_x, tiles_y, tp);
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, true, SP, PB>), grid, block, 0, s, w,
+                               g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp);
         else
-            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, true, SP>), grid, block, 0, s, w, g.nx,
-                               g.ny, g.nz, zc, tiles_x, tiles_y, tp);
+            hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, true, SP, PB>), grid, block, 0, s, w,
+                               g.nx, g.ny, g.nz, zc, tiles_x, tiles_y, tp);
         return hipGetLastError();
     }
     if (g.iso)
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, false, SP>), grid, block, 0, s, w, g.nx,
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, true, false, SP, PB>), grid, block, 0, s, w, g.nx,
                            g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     else
-        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, false, SP>), grid, block, 0, s, w, g.nx,
+        hipLaunchKernelGGL((wave3d_ring_kernel<R, BC, RY, NW, D, false, false, SP, PB>), grid, block, 0, s, w, g.nx,
                            g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     return hipGetLastError();
+}
+
+// cfg.tile_x selects the planes staged per barrier: 2 = the two planes of a
+// march step, else one.
+template <int R, int BC, int RY, int NW, bool SP>
+static hipError_t go_pb(const Geom& g, const LaunchCfg& c, int zc, const Taps& tp, const WaveLaunch& w,
+                        hipStream_t s) {
+    if (c.tile_x == 2) return go<R, BC, RY, NW, SP, 2>(g, zc, tp, w, s);
+    return go<R, BC, RY, NW, SP, 1>(g, zc, tp, w, s);
 }
 
 // The absorbing layer is provided with the zero frame only (its damping band
 // lines the faces of a bounded domain).
 template <int R, int BC, int RY, int NW>
-static hipError_t go_sp(const Geom& g, int zc, const Taps& tp, const WaveLaunch& w, hipStream_t s) {
+static hipError_t go_sp(const Geom& g, const LaunchCfg& c, int zc, const Taps& tp, const WaveLaunch& w,
+                        hipStream_t s) {
     if constexpr (BC == kZero) {
-        if (w.sp_w > 0) return go<R, BC, RY, NW, true>(g, zc, tp, w, s);
+        if (w.sp_w > 0) return go_pb<R, BC, RY, NW, true>(g, c, zc, tp, w, s);
     } else {
         if (w.sp_w > 0) return hipErrorInvalidValue;
     }
-    return go<R, BC, RY, NW, false>(g, zc, tp, w, s);
+    return go_pb<R, BC, RY, NW, false>(g, c, zc, tp, w, s);
 }
 
 template <int R, int BC>
@@ -227,9 +259,9 @@ static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const Taps& tp, const
     // Two rows per thread at every tile height: taller tiles add waves (up
     // to 16, a 1024-thread workgroup) rather than registers, so occupancy
     // stays at four waves per SIMD while the halo share of each plane falls.
-    if (c.tile_y >= 32) return go_sp<R, BC, 2, 16>(g, zc, tp, w, s);
-    if (c.tile_y >= 16) return go_sp<R, BC, 2, 8>(g, zc, tp, w, s);
-    return go_sp<R, BC, 2, 4>(g, zc, tp, w, s);
+    if (c.tile_y >= 32) return go_sp<R, BC, 2, 16>(g, c, zc, tp, w, s);
+    if (c.tile_y >= 16) return go_sp<R, BC, 2, 8>(g, c, zc, tp, w, s);
+    return go_sp<R, BC, 2, 4>(g, c, zc, tp, w, s);
 }
 
 template <int R>

@@ -39,6 +39,12 @@ struct CaseKey {
 CaseKey classify(const st_problem& p);
 std::string key_string(const CaseKey& k);
 
+// Key-only update value: the reverse (adjoint and gradient) step of a wave
+// case has a map cell of its own next to the forward step's.
+constexpr int kKeyWaveReverse = 3;
+CaseKey reverse_key(const st_problem& p);
+bool adj_cfg_legal(const st_problem& p, const LaunchCfg& c);
+
 // Default entry for a case (compiled in), then the tuning cache file and the
 // in-process table written by the autotuner override it.
 LaunchCfg dispatch_lookup(const CaseKey& k);
@@ -53,7 +59,12 @@ constexpr int kAutoChunk = -1;   // dispatch-map value: derive the plane chunk f
 int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident = 0);
 
 void set_error(const char* fmt, ...);
-size_t batched_meta_bytes(const st_plan* plan, int steps);
+// Batch depth value asking for each member's own map depth.
+constexpr int kMemberDepths = -1;
+// Member-table bytes of a batched launch of `steps` steps at batch depth
+// kbatch (0: the plan's own).
+size_t batched_meta_bytes(const st_plan* plan, int steps, int kbatch = 0);
+size_t reverse_tune_bytes(const st_problem& p);   // autotune scratch for a wave plan's reverse step
 size_t batch_tune_bytes(const st_plan* plan);   // autotune scratch for the batch depth
 Geom geom_of(const st_problem& p);
 Geom plan_geom(const st_plan* pl);

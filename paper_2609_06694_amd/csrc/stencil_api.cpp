@@ -195,12 +195,18 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
         if (d.zchunk == kAutoChunk) d.zchunk = auto_zchunk(*p, d);
         pl->cfg = d;
     }
-    // The adjoint and gradient steps have their own configuration: the
-    // LDS-ring kernel with 64 x 32 tiles (16 waves, one workgroup per CU;
-    // measured best for the pointwise gradient step, 43.0 against 44.6 ms
-    // with 64 x 16 tiles on the 256^3 x 200 workload).
-    pl->adj_cfg = LaunchCfg{ST_VARIANT_WAVE3D_LDS, 0, 32, 1, 0};
-    pl->adj_cfg.zchunk = auto_zchunk(*p, pl->adj_cfg, 1);
+    // The adjoint and gradient steps have a map cell of their own.
+    if (p->update == ST_WAVE) {
+        auto fix_chunk = [&](LaunchCfg& c) {
+            if (c.zchunk == kAutoChunk) c.zchunk = auto_zchunk(*p, c, c.variant == ST_VARIANT_WAVE3D_LDS ? 1 : 0);
+        };
+        pl->adj_cfg = dispatch_lookup(reverse_key(*p));
+        fix_chunk(pl->adj_cfg);
+        if (!adj_cfg_legal(pl->prob, pl->adj_cfg)) {
+            pl->adj_cfg = default_dispatch(reverse_key(*p));
+            fix_chunk(pl->adj_cfg);
+        }
+    }
     pl->ckpt_every = 20;
     pl->batched = false;
     if (opts) {
@@ -514,6 +520,19 @@ st_status stencil_plan_describe(const st_plan* plan, int32_t* variant, int32_t* 
     return ST_OK;
 }
 
+st_status stencil_plan_describe_reverse(const st_plan* plan, int32_t* variant, int32_t* tile_x,
+                                        int32_t* tile_y, int32_t* tsteps, int32_t* zchunk) {
+    stk::set_error("%s", "");
+    if (!plan || plan->batched || plan->prob.update != ST_WAVE) ST_FAIL(ST_EINVAL, "needs a wave plan");
+    const LaunchCfg& c = plan->adj_cfg;
+    if (variant) *variant = c.variant;
+    if (tile_x) *tile_x = c.tile_x;
+    if (tile_y) *tile_y = c.tile_y;
+    if (tsteps) *tsteps = c.tsteps;
+    if (zchunk) *zchunk = c.zchunk;
+    return ST_OK;
+}
+
 st_status stencil_plan_coefficients(const st_plan* plan, float* dense, int32_t count, double* weight_sum) {
     stk::set_error("%s", "");
     if (!plan || plan->batched) ST_FAIL(ST_EINVAL, "needs a single-grid plan");
@@ -684,7 +703,8 @@ size_t stencil_workspace_bytes(const st_plan* plan, int32_t steps, int32_t mode)
         const size_t kb = plan->prob.update == ST_WAVE      ? gb
                           : plan->prob.update == ST_VARCOEF ? (size_t)(varcoef_taps(plan->prob) + 1) * gb
                                                             : 0;
-        return 4 * gb + kb + 64;
+        // A wave plan also tunes its reverse step (fields past tune_one's).
+        return 4 * gb + kb + 64 + (plan->prob.update == ST_WAVE ? reverse_tune_bytes(plan->prob) : 0);
     }
     return grid_bytes(plan->prob);
 }

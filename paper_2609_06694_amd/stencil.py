@@ -76,9 +76,12 @@ class _Plan:
         return self._h
 
     def describe(self) -> dict:
+        return self._describe(lib().stencil_plan_describe)
+
+    def _describe(self, fn) -> dict:
         v, tx, ty, k, zc = (ctypes.c_int32() for _ in range(5))
-        check(lib().stencil_plan_describe(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty),
-                                          ctypes.byref(k), ctypes.byref(zc)))
+        check(fn(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k),
+                 ctypes.byref(zc)))
         return {"variant": _abi.VARIANT_NAMES.get(v.value, v.value), "tile_x": tx.value,
                 "tile_y": ty.value, "tsteps": k.value, "zchunk": zc.value}
 
@@ -273,6 +276,10 @@ class WaveModel(_Plan):
         self.grid_shape = tuple(reversed(self.n))
         self._ws: Optional[_Workspace] = None
 
+    def describe_reverse(self) -> dict:
+        """Configuration of the adjoint and gradient steps (a map cell of its own)."""
+        return self._describe(lib().stencil_plan_describe_reverse)
+
     def _chk(self, ops):
         """Each (name, tensor, shape, min_len) must be a contiguous float32
         device tensor of that shape (or, with min_len, at least that many
@@ -382,7 +389,8 @@ def wave_misfit(kappa, model: WaveModel, u0, u_prev, steps, src, wavelet, rec_z,
 
 class BatchedStencil(_Plan):
     """Many independent 2D linear sweeps advanced together: one launch per
-    time block for the whole batch."""
+    time block for the whole batch.  tsteps: the batch depth (default 3),
+    or -1 for each member's own map depth."""
 
     def __init__(self, cases: List[dict], **opts):
         super().__init__()
@@ -401,6 +409,16 @@ class BatchedStencil(_Plan):
         check(lib().stencil_plan_batched(arr, len(cases), ctypes.byref(o) if o is not None else None,
                                          ctypes.byref(self._h)))
         self._ws: Optional[_Workspace] = None
+
+    def schedule(self, steps: int, cus: int = 0) -> dict:
+        """Grouped launches, member tables and workgroups of an apply of
+        `steps` steps on a device of `cus` compute units (0: the current
+        device's); host only for cus > 0."""
+        n, t = ctypes.c_int32(), ctypes.c_int32()
+        wg = ctypes.c_int64()
+        check(lib().stencil_plan_describe_batched(self._h, int(steps), int(cus), ctypes.byref(n), ctypes.byref(t),
+                                                  ctypes.byref(wg)))
+        return {"launches": n.value, "tables": t.value, "workgroups": wg.value}
 
     def apply(self, us: List[torch.Tensor], steps: int, outs: Optional[List[torch.Tensor]] = None,
               stream=None) -> List[torch.Tensor]:

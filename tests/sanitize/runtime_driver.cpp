@@ -156,7 +156,24 @@ int main(int argc, char** argv) {
         EXPECT(stencil_apply_batched(h, ptrs.data(), ptrs.data(), 8, nullptr, 0, nullptr) == ST_EWORKSPACE);
         EXPECT(stencil_apply_batched(h, ptrs.data(), ptrs.data(), -1, nullptr, 0, nullptr) == ST_EINVAL);
         EXPECT(stencil_plan_coefficients(h, nullptr, 0, nullptr) == ST_EINVAL);
+        // The launch schedule (member tables built and checked on the host)
+        // at a batch depth and at each member's own depth.
+        for (int steps : {1, 7, 32}) {
+            int32_t launches = 0, tables = 0;
+            int64_t wg = 0;
+            EXPECT(stencil_plan_describe_batched(h, steps, 256, &launches, &tables, &wg) == ST_OK);
+            EXPECT(launches >= 1 && tables >= 1 && wg >= launches);
+        }
+        EXPECT(stencil_plan_describe_batched(h, 0, 256, nullptr, nullptr, nullptr) == ST_EINVAL);
         stencil_plan_destroy(h);
+        st_plan_opts own;
+        memset(&own, 0, sizeof own);
+        own.tsteps = -1;
+        EXPECT(stencil_plan_batched(ps.data(), (int)ps.size(), &own, &h) == ST_OK);
+        for (int steps : {1, 5, 33}) EXPECT(stencil_plan_describe_batched(h, steps, 7, nullptr, nullptr, nullptr) == ST_OK);
+        stencil_plan_destroy(h);
+        own.tsteps = -2;
+        EXPECT(stencil_plan_batched(ps.data(), (int)ps.size(), &own, &h) == ST_EINVAL);
         ps[3].dtype = 1;
         EXPECT(stencil_plan_batched(ps.data(), (int)ps.size(), nullptr, &h) == ST_EINVAL);
         EXPECT(stencil_plan_batched(ps.data(), 0, nullptr, &h) == ST_EINVAL);

@@ -198,6 +198,21 @@ def test_batched_plan_host_checks(L):
     assert L.stencil_apply_batched(h, fake, fake, 4, None, 0, None) == _abi.ST_EWORKSPACE
     assert L.stencil_apply(h, fake[0], fake[0], 1, None, None, 0, None) == _abi.ST_EINVAL
     L.stencil_plan_destroy(h)
+    # Each member's own map depth (tsteps = -1): the plan reports -1, and
+    # members that finish early add member tables to the workspace; below
+    # -1 is rejected.
+    grids = sum((c.cells * 4 + 255) // 256 * 256 for c in cases)
+    for k, code in ((-1, _abi.ST_OK), (-2, _abi.ST_EINVAL), (8, _abi.ST_OK)):
+        o = _abi.StPlanOpts(0, 0, 0, k, 0, 0)
+        hk = ctypes.c_void_p()
+        assert L.stencil_plan_batched(arr, len(cases), ctypes.byref(o), ctypes.byref(hk)) == code, k
+        if code != _abi.ST_OK:
+            continue
+        ts = ctypes.c_int32()
+        L.stencil_plan_describe(hk, None, None, None, ctypes.byref(ts), None)
+        assert ts.value == k
+        assert L.stencil_workspace_bytes(hk, 32, 0) > grids
+        L.stencil_plan_destroy(hk)
     arr[2].dtype = 1   # mixed storage types are rejected
     assert L.stencil_plan_batched(arr, len(cases), None, ctypes.byref(h)) == _abi.ST_EINVAL
     assert L.stencil_plan_batched(arr, 0, None, ctypes.byref(h)) == _abi.ST_EINVAL
@@ -379,3 +394,63 @@ def test_packed_half_variant_needs_even_fp16_box(L):
     for kw in (dict(n=(63, 20, 10), dtype=1), dict(n=(64, 20, 10), dtype=0), dict(n=(64, 20, 10), dtype=1, r=2)):
         p, keep2 = _prob(ndim=3, shape=1, **dict(dict(r=1), **kw))
         assert _plan(L, p, _abi.StPlanOpts(_abi.ST_VARIANT_ZM3D_H2, 0, 16, 0, 0, 0))[0] == _abi.ST_EINVAL, kw
+
+
+def test_reverse_step_has_its_own_map_cell(tmp_path):
+    """A wave plan's adjoint/gradient step reads the map cell of the reverse
+    key (update value 3 next to the forward key's 1): a cache line for it
+    changes the reverse configuration and leaves the forward one alone; an
+    illegal line falls back to the compiled-in default."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    # 256^3 is size class 3; the forward key (update 1) is not in the file.
+    cache.write_text("3 0 4 0 1 3 3 0 4 0 16 1 48\n")
+    code = (
+        "from paper_2609_06694_amd import stencil as st\n"
+        "m=st.WaveModel((256,256,256)); f=m.describe(); r=m.describe_reverse()\n"
+        "print(r['variant'], r['tile_y'], r['zchunk'], f['variant'])\n")
+    env = dict(os.environ, STENCIL_TUNE_CACHE=str(cache), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["wave3d_lds", "16", "48", "wave3d_lds"]
+    cache.write_text("3 0 4 0 1 3 3 0 4 0 12 1 48\n")   # 12-row tiles do not exist
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[:2] == ["wave3d_lds", "32"]
+
+
+def test_describe_reverse_needs_a_wave_plan(L):
+    p, keep = _prob(ndim=3, n=(64, 40, 30), shape=0, r=1)
+    st, h = _plan(L, p)
+    assert st == _abi.ST_OK
+    v = ctypes.c_int32()
+    assert L.stencil_plan_describe_reverse(h, ctypes.byref(v), None, None, None, None) == _abi.ST_EINVAL
+    assert b"wave" in L.stencil_last_error()
+    L.stencil_plan_destroy(h)
+    assert L.stencil_plan_describe_reverse(None, None, None, None, None, None) == _abi.ST_EINVAL
+
+
+@pytest.mark.parametrize("tsteps", [0, 1, 3, 8, -1])
+def test_batched_schedule_tables_check_out(tsteps):
+    """The grouped launch's schedule (the same host code that builds and
+    checks the apply's member tables): one launch per time block of the
+    deepest-running member, a new table where the set of running members
+    changes, every table's workgroup ranges contiguous (checked inside).
+    Host only."""
+    from paper_2609_06694_amd import stencil as st
+    cases = wl.batch2d(count=40, lo=64, hi=1500, steps=4)
+    spec = [dict(n=c.n[:2], shape=wl.SHAPE_NAMES[c.shape], radius=c.radius, coeffs=c.coeffs) for c in cases]
+    bs = st.BatchedStencil(spec, **({"tsteps": tsteps} if tsteps else {}))
+    for steps in (1, 5, 7, 32, 33):
+        for cus in (1, 256):
+            sc = bs.schedule(steps, cus)
+            assert sc["launches"] >= 1 and sc["tables"] >= 1 and sc["workgroups"] >= sc["launches"]
+            if tsteps > 0:
+                assert sc["launches"] == -(-steps // tsteps)
+            if tsteps == 1:
+                assert sc["tables"] == 1
+    if tsteps == -1:   # members at their own depths finish at different launches
+        assert bs.schedule(32, 256)["tables"] > 1
+    with pytest.raises(_abi.StencilError):
+        bs.schedule(0, 256)

@@ -144,3 +144,38 @@ def test_autotune_f64(st):
     outs = bs.apply([torch.from_numpy(cb.u0).cuda() for cb in cases], 6)
     for cb, o in zip(cases, outs):
         assert rel_l2(o.cpu().numpy(), oracle.sweep(cb.u0, cb.coeffs, cb.shape, cb.radius, wl.PERIODIC, 6)) <= 1e-12
+
+
+def test_autotune_reverse_step(st, monkeypatch):
+    """The reverse (adjoint/gradient) step has its own tuned map cell: the
+    planted fault (16-row candidates, shifted centre weight of L^T) is
+    rejected before timing, and the tuned plan's gradient matches the
+    untuned plan's and the FP64 oracle."""
+    monkeypatch.setenv("STENCIL_TUNE_FAULT", "1")
+    rng = np.random.default_rng(64)
+    nx, ny, nz = 72, 60, 88
+    steps = 24
+    kappa = rng.uniform(0.05, 0.19, (nz, ny, nx)).astype(np.float32)
+    zeros = np.zeros_like(kappa)
+    src, rec = (nx // 2, ny // 2, 20), 9
+    wav = wl.ricker(steps, 8.0)
+    target = np.zeros((steps, ny, nx), np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def grad(m):
+        dk, loss = m.gradient(dev(zeros), dev(zeros), dev(kappa), steps, src, dev(wav), rec, dev(target))
+        return dk.cpu().numpy(), float(loss.cpu().numpy()[0])
+
+    base = st.WaveModel((nx, ny, nz), ckpt_every=6)
+    g0, J0 = grad(base)
+    m = st.WaveModel((nx, ny, nz), ckpt_every=6)
+    before = m.describe_reverse()
+    stats = m.autotune()
+    after = m.describe_reverse()
+    print("reverse step:", before, "->", after, stats)
+    assert stats["rejected"] > 0 and after["tile_y"] != 16 and after["variant"] == "wave3d_lds"
+    g1, J1 = grad(m)
+    g_ref, J_ref = oracle.wave_gradient(zeros, zeros, kappa, steps, src, wav, rec, target, ckpt_every=0)
+    print(f"tuned vs untuned dkappa rel-L2 {rel_l2(g1, g0):.2e}; vs oracle {rel_l2(g1, g_ref):.2e}")
+    assert rel_l2(g1, g0) <= 1e-6 and abs(J1 - J0) <= 1e-6 * abs(J0)
+    assert rel_l2(g1, g_ref) <= 1e-5 and abs(J1 - J_ref) <= 1e-5 * abs(J_ref)

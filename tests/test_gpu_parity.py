@@ -402,6 +402,32 @@ def test_3d_box_fp16_packed_half_vs_oracle(st, bc, ty):
         assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, 1, bcode, steps, adjoint=True)) <= TOL["f16"]
 
 
+@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+@pytest.mark.parametrize("nt,k,ych", [(256, 1, 0), (256, 2, 0), (512, 3, 32), (256, 4, 16), (512, 8, 0)])
+def test_2d_box_fp16_packed_half_vs_oracle(st, r, bc, nt, k, ych):
+    """Packed-half row march (fp16 boxes, two cells per lane, k fused steps
+    with every level rounded to binary16): ragged even nx, grids narrower
+    than a window, few rows, step counts that leave a shorter last block;
+    forward and transpose against the oracle at the fp16 gate and within 5x
+    of the binary16 storage floor."""
+    rng = np.random.default_rng(6160 + 10 * r + k)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    for (nx, ny), steps in [((1030, 517), 7), ((2, 9), 5), ((600, 3), 4), ((1536, 300), 9)]:
+        c = wl.random_unit_sum_coeffs(rng, 2, wl.BOX, r)
+        u = wl.small_random_grid(rng, 2, (nx, ny), np.float16, 0.0, 1.0)
+        s = st.Stencil((nx, ny), "box", r, c, dtype="f16", boundary=bc, variant=9, tile_x=nt, tile_y=ych, tsteps=k)
+        assert s.describe()["variant"] == "ym2d_h2"
+        got = _host(s.apply(_dev(u), steps)).astype(np.float64)
+        ref = oracle.sweep(u, c, wl.BOX, r, bcode, steps)
+        floor = rel_l2(oracle.sweep(u, c, wl.BOX, r, bcode, steps, storage="binary16"), ref)
+        e = rel_l2(got, ref)
+        assert e <= TOL["f16"] and e <= 5 * floor, (nx, ny, steps, e, floor)
+        v = wl.small_random_grid(rng, 2, (nx, ny), np.float16, 0.0, 1.0)
+        gotT = _host(s.apply_adjoint(_dev(v), steps)).astype(np.float64)
+        assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, r, bcode, steps, adjoint=True)) <= TOL["f16"]
+
+
 def test_graph_capture_replays_match_eager(st):
     """A sweep captured in a HIP graph (torch.cuda.graph) replays bitwise
     equal to the eager call, every replay, with eager work and
@@ -475,6 +501,47 @@ def test_wave_forward_vs_oracle(st, bc, variant, ty, zc, aniso):
     assert rel_l2(_host(uT), rb) <= 1e-5
     assert rel_l2(_host(uT1), ra) <= 1e-5
     assert rel_l2(_host(tr), rtr) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("ty,zc", [(32, 0), (16, 9), (8, 5), (32, 16)])
+def test_wave_two_planes_per_barrier_bitwise(st, bc, ty, zc):
+    """Staging the two planes of a march step per barrier (tile_x=2) gives
+    the one-plane-per-barrier result bit for bit (the same per-cell
+    arithmetic): forward with source and receiver against the oracle too,
+    and under the zero frame the absorbing layer and the gradient (whose
+    recompute writes L(u_t))."""
+    rng = np.random.default_rng(23)
+    n = (75, 41, 33)
+    kappa, u0, up = _wave_inputs(rng, n)
+    steps, src = 6, (30, 20, 17)
+    wav = wl.ricker(steps, 4.0)
+    bcode = wl.ZERO if bc == "zero" else wl.PERIODIC
+    outs = []
+    for tx in (0, 2):
+        m = st.WaveModel(n, boundary=bc, tile_y=ty, zchunk=zc, variant=4, tile_x=tx)
+        assert m.describe()["tile_x"] == tx
+        outs.append([_host(a) for a in m.forward(_dev(u0), _dev(up), _dev(kappa), steps, src=src,
+                                                 wavelet=_dev(wav), rec_z=5, record=True)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    ra, rb, rtr = oracle.wave_forward(up, u0, kappa, steps, boundary=bcode, src=src, wavelet=wav, rec_z=5)
+    assert rel_l2(outs[1][0], rb) <= 1e-5 and rel_l2(outs[1][1], ra) <= 1e-5 and rel_l2(outs[1][2], rtr) <= 1e-5
+    if bc != "zero":
+        return
+    sp = []
+    for tx in (0, 2):
+        m = st.WaveModel(n, tile_y=ty, zchunk=zc, variant=4, tile_x=tx, sponge=(6, 0.8))
+        sp.append([_host(a) for a in m.forward(_dev(u0), _dev(up), _dev(kappa), steps)[:2]])
+    for a, b in zip(*sp):
+        assert np.array_equal(a, b)
+    kg, zeros, gsrc, gwav, rec, target = _grad_case(steps=20, blob=False)
+    gr = []
+    for tx in (0, 2):
+        m = st.WaveModel(kg.shape[::-1], tile_y=ty, zchunk=zc, variant=4, tile_x=tx, ckpt_every=6)
+        dk, loss = m.gradient(_dev(zeros), _dev(zeros), _dev(kg), 20, gsrc, _dev(gwav), rec, _dev(target))
+        gr.append((_host(dk), _host(loss)))
+    assert np.array_equal(gr[0][0], gr[1][0]) and np.array_equal(gr[0][1], gr[1][1])
 
 
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
@@ -633,13 +700,15 @@ def _batched_cases(count, lo, hi, steps, seed, dtype=np.float32):
 def test_batched_matches_plain_and_oracle(st, dtype, bc):
     """Every member of a grouped batch equals the oracle and its own
     single-grid plan; in place with odd and even block counts; members
-    with different fused depths (so some finish before the last launch)."""
+    with different fused depths (so some finish before the last launch and
+    the later launches run on re-divided member tables): depth 8 (clamped
+    per member for f64) and each member's own map depth (tsteps=-1)."""
     npdt = {"f32": np.float32, "f16": np.float16, "f64": np.float64}[dtype]
     cases = _batched_cases(10, 64, 400, 7, 9, npdt)
     bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
     spec = [dict(n=c.n[:2], shape=c.shape, radius=c.radius, coeffs=c.coeffs, dtype=dtype, boundary=bc)
             for c in cases]
-    for opts in ({}, {"tsteps": 1}, {"tsteps": 3}):
+    for opts in ({}, {"tsteps": 1}, {"tsteps": 3}, {"tsteps": 8}, {"tsteps": -1}):
         bs = st.BatchedStencil(spec, **opts)
         ins = [_dev(c.u0) for c in cases]
         outs = bs.apply(ins, 7)
