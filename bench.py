@@ -166,10 +166,12 @@ TRAFFIC_PROFILE = "profiles/wave3d_fwd_r4_512cube_pmc_traffic.md"
 
 def ring_kernel_name(disp):
     """Instantiation of the LDS-ring leapfrog kernel a dispatch selects: two
-    rows per thread, tile_y / 2 waves per workgroup."""
+    rows per thread, tile_y / 2 waves per workgroup, tile_x = 2: both
+    planes of a march step staged per barrier."""
     if disp.get("variant") != "wave3d_lds":
         return disp.get("variant")
-    return f"wave3d_ring_kernel<R=4,zero,RY=2,NW={disp['tile_y'] // 2},D=2,iso>"
+    pb = ",PB=2" if disp.get("tile_x") == 2 else ""
+    return f"wave3d_ring_kernel<R=4,zero,RY=2,NW={disp['tile_y'] // 2},D=2,iso{pb}>"
 
 
 def measured_traffic(kernel):
