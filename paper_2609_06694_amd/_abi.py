@@ -25,8 +25,9 @@ ST_VARIANT_YM2D = 5
 ST_VARIANT_ZM3D_MFMA = 6
 ST_VARIANT_ZM3D_H2 = 8
 ST_VARIANT_YM2D_H2 = 9
+ST_VARIANT_YM3D = 10
 VARIANT_NAMES = {0: "auto", 1: "tb2d", 2: "zm3d", 3: "wave3d", 4: "wave3d_lds", 5: "ym2d", 6: "zm3d_mfma",
-                 7: "vc3d", 8: "zm3d_h2", 9: "ym2d_h2"}
+                 7: "vc3d", 8: "zm3d_h2", 9: "ym2d_h2", 10: "ym3d"}
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = ["stencil_plan", "stencil_plan_destroy", "stencil_workspace_bytes",

@@ -150,6 +150,14 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                 LaunchCfg c{ST_VARIANT_ZM3D_H2, 0, ty, 1, zc};
                 if (cfg_legal(p, c)) out.push_back(c);
             }
+        // The march along y, where z is shorter than y.
+        if (p.update == ST_LINEAR && p.n[2] < p.n[1])
+            for (int ty : {8, 16, 32})
+                for (int zc : {16, 32, 64, 128, 256, 0}) {
+                    if (zc != 0 && zc >= p.n[1]) continue;
+                    LaunchCfg c{ST_VARIANT_YM3D, 0, ty, 1, zc};
+                    if (cfg_legal(p, c)) out.push_back(c);
+                }
         // Matrix-core form of the fp16 27-point box (64 x 64 tiles).
         for (int zc : {16, 32, 64, 128, 0}) {
             if (zc != 0 && zc >= p.n[2]) continue;

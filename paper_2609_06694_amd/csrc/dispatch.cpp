@@ -124,6 +124,13 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.variant = ST_VARIANT_ZM3D;
         c.tile_y = k.dtype == 0 ? 32 : 16;
         c.zchunk = kAutoChunk;
+        // The 125-point box on a slab with few z planes marches y instead
+        // (a march of a few planes computes partial sums for 2R planes
+        // outside its chunk).
+        if (k.shape == kBox && k.r == 2 && k.slab == 1) {
+            c.variant = ST_VARIANT_YM3D;
+            c.tile_y = 8;
+        }
         return c;
     }
     if (k.size_class <= 1 && k.dtype != ST_F64) {   // (f64 in 2D: row march only)
@@ -163,6 +170,7 @@ LaunchCfg variant_default(const st_problem& p, int variant) {
         case ST_VARIANT_ZM3D: c.tile_y = 16; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_ZM3D_MFMA: c.tile_y = 64; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_ZM3D_H2: c.tile_y = 16; c.zchunk = kAutoChunk; break;
+        case ST_VARIANT_YM3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_YM2D_H2: c.tile_x = 256; c.tile_y = 0; c.tsteps = 2; break;
         case ST_VARIANT_WAVE3D: c.tile_y = 8; c.zchunk = kAutoChunk; break;
         case ST_VARIANT_WAVE3D_LDS: c.tile_y = 32; c.zchunk = kAutoChunk; break;
@@ -269,7 +277,12 @@ static int device_cus() {
 // Plane chunk for a z-march: split z so that the grid fills every CU about
 // once (one round of workgroups; a partial second round costs a whole
 // round's time), with chunks of at least 16 planes.
-int auto_zchunk(const st_problem& p, const LaunchCfg& c, int resident) {
+int auto_zchunk(const st_problem& p0, const LaunchCfg& c, int resident) {
+    st_problem p = p0;
+    if (c.variant == ST_VARIANT_YM3D) {   // chunks of the y march over (x, z) tiles
+        p.n[1] = p0.n[2];
+        p.n[2] = p0.n[1];
+    }
     const int rows = c.tile_y >= 64 ? 64 : (c.tile_y >= 32 ? 32 : (c.tile_y >= 16 ? 16 : 8));
     const int64_t tile_w = c.variant == ST_VARIANT_ZM3D_H2 ? 2 * kWave : kWave;   // H2: two cells per lane
     int64_t tiles = ((p.n[0] + tile_w - 1) / tile_w) * ((p.n[1] + rows - 1) / rows);
@@ -306,6 +319,13 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
         if (c.variant == ST_VARIANT_ZM3D_MFMA)
             return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 8 == 0 &&
                    c.tile_y == 64 && c.zchunk >= 0;
+        if (c.variant == ST_VARIANT_YM3D) {
+            const size_t esz = p.dtype == ST_F16 ? 2 : (p.dtype == ST_F64 ? 8 : 4);
+            return p.shape == ST_BOX && p.radius <= 2 &&
+                   (size_t)p.n[0] * p.n[1] * p.n[2] * esz <= 0xFFFFFFFFull &&
+                   (c.tile_y == 8 || c.tile_y == 16 || (c.tile_y == 32 && p.dtype != ST_F64)) && c.zchunk >= 0 &&
+                   c.tsteps >= 0 && c.tsteps <= 1;
+        }
         if (c.variant == ST_VARIANT_ZM3D_H2)
             return p.shape == ST_BOX && p.radius == 1 && p.dtype == ST_F16 && p.n[0] % 2 == 0 &&
                    (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1;

@@ -17,6 +17,10 @@ struct Geom {
     int nx, ny, nz;
     int shape, r, dtype, boundary;
     bool iso;   // star with one weight per distance on every arm and sign
+    // Element strides of the in-plane second axis and of the march axis for
+    // a march along y (0: the z-march's nx and nx * ny).
+    int sy = 0;
+    size_t sz = 0;
 };
 
 // Launch parameters chosen by the dispatch map.
@@ -110,6 +114,9 @@ hipError_t launch_zm3d_mfma(const Geom& g, const LaunchCfg& cfg, const Taps& tap
 bool zm3d_mfma_supported(const Geom& g);
 hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
                           hipStream_t stream);
+hipError_t launch_ym3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
+                       hipStream_t stream);
+bool ym3d_supported(const Geom& g);
 bool zm3d_h2_supported(const Geom& g);
 hipError_t launch_ym2d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out, int k,
                           hipStream_t stream);
@@ -131,6 +138,7 @@ inline hipError_t launch_linear3d(const Geom& g, const LaunchCfg& cfg, const Tap
     if (k == 2) return launch_zm3d_tb2(g, cfg, taps, in, out, stream);
     if (cfg.variant == 6) return launch_zm3d_mfma(g, cfg, taps, in, out, stream);
     if (cfg.variant == 8) return launch_zm3d_h2(g, cfg, taps, in, out, stream);
+    if (cfg.variant == 10) return launch_ym3d(g, cfg, taps, in, out, stream);
     return launch_zm3d(g, cfg, taps, in, out, stream);
 }
 hipError_t launch_wave3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps,

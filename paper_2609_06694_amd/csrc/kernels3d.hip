@@ -1,4 +1,12 @@
 // 3D linear sweep (star r = 1..4, box r = 1..2): plane-streaming z-march.
+//
+// The same kernel marches the y axis for slabs with few z planes (variant
+// ST_VARIANT_YM3D, boxes): the host passes the grid as (x, z, y) with the
+// strides of that order (in-plane second axis z: stride nx*ny; march axis
+// y: stride nx) and the weights with dz and dy exchanged.  A march of 8
+// planes re-reads 2R halo planes and computes partial sums for 2R output
+// planes outside its chunk; marching the long axis instead keeps both
+// below 2 % for a 4096 x 4096 x 8 slab.
 #include "internal.h"
 #include "zmarch.h"
 
@@ -12,7 +20,7 @@ template <int R, int SHAPE, typename T, int BC, int RY, int NW, int D>
 __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ in,
                                                           T* __restrict__ out, int nx, int ny,
                                                           int nz, int zc, int tiles_x, int tiles_y,
-                                                          Taps tp) {
+                                                          Taps tp, int sy, size_t sz) {
     using G = PlaneGeom<R, RY, NW>;
     using A = acc_t<T>;   // arithmetic type (f64 for f64 storage, else f32)
     __shared__ A tile[2][G::H * G::W];
@@ -54,10 +62,12 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
     // cache hit), keeping every load unconditional.
     T vin[D][RY], vhalo[D][G::HT];
     uint32_t vm[D];
-    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, T, NW>(nx, ny, x0, y0);
+    // Strides: sy of the in-plane second axis, sz of the march axis (0 for
+    // the z-march's nx and nx * ny).
+    const PlaneIdx<R, RY, NW> pidx = plane_index<R, RY, BC, T, NW>(nx, ny, x0, y0, sy);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d], sz);
 
     for (int zb = zbeg; zb < zend; zb += D) {
 #pragma unroll
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
             A cen[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) cen[i] = masked<BC>(vin[d][i], vm[d], i);
-            vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
+            vm[d] = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d], sz);
             __syncthreads();
 
             if constexpr (SHAPE == kStar) {
@@ -149,11 +159,12 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_kernel(const T* __restrict__ 
             // Output plane zp - R has received all 2R+1 planes.
             const int zo = zp - R;
             if (zo >= z0 && zo < z1 && gx < nx) {
-                T* o = out + (size_t)zo * nx * ny;
+                T* o = out + (size_t)zo * (sz ? sz : (size_t)nx * ny);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     const int gy = y0 + ty * RY + i;
-                    if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[0][i]), &o[(uint32_t)(gy * nx + gx)]);
+                    const uint32_t oi = sy > 0 ? (uint32_t)gy * (uint32_t)sy + (uint32_t)gx : (uint32_t)(gy * nx + gx);
+                    if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[0][i]), &o[oi]);
                 }
             }
 #pragma unroll
@@ -180,6 +191,7 @@ constexpr int zm3d_depth() {
     return RY >= 8 ? 1 : (RY >= 4 ? 2 : (R >= 3 ? 3 : 4));
 }
 
+// g.sy / g.sz: strides of a y-march view (0 for the z-march).
 template <int R, int SHAPE, typename T, int BC, int RY, int NW>
 static hipError_t go(const Geom& g, int zc, const Taps& tp, const void* in, void* out,
                      hipStream_t s) {
@@ -189,7 +201,7 @@ static hipError_t go(const Geom& g, int zc, const Taps& tp, const void* in, void
     constexpr int D = zm3d_depth<R, RY>();
     hipLaunchKernelGGL((zm3d_kernel<R, SHAPE, T, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks),
                        dim3(G::NT), 0, s, (const T*)in, (T*)out, g.nx, g.ny, g.nz, zc, tiles_x,
-                       tiles_y, tp);
+                       tiles_y, tp, g.sy, g.sz);
     return hipGetLastError();
 }
 
@@ -240,6 +252,31 @@ hipError_t launch_zm3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, co
     if (g.dtype == 0) return go_t<float>(g, cfg, taps, in, out, stream);
     if (g.dtype == 2) return go_t<double>(g, cfg, taps, in, out, stream);
     return go_t<_Float16>(g, cfg, taps, in, out, stream);
+}
+
+bool ym3d_supported(const Geom& g) {
+    const size_t esz = g.dtype == 1 ? 2 : (g.dtype == 2 ? 8 : 4);
+    return g.ndim == 3 && g.shape == kBox && (g.r == 1 || g.r == 2) &&
+           (size_t)g.nx * g.ny * g.nz * esz <= 0xFFFFFFFFull;
+}
+
+// The march along y: the z-march kernel on the (x, z, y) view of the grid,
+// with the weights' dz and dy exchanged.  cfg.tile_y: z rows per workgroup;
+// cfg.zchunk: y rows per march chunk.
+hipError_t launch_ym3d(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
+                       hipStream_t stream) {
+    if (!ym3d_supported(g)) return hipErrorInvalidValue;
+    Geom v = g;
+    v.ny = g.nz;
+    v.nz = g.ny;
+    v.sy = g.nx * g.ny;
+    v.sz = (size_t)g.nx;
+    Taps t = taps;
+    const int w = 2 * g.r + 1;
+    for (int a = 0; a < w; ++a)        // dz + r
+        for (int b = 0; b < w; ++b)    // dy + r
+            for (int c = 0; c < w; ++c) t.c[(b * w + a) * w + c] = taps.c[(a * w + b) * w + c];
+    return launch_zm3d(v, cfg, t, in, out, stream);
 }
 
 }  // namespace stk

@@ -192,6 +192,9 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
     if (pl->cfg.zchunk == kAutoChunk) pl->cfg.zchunk = auto_zchunk(*p, pl->cfg);
     if (!cfg_legal(pl->prob, pl->cfg)) {   // a stale map entry falls back to the default
         LaunchCfg d = default_dispatch(classify(*p));
+        // (the y-march default of a few-plane slab needs the grid under 4 GiB)
+        if (!cfg_legal(pl->prob, d) && p->ndim == 3 && p->update == ST_LINEAR)
+            d = variant_default(*p, ST_VARIANT_ZM3D);
         if (d.zchunk == kAutoChunk) d.zchunk = auto_zchunk(*p, d);
         pl->cfg = d;
     }

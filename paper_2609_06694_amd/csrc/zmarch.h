@@ -141,8 +141,9 @@ struct PlaneIdx {
     uint32_t mxy;
 };
 
+// sy: element stride of the in-plane second axis (0: nx, a z-march plane).
 template <int R, int RY, int BC, typename T, int NW = 4>
-__device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x0, int y0) {
+__device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x0, int y0, int sy = 0) {
     using G = PlaneGeom<R, RY, NW>;
     static_assert(RY + G::HT <= 32, "validity mask holds 32 cells");
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
@@ -152,7 +153,8 @@ __device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x
     for (int i = 0; i < RY; ++i) {
         int gx = x0 + tx, gy = y0 + ty * RY + i;
         const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
-        pi.off[i] = (uint32_t)(gy * nx + gx) * (uint32_t)sizeof(T);
+        pi.off[i] = (sy > 0 ? (uint32_t)gy * (uint32_t)sy + (uint32_t)gx : (uint32_t)(gy * nx + gx)) *
+                    (uint32_t)sizeof(T);
         pi.mxy |= (uint32_t)(okx && oky) << i;
     }
 #pragma unroll
@@ -163,7 +165,8 @@ __device__ __forceinline__ PlaneIdx<R, RY, NW> plane_index(int nx, int ny, int x
         halo_coord<R, RY, NW>(hv ? h : 0, ly, lx);
         int gx = x0 - R + lx, gy = y0 - R + ly;
         const bool okx = fix_coord<BC>(gx, nx), oky = fix_coord<BC>(gy, ny);
-        pi.off[RY + j] = (uint32_t)(gy * nx + gx) * (uint32_t)sizeof(T);
+        pi.off[RY + j] = (sy > 0 ? (uint32_t)gy * (uint32_t)sy + (uint32_t)gx : (uint32_t)(gy * nx + gx)) *
+                         (uint32_t)sizeof(T);
         pi.mxy |= (uint32_t)(hv && okx && oky) << (RY + j);
     }
     return pi;
@@ -187,15 +190,16 @@ __device__ __forceinline__ T load_at_nt(const char* base, uint32_t off) {
     return __builtin_nontemporal_load(reinterpret_cast<const T*>(base + off));
 }
 
-// load_plane with the in-plane addressing taken from plane_index.
+// load_plane with the in-plane addressing taken from plane_index; plane zp
+// starts zp * sz elements into f (sz = 0: nx * ny, a z-march plane).
 template <int R, int RY, int BC, typename T, int NW = 4, bool PIN = true>
 __device__ __forceinline__ uint32_t load_plane_at(const T* __restrict__ f, int nx, int ny, int nz, int zp,
                                                   const PlaneIdx<R, RY, NW>& pi, T (&in)[RY],
-                                                  T (&halo)[PlaneGeom<R, RY, NW>::HT]) {
+                                                  T (&halo)[PlaneGeom<R, RY, NW>::HT], size_t sz = 0) {
     using G = PlaneGeom<R, RY, NW>;
     int gz = zp;
     const bool zin = fix_coord<BC>(gz, nz);
-    const char* plane = reinterpret_cast<const char*>(f + (size_t)gz * nx * ny);
+    const char* plane = reinterpret_cast<const char*>(f + (size_t)gz * (sz ? sz : (size_t)nx * ny));
 #pragma unroll
     for (int i = 0; i < RY; ++i) in[i] = load_at<T, PIN>(plane, pi.off[i]);
 #pragma unroll

@@ -47,6 +47,12 @@ def main(out: str) -> None:
             plans.append((f"star3d {m}^3 {dt}", st.Stencil((m, m, m), "star", 1, c.coeffs, dtype=dt)))
             c = wl.box3d(n=16, dtype=wl.F32)
             plans.append((f"box3d {m}^3 {dt}", st.Stencil((m, m, m), "box", 1, c.coeffs, dtype=dt)))
+    # The 125-point box on small cubes and on slabs (the march along y and
+    # the whole-block kernel are candidates there).
+    for dt in ("f16", "f32"):
+        c = wl.box3d_r2(n=16, dtype=wl.F16 if dt == "f16" else wl.F32)
+        for shp in ((128, 128, 128), (256, 256, 256), (4096, 4096, 8), (4096, 64, 512), (64, 64, 32768)):
+            plans.append((f"box3d r2 {shp} {dt}", st.Stencil(shp, "box", 2, c.coeffs, dtype=dt)))
     plans.append(("varcoef star1 512^3 f32", st.VarCoefStencil((512, 512, 512), "star", 1)))
     plans.append(("varcoef box1 512^3 f32", st.VarCoefStencil((512, 512, 512), "box", 1)))
     plans.append(("wave 512^3", st.WaveModel((512, 512, 512))))

@@ -454,3 +454,23 @@ def test_batched_schedule_tables_check_out(tsteps):
         assert bs.schedule(32, 256)["tables"] > 1
     with pytest.raises(_abi.StencilError):
         bs.schedule(0, 256)
+
+
+def test_box_slab_dispatch_marches_y_within_4gib():
+    """A 125-point box on a slab with few z planes dispatches the march along
+    y by default; a slab whose whole grid exceeds 4 GiB (the y march
+    addresses x-z planes with 32-bit offsets) falls back to the z-march; an
+    explicit y march is refused there and for stars."""
+    from paper_2609_06694_amd import stencil as st
+    c = wl.random_unit_sum_coeffs(np.random.default_rng(3), 3, wl.BOX, 2)
+    assert st.Stencil((4096, 4096, 8), "box", 2, c).describe()["variant"] == "ym3d"
+    assert st.Stencil((512, 512, 512), "box", 2, c).describe()["variant"] == "zm3d"
+    assert st.Stencil((32768, 8192, 8), "box", 2, c).describe()["variant"] == "zm3d"
+    with pytest.raises(_abi.StencilError):
+        st.Stencil((32768, 8192, 8), "box", 2, c, variant=10)
+    cs = wl.random_unit_sum_coeffs(np.random.default_rng(4), 3, wl.STAR, 1)
+    with pytest.raises(_abi.StencilError):
+        st.Stencil((300, 200, 9), "star", 1, cs, variant=10)
+    c1 = wl.random_unit_sum_coeffs(np.random.default_rng(5), 3, wl.BOX, 1)
+    d = st.Stencil((300, 200, 9), "box", 1, c1, variant=10, tile_y=16, zchunk=32).describe()
+    assert d["variant"] == "ym3d" and d["tile_y"] == 16 and d["zchunk"] == 32

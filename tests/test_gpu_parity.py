@@ -141,6 +141,40 @@ def test_3d_sweep_vs_oracle(st, shape, r, dtype, bc):
         assert e <= TOL[dtype], (nx, ny, nz, ty, zc, steps, e)
 
 
+@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "f64"])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_3d_box_y_march_vs_oracle(st, r, dtype, bc):
+    """The march along y (variant ym3d, the few-plane slab structure of the
+    boxes): ragged x, few z planes (fewer than a tile's rows, fewer than
+    2r+1), y chunks with a ragged tail, grids smaller than 2r+1 in every
+    axis; forward, in place and transpose against the oracle, and equal to
+    the z-march up to rounding order."""
+    rng = np.random.default_rng(7100 + 10 * r + {"f32": 0, "f16": 1, "f64": 2}[dtype])
+    npdt = {"f32": np.float32, "f16": np.float16, "f64": np.float64}[dtype]
+    c = wl.random_unit_sum_coeffs(rng, 3, wl.BOX, r)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    tys = (8, 16) if dtype == "f64" else (8, 16, 32)
+    for (nx, ny, nz), zc, steps in [((300, 90, 8), 32, 2), ((70, 130, 3), 0, 3), ((129, 64, 17), 16, 1),
+                                    ((6, 5, 4), 0, 2), ((64, 41, 1), 16, 2)]:
+        ty = tys[(nx + nz) % len(tys)]
+        u = wl.small_random_grid(rng, 3, (nx, ny, nz), npdt, 0.0, 1.0)
+        s = st.Stencil((nx, ny, nz), "box", r, c, dtype=dtype, boundary=bc, variant=10, tile_y=ty, zchunk=zc)
+        assert s.describe()["variant"] == "ym3d"
+        ref = oracle.sweep(u, c, wl.BOX, r, bcode, steps)
+        got = _host(s.apply(_dev(u), steps)).astype(np.float64)
+        e = rel_l2(got, ref)
+        assert e <= TOL[dtype], (nx, ny, nz, ty, zc, steps, e)
+        du = _dev(u)
+        s.apply(du, steps, out=du)   # in place
+        assert rel_l2(_host(du).astype(np.float64), ref) <= TOL[dtype]
+        zm = st.Stencil((nx, ny, nz), "box", r, c, dtype=dtype, boundary=bc, variant=2, tile_y=8)
+        assert rel_l2(got, _host(zm.apply(_dev(u), steps)).astype(np.float64)) <= TOL[dtype]
+        v = wl.small_random_grid(rng, 3, (nx, ny, nz), npdt, 0.0, 1.0)
+        gotT = _host(s.apply_adjoint(_dev(v), steps)).astype(np.float64)
+        assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, r, bcode, steps, adjoint=True)) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("shape,r", CASES_3D)
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
 def test_3d_f64_vs_oracle(st, shape, r, bc):
