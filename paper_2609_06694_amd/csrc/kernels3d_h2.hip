@@ -19,11 +19,22 @@
 // taps that leave the grid read zero rather than the centre value, so there
 // the residual sum runs over the taps inside the grid only.
 //
+// Radius 2 (the 125-point box) uses the same pairs: for a row of weights
+// w_-2..w_2,
+//   out(x)   += dot2((u_x-2, u_x-1), (w_-2, w_-1)) + dot2((u_x, u_x+1), (w_0, w_1)) + w_2 u_x+2
+//   out(x+1) += w_-2 u_x-1 + dot2((u_x, u_x+1), (w_-1, w_0)) + dot2((u_x+2, u_x+3), (w_1, w_2)),
+// six instructions for ten multiply-adds; its 25 weight rows (six words
+// each) are read per row through the scalar cache, five rows at a time.
+//
 // Layout and march follow the z-march of zmarch.h: a workgroup owns a
 // column of 128 x BY cells, stages every plane once (with a one-pair halo
 // in x and an R-row halo in y) and adds the plane's contributions to the
 // 2R+1 output planes it touches into a register queue of partial sums.
 // Requires an even nx (whole pairs in every row).
+#include <string.h>
+
+#include <type_traits>
+
 #include "internal.h"
 #include "zmarch.h"
 
@@ -42,16 +53,29 @@ struct H2Taps {
     float rr[27];
 };
 
-// Sum of the residuals rr (27, in LDS) of the taps of cell (cx, cy, cz)
+// Radius 2: per (dz, dy) row k = (dz+2)*5 + (dy+2), words [8k .. 8k+5] of
+// `row` hold (w_-2, w_-1), (w_0, w_1), (w_-1, w_0), (w_1, w_2) as binary16
+// pairs and w_2, w_-2 as f32 bit patterns; rr holds the 125 residuals in
+// (dz, dy, dx) order.  A kernel argument (1.3 KB), read per row through
+// the scalar cache.
+struct H2Taps5 {
+    uint32_t row[25 * 8];
+    float rr[125];
+    float res;
+};
+
+// Sum of the residuals rr ((2R+1)^3, in LDS) of the taps of cell (cx, cy, cz)
 // that land inside an nx x ny x nz grid (with all_z, every plane counts as
 // inside).  A rolled loop: it runs once per thread and on the two face
 // planes only.
+template <int R = 1>
 __device__ __forceinline__ float h2_inner_res(const float* rr, int cx, int cy, int cz, int nx, int ny, int nz,
                                               bool all_z) {
+    constexpr int Q = 2 * R + 1;
     float r = 0.f;
 #pragma unroll 1
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    for (int t = 0; t < Q * Q * Q; ++t) {
+        const int dz = t / (Q * Q) - R, dy = (t / Q) % Q - R, dx = t % Q - R;
         const bool in = (all_z || (unsigned)(cz + dz) < (unsigned)nz) && (unsigned)(cy + dy) < (unsigned)ny &&
                         (unsigned)(cx + dx) < (unsigned)nx;
         r += in ? rr[t] : 0.f;
@@ -59,26 +83,31 @@ __device__ __forceinline__ float h2_inner_res(const float* rr, int cx, int cy, i
     return r;
 }
 
-template <int RY, int NW>
+template <int RY, int NW, int R = 1>
 struct H2Geom {
     static constexpr int NT = NW * kWave;
     static constexpr int BXP = kWave;          // pairs per tile row
     static constexpr int BY = NW * RY;
-    static constexpr int WP = BXP + 2;         // one halo pair on each side
-    static constexpr int H = BY + 2;           // one halo row above and below (radius 1)
+    static constexpr int WP = BXP + 2;         // one halo pair on each side (R <= 2 cells)
+    static constexpr int H = BY + 2 * R;       // R halo rows above and below
     static constexpr int NH = WP * H - BXP * BY;
     static constexpr int HT = (NH + NT - 1) / NT;
 };
 
 __device__ __forceinline__ half2_t as_h2(uint32_t v) { return __builtin_bit_cast(half2_t, v); }
 
-template <int BC, int RY, int NW, int D>
+template <int R>
+using H2TapsOf = std::conditional_t<R == 1, H2Taps, H2Taps5>;
+
+template <int R, int BC, int RY, int NW, int D>
 __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out, int nxp, int ny,
                                                              int nz, int zc, int tiles_x, int tiles_y,
-                                                             H2Taps tp) {
-    using G = H2Geom<RY, NW>;
+                                                             H2TapsOf<R> tp) {
+    using G = H2Geom<RY, NW, R>;
+    constexpr int Q = 2 * R + 1;
     __shared__ uint32_t tile[2][G::H * G::WP];
+
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int txi = b % tiles_x;
     const int rest = b / tiles_x;
@@ -87,7 +116,7 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
     const int z0 = zci * zc, z1 = min(z0 + zc, nz);
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const int gx = x0 + tx;
-    const int zbeg = z0 - 1, zend = z1 + 1;
+    const int zbeg = z0 - R, zend = z1 + R;
 
     // In-plane addressing (pair offsets after the boundary rule) and x/y
     // validity, the same for every plane.
@@ -106,15 +135,16 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
         const bool hv = h < G::NH;
         const int hh = hv ? h : 0;
         int ly, lx;
-        if (hh < 2 * G::WP) {   // top row, then bottom row
-            ly = hh < G::WP ? 0 : G::H - 1;
-            lx = hh < G::WP ? hh : hh - G::WP;
-        } else {                // side pairs of the interior rows
-            const int q = hh - 2 * G::WP;
-            ly = 1 + (q >> 1);
+        if (hh < 2 * R * G::WP) {   // the R top rows, then the R bottom rows
+            const int row = hh / G::WP;
+            ly = row < R ? row : G::BY + row;
+            lx = hh - row * G::WP;
+        } else {                    // side pairs of the interior rows
+            const int q = hh - 2 * R * G::WP;
+            ly = R + (q >> 1);
             lx = (q & 1) ? G::WP - 1 : 0;
         }
-        int px = x0 - 1 + lx, py = y0 - 1 + ly;
+        int px = x0 - 1 + lx, py = y0 - R + ly;
         const bool okx = fix_coord<BC>(px, nxp), oky = fix_coord<BC>(py, ny);
         off[RY + j] = (uint32_t)(py * nxp + px) * 4u;
         mxy |= (uint32_t)(hv && okx && oky) << (RY + j);
@@ -123,22 +153,22 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
     // Zero frame: residual sums over the in-grid taps of each cell of the
     // thread's pairs, for planes away from the z faces (the face planes
     // recompute theirs).
-    __shared__ float rrs[27];
+    __shared__ float rrs[Q * Q * Q];
     float ria[RY], rib[RY];
     if constexpr (BC == kZero) {
-        if (threadIdx.x < 27) rrs[threadIdx.x] = tp.rr[threadIdx.x];
+        for (int i = threadIdx.x; i < Q * Q * Q; i += G::NT) rrs[i] = tp.rr[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             const int cy = y0 + ty * RY + i;
-            ria[i] = h2_inner_res(rrs, 2 * gx, cy, 0, 2 * nxp, ny, nz, true);
-            rib[i] = h2_inner_res(rrs, 2 * gx + 1, cy, 0, 2 * nxp, ny, nz, true);
+            ria[i] = h2_inner_res<R>(rrs, 2 * gx, cy, 0, 2 * nxp, ny, nz, true);
+            rib[i] = h2_inner_res<R>(rrs, 2 * gx + 1, cy, 0, 2 * nxp, ny, nz, true);
         }
     }
 
-    float ax[3][RY], ay[3][RY];   // partial sums of output planes zp-1, zp, zp+1 (cells x, x+1)
+    float ax[Q][RY], ay[Q][RY];   // partial sums of output planes zp-R .. zp+R (cells x, x+1)
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int i = 0; i < RY; ++i) ax[q][i] = ay[q][i] = 0.f;
 
@@ -165,19 +195,20 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
                 const uint32_t v = BC == kPeriodic || ((vm[d] >> i) & 1u) ? vin[d][i] : 0u;
-                t[(1 + ty * RY + i) * G::WP + 1 + tx] = v;
+                t[(R + ty * RY + i) * G::WP + 1 + tx] = v;
             }
 #pragma unroll
             for (int j = 0; j < G::HT; ++j) {
                 const int h = threadIdx.x + j * G::NT;
                 if (h < G::NH) {
                     int ly, lx;
-                    if (h < 2 * G::WP) {
-                        ly = h < G::WP ? 0 : G::H - 1;
-                        lx = h < G::WP ? h : h - G::WP;
+                    if (h < 2 * R * G::WP) {
+                        const int row = h / G::WP;
+                        ly = row < R ? row : G::BY + row;
+                        lx = h - row * G::WP;
                     } else {
-                        const int q = h - 2 * G::WP;
-                        ly = 1 + (q >> 1);
+                        const int q = h - 2 * R * G::WP;
+                        ly = R + (q >> 1);
                         lx = (q & 1) ? G::WP - 1 : 0;
                     }
                     const uint32_t v = BC == kPeriodic || ((vm[d] >> (RY + j)) & 1u) ? vin[d][RY + j] : 0u;
@@ -187,57 +218,99 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
             load(d, zp + D);
             __syncthreads();
 
-            // Rows -1 .. RY of this thread's column of pairs: the pair to
-            // the left, its own pair and the pair to the right.
-            uint32_t pm[RY + 2], p0[RY + 2], pp[RY + 2];
-            const uint32_t* rb = t + (ty * RY) * G::WP + tx;
+            // Rows -R .. RY-1+R of this thread's column of pairs: the pair
+            // to the left, its own pair and the pair to the right.
+            const uint32_t* cp = t + (ty * RY) * G::WP + tx;
+            if constexpr (R == 1) {
+                uint32_t pm[RY + 2], p0[RY + 2], pp[RY + 2];
 #pragma unroll
-            for (int j = 0; j < RY + 2; ++j) {
-                pm[j] = rb[j * G::WP];
-                p0[j] = rb[j * G::WP + 1];
-                pp[j] = rb[j * G::WP + 2];
-            }
-            // Plane zp feeds output plane zp - dz with the weights of dz.
+                for (int j = 0; j < RY + 2; ++j) {
+                    pm[j] = cp[j * G::WP];
+                    p0[j] = cp[j * G::WP + 1];
+                    pp[j] = cp[j * G::WP + 2];
+                }
+                // Plane zp feeds output plane zp - dz with the weights of dz.
 #pragma unroll
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int q = 1 - dz;
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int q = 1 - dz;
 #pragma unroll
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int k = (dz + 1) * 3 + (dy + 1);
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int k = (dz + 1) * 3 + (dy + 1);
+#pragma unroll
+                        for (int i = 0; i < RY; ++i) {
+                            const int j = i + 1 + dy;
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.p01[k]), ax[q][i], false);
+                            ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.pm0[k]), ay[q][i], false);
+                            ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
+                        }
+                    }
+                }
+            } else {
+                // Radius 2: a rolled loop over dy (five weight rows and the
+                // thread's RY rows at offset dy live at a time; unrolled, the
+                // compiler would load all 25 weight rows, 150 registers, at
+                // once), the dz groups unrolled so each sum stays in its
+                // register.
+#pragma unroll 1
+                for (int dy = -R; dy <= R; ++dy) {
+                    uint32_t pm[RY], p0[RY], pp[RY];
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
-                        const int j = i + 1 + dy;
-                        ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.p01[k]), ax[q][i], false);
-                        ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
-                        ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.pm0[k]), ay[q][i], false);
-                        ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
+                        const uint32_t* r = cp + (i + R + dy) * G::WP;
+                        pm[i] = r[0];
+                        p0[i] = r[1];
+                        pp[i] = r[2];
+                    }
+#pragma unroll
+                    for (int dz = -R; dz <= R; ++dz) {
+                        const int q = R - dz;
+                        const int k = (dz + R) * Q + (dy + R);
+                        // (w_-2, w_-1), (w_0, w_1), (w_-1, w_0), (w_1, w_2), w_2, w_-2
+                        // (scalar loads from the arguments: uniform, no LDS traffic)
+                        const uint4 wa = {tp.row[8 * k], tp.row[8 * k + 1], tp.row[8 * k + 2], tp.row[8 * k + 3]};
+                        const float fa = __uint_as_float(tp.row[8 * k + 4]);
+                        const float fb = __uint_as_float(tp.row[8 * k + 5]);
+#pragma unroll
+                        for (int i = 0; i < RY; ++i) {
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(pm[i]), as_h2(wa.x), ax[q][i], false);
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[i]), as_h2(wa.y), ax[q][i], false);
+                            ax[q][i] = fmaf(fa, (float)as_h2(pp[i]).x, ax[q][i]);
+                            ay[q][i] = fmaf(fb, (float)as_h2(pm[i]).y, ay[q][i]);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[i]), as_h2(wa.z), ay[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(pp[i]), as_h2(wa.w), ay[q][i], false);
+                        }
                     }
                 }
             }
+            // The centre pairs of the thread's rows (for the residual term).
+            uint32_t pc[RY];
+#pragma unroll
+            for (int i = 0; i < RY; ++i) pc[i] = cp[(i + R) * G::WP + 1];
             // The weight residuals, applied to the centre value.
             if constexpr (BC == kPeriodic) {
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    ax[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).x, ax[1][i]);
-                    ay[1][i] = fmaf(tp.res, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+                    ax[R][i] = fmaf(tp.res, (float)as_h2(pc[i]).x, ax[R][i]);
+                    ay[R][i] = fmaf(tp.res, (float)as_h2(pc[i]).y, ay[R][i]);
                 }
             } else {
-                const bool zface = zp < 1 || zp > nz - 2;   // uniform over the workgroup
+                const bool zface = zp < R || zp > nz - 1 - R;   // uniform over the workgroup
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     float ra = ria[i], rb = rib[i];
                     if (zface) {
                         const int cy = y0 + ty * RY + i;
-                        ra = h2_inner_res(rrs, 2 * gx, cy, zp, 2 * nxp, ny, nz, false);
-                        rb = h2_inner_res(rrs, 2 * gx + 1, cy, zp, 2 * nxp, ny, nz, false);
+                        ra = h2_inner_res<R>(rrs, 2 * gx, cy, zp, 2 * nxp, ny, nz, false);
+                        rb = h2_inner_res<R>(rrs, 2 * gx + 1, cy, zp, 2 * nxp, ny, nz, false);
                     }
-                    ax[1][i] = fmaf(ra, (float)as_h2(p0[i + 1]).x, ax[1][i]);
-                    ay[1][i] = fmaf(rb, (float)as_h2(p0[i + 1]).y, ay[1][i]);
+                    ax[R][i] = fmaf(ra, (float)as_h2(pc[i]).x, ax[R][i]);
+                    ay[R][i] = fmaf(rb, (float)as_h2(pc[i]).y, ay[R][i]);
                 }
             }
 
-            // Output plane zp - 1 has received all three planes.
-            const int zo = zp - 1;
+            // Output plane zp - R has received all 2R + 1 planes.
+            const int zo = zp - R;
             if (zo >= z0 && zo < z1 && gx < nxp) {
                 char* o = reinterpret_cast<char*>(out + (size_t)zo * plane_sz);
 #pragma unroll
@@ -253,20 +326,23 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                 }
             }
 #pragma unroll
+            for (int q = 0; q < Q - 1; ++q)
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    ax[q][i] = ax[q + 1][i];
+                    ay[q][i] = ay[q + 1][i];
+                }
+#pragma unroll
             for (int i = 0; i < RY; ++i) {
-                ax[0][i] = ax[1][i];
-                ay[0][i] = ay[1][i];
-                ax[1][i] = ax[2][i];
-                ay[1][i] = ay[2][i];
-                ax[2][i] = 0.f;
-                ay[2][i] = 0.f;
+                ax[Q - 1][i] = 0.f;
+                ay[Q - 1][i] = 0.f;
             }
         }
     }
 }
 
 bool zm3d_h2_supported(const Geom& g) {
-    return g.ndim == 3 && g.shape == kBox && g.r == 1 && g.dtype == 1 && g.nx % 2 == 0;
+    return g.ndim == 3 && g.shape == kBox && (g.r == 1 || g.r == 2) && g.dtype == 1 && g.nx % 2 == 0;
 }
 
 // Host-side weight preparation (dense (dz,dy,dx) box weights, f32).
@@ -295,33 +371,73 @@ static H2Taps pack_h2(const Taps& t) {
     return h;
 }
 
-template <int BC, int RY, int NW>
-static hipError_t go(const Geom& g, int zc, const H2Taps& tp, const void* in, void* out, hipStream_t s) {
-    using G = H2Geom<RY, NW>;
+// Radius 2: the 25 weight rows as binary16 pairs plus the two end weights,
+// and the residuals (dense (dz,dy,dx) box weights, f32).
+static H2Taps5 pack_h2_r2(const Taps& t) {
+    H2Taps5 h;
+    memset(&h, 0, sizeof h);
+    double res = 0.0;
+    auto pk = [](_Float16 a, _Float16 b) {
+        half2_t v;
+        v.x = a;
+        v.y = b;
+        return __builtin_bit_cast(uint32_t, v);
+    };
+    for (int k = 0; k < 25; ++k) {
+        _Float16 c[5];
+        for (int dx = 0; dx < 5; ++dx) {
+            const float w = t.c[k * 5 + dx];
+            c[dx] = (_Float16)w;
+            const double r = (double)w - (double)(float)c[dx];
+            h.rr[k * 5 + dx] = (float)r;
+            res += r;
+        }
+        h.row[8 * k + 0] = pk(c[0], c[1]);
+        h.row[8 * k + 1] = pk(c[2], c[3]);
+        h.row[8 * k + 2] = pk(c[1], c[2]);
+        h.row[8 * k + 3] = pk(c[3], c[4]);
+        const float fa = (float)c[4], fb = (float)c[0];
+        memcpy(&h.row[8 * k + 4], &fa, 4);
+        memcpy(&h.row[8 * k + 5], &fb, 4);
+    }
+    h.res = (float)res;
+    return h;
+}
+
+template <int R, int BC, int RY, int NW>
+static hipError_t go(const Geom& g, int zc, const H2TapsOf<R>& tp, const void* in, void* out, hipStream_t s) {
+    using G = H2Geom<RY, NW, R>;
     const int nxp = g.nx / 2;
     const int tiles_x = (nxp + G::BXP - 1) / G::BXP, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = 2;
-    hipLaunchKernelGGL((zm3d_h2_kernel<BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks), dim3(G::NT), 0, s,
+    hipLaunchKernelGGL((zm3d_h2_kernel<R, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks), dim3(G::NT), 0, s,
                        (const uint32_t*)in, (uint32_t*)out, nxp, g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     return hipGetLastError();
+}
+
+template <int R, int BC>
+static hipError_t go_rows(const Geom& g, int rows, int zc, const H2TapsOf<R>& tp, const void* in, void* out,
+                          hipStream_t s) {
+    if (rows == 8) return go<R, BC, 2, 4>(g, zc, tp, in, out, s);
+    if (rows == 16) return go<R, BC, 4, 4>(g, zc, tp, in, out, s);
+    return go<R, BC, 8, 4>(g, zc, tp, in, out, s);
 }
 
 // tile_y: 8, 16 or 32 rows per workgroup (4 waves of 2, 4 or 8 rows).
 hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps, const void* in, void* out,
                           hipStream_t s) {
     if (!zm3d_h2_supported(g)) return hipErrorInvalidValue;
-    const H2Taps tp = pack_h2(taps);
     const int zc = cfg.zchunk > 0 ? cfg.zchunk : g.nz;
     const int rows = cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8);
-    if (g.boundary == kPeriodic) {
-        if (rows == 8) return go<kPeriodic, 2, 4>(g, zc, tp, in, out, s);
-        if (rows == 16) return go<kPeriodic, 4, 4>(g, zc, tp, in, out, s);
-        return go<kPeriodic, 8, 4>(g, zc, tp, in, out, s);
+    if (g.r == 2) {
+        const H2Taps5 tp = pack_h2_r2(taps);
+        return g.boundary == kPeriodic ? go_rows<2, kPeriodic>(g, rows, zc, tp, in, out, s)
+                                       : go_rows<2, kZero>(g, rows, zc, tp, in, out, s);
     }
-    if (rows == 8) return go<kZero, 2, 4>(g, zc, tp, in, out, s);
-    if (rows == 16) return go<kZero, 4, 4>(g, zc, tp, in, out, s);
-    return go<kZero, 8, 4>(g, zc, tp, in, out, s);
+    const H2Taps tp = pack_h2(taps);
+    return g.boundary == kPeriodic ? go_rows<1, kPeriodic>(g, rows, zc, tp, in, out, s)
+                                   : go_rows<1, kZero>(g, rows, zc, tp, in, out, s);
 }
 
 }  // namespace stk

@@ -382,7 +382,7 @@ def test_sponge_argument_checks_before_device(L):
 
 
 def test_packed_half_variant_needs_even_fp16_box(L):
-    """The packed-half 27-point box kernel takes fp16 boxes of radius 1 with
+    """The packed-half 3D box kernel takes fp16 boxes of radius 1 or 2 with
     an even nx only; other cases reject it as a plan option."""
     ok, keep = _prob(ndim=3, n=(64, 20, 10), shape=1, r=1, dtype=1)
     st, h = _plan(L, ok, _abi.StPlanOpts(_abi.ST_VARIANT_ZM3D_H2, 0, 16, 0, 0, 0))
@@ -391,7 +391,12 @@ def test_packed_half_variant_needs_even_fp16_box(L):
     L.stencil_plan_describe(h, ctypes.byref(v), None, None, None, None)
     assert v.value == _abi.ST_VARIANT_ZM3D_H2
     L.stencil_plan_destroy(h)
-    for kw in (dict(n=(63, 20, 10), dtype=1), dict(n=(64, 20, 10), dtype=0), dict(n=(64, 20, 10), dtype=1, r=2)):
+    r2, keep3 = _prob(ndim=3, n=(64, 20, 10), shape=1, r=2, dtype=1)
+    st, h = _plan(L, r2, _abi.StPlanOpts(_abi.ST_VARIANT_ZM3D_H2, 0, 16, 0, 0, 0))
+    assert st == _abi.ST_OK
+    L.stencil_plan_destroy(h)
+    assert _plan(L, r2, _abi.StPlanOpts(_abi.ST_VARIANT_ZM3D_H2, 0, 12, 0, 0, 0))[0] == _abi.ST_EINVAL
+    for kw in (dict(n=(63, 20, 10), dtype=1), dict(n=(64, 20, 10), dtype=0), dict(n=(64, 20, 10), dtype=2, r=2)):
         p, keep2 = _prob(ndim=3, shape=1, **dict(dict(r=1), **kw))
         assert _plan(L, p, _abi.StPlanOpts(_abi.ST_VARIANT_ZM3D_H2, 0, 16, 0, 0, 0))[0] == _abi.ST_EINVAL, kw
 

@@ -411,29 +411,30 @@ def test_3d_box_fp16_mfma_vs_oracle(st, bc):
 
 
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
-@pytest.mark.parametrize("ty", [8, 16, 32])
-def test_3d_box_fp16_packed_half_vs_oracle(st, bc, ty):
-    """Packed-half 27-point box (fp16 storage, two cells per lane, binary16
-    weights with the residual sum on the centre): several tiles with ragged
-    x (even), y and z tails, grids smaller than a tile, plane chunks, nx not
-    a multiple of 4, nx = 2; forward and transpose against the oracle at the
-    fp16 gate and within 5x of the binary16 storage floor."""
-    rng = np.random.default_rng(5150 + ty)
+@pytest.mark.parametrize("r,ty", [(1, 8), (1, 16), (1, 32), (2, 8), (2, 16), (2, 32)])
+def test_3d_box_fp16_packed_half_vs_oracle(st, bc, r, ty):
+    """Packed-half 27- and 125-point boxes (fp16 storage, two cells per
+    lane, binary16 weights with the residual sum on the centre): several
+    tiles with ragged x (even), y and z tails, grids smaller than a tile and
+    than 2r+1, plane chunks, nx not a multiple of 4, nx = 2; forward and
+    transpose against the oracle at the fp16 gate and within 5x of the
+    binary16 storage floor."""
+    rng = np.random.default_rng(5150 + ty + 100 * r)
     bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
     for (nx, ny, nz), zc, steps in [((256, 40, 20), 0, 3), ((202, 70, 33), 5, 4), ((10, 5, 7), 0, 3),
                                     ((130, 33, 18), 8, 5), ((2, 3, 4), 0, 2), ((386, 17, 9), 0, 6)]:
-        c = wl.random_unit_sum_coeffs(rng, 3, wl.BOX, 1)
+        c = wl.random_unit_sum_coeffs(rng, 3, wl.BOX, r)
         u = wl.small_random_grid(rng, 3, (nx, ny, nz), np.float16, 0.0, 1.0)
-        s = st.Stencil((nx, ny, nz), "box", 1, c, dtype="f16", boundary=bc, variant=8, tile_y=ty, zchunk=zc)
+        s = st.Stencil((nx, ny, nz), "box", r, c, dtype="f16", boundary=bc, variant=8, tile_y=ty, zchunk=zc)
         assert s.describe()["variant"] == "zm3d_h2"
         got = _host(s.apply(_dev(u), steps)).astype(np.float64)
-        ref = oracle.sweep(u, c, wl.BOX, 1, bcode, steps)
-        floor = rel_l2(oracle.sweep(u, c, wl.BOX, 1, bcode, steps, storage="binary16"), ref)
+        ref = oracle.sweep(u, c, wl.BOX, r, bcode, steps)
+        floor = rel_l2(oracle.sweep(u, c, wl.BOX, r, bcode, steps, storage="binary16"), ref)
         e = rel_l2(got, ref)
         assert e <= TOL["f16"] and e <= 5 * floor, (nx, ny, nz, zc, e, floor)
         v = wl.small_random_grid(rng, 3, (nx, ny, nz), np.float16, 0.0, 1.0)
         gotT = _host(s.apply_adjoint(_dev(v), steps)).astype(np.float64)
-        assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, 1, bcode, steps, adjoint=True)) <= TOL["f16"]
+        assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, r, bcode, steps, adjoint=True)) <= TOL["f16"]
 
 
 @pytest.mark.parametrize("r", [1, 2])
