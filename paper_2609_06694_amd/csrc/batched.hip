@@ -146,10 +146,27 @@ struct Layout {
     size_t lds = 0;
 };
 
+// Relative cost of one cell of member b in a grouped launch: its stencil's
+// taps plus a fixed share for the loads, stores, ring traffic and
+// addressing of a cell, times the window's recompute (the fused stages run
+// on all kGroupThreads columns to keep ow).  The fixed share is measured:
+// on the 64-grid mixed workload (k = 3) shares by cells alone ran at
+// 614-620 GCells/s, and a fixed share of 6, 12, 15, 18, 24 and 36 taps at
+// about 655, 695, 713, 712, 675 and 670.
+constexpr double kCellOverhead = 15.0;
+
+double member_cost(const GMember& b) {
+    const int taps = b.shape == kStar ? 4 * b.r + 1 : (2 * b.r + 1) * (2 * b.r + 1);
+    return (taps + kCellOverhead) * (double)kGroupThreads / b.ow;
+}
+
 // Geometry of the grouped launches from launch `round` on: chunks sized so
 // that every member still running gets workgroups in proportion to its
-// cells, about eight per CU in total (two and four per CU measured 40 % and
-// 5 % slower on the 64-grid workload); finished members get none.  The row
+// cells times their cost, about eight per CU in total (two and four per CU
+// measured 40 % and 5 % slower on the 64-grid workload); finished members
+// get none.  Weighting by cost keeps the workgroups of a launch of similar
+// length: each XCD runs a contiguous range of them, and a range heavy in
+// wide stencils would otherwise finish last.  The row
 // count per iteration and the LDS reservation cover every member, so all
 // launches share one kernel.
 Layout layout(const st_plan* plan, int steps, int cus, int round = 0) {
@@ -175,7 +192,7 @@ Layout layout(const st_plan* plan, int steps, int cus, int round = 0) {
     }
     double total = 0;
     for (const GMember& b : lay.members)
-        if (b.L > round) total += (double)b.nx * b.ny;
+        if (b.L > round) total += (double)b.nx * b.ny * member_cost(b);
     const double target = 8.0 * cus;
     // Eight input rows per iteration unless a member's rings would outgrow
     // 64 KiB; the launch reserves the largest member's rings.
@@ -184,7 +201,7 @@ Layout layout(const st_plan* plan, int steps, int cus, int round = 0) {
     // the workgroup ranges follow.
     lay.grid = 0;
     for (GMember& b : lay.members) {
-        const double share = target * ((double)b.nx * b.ny / std::max(1.0, total));
+        const double share = target * ((double)b.nx * b.ny * member_cost(b) / std::max(1.0, total));
         const int chunks = std::max(1, (int)(share / b.strips + 0.5));
         int ych = (b.ny + chunks - 1) / chunks;
         ych = std::max(ych, std::max(16, 4 * b.k * b.r));
