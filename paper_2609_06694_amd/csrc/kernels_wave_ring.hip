@@ -75,13 +75,13 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
         const char* kp = reinterpret_cast<const char*>(w.kappa + zoff);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            pv[slot][i] = __builtin_nontemporal_load(reinterpret_cast<const float*>(pp + pidx.off[i]));
-            kv[slot][i] = __builtin_nontemporal_load(reinterpret_cast<const float*>(kp + pidx.off[i]));
+            pv[slot][i] = load_at_nt<float, true>(pp, pidx.off[i]);
+            kv[slot][i] = load_at_nt<float, true>(kp, pidx.off[i]);
         }
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, float, NW, true, true>(w.cur, nx, ny, nz, min(zbeg + d, zend - 1), pidx, vin[d], vhalo[d]);
         issue_point(d, zbeg + d - R);
     }
 
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
 #pragma unroll
         for (int i = 0; i < RY; ++i) ring[sl][(ty * RY + i) * G::BX + tx] = masked<BC>(vin[d][i], vm[d], i);
         __builtin_amdgcn_s_setprio(3);
-        vm[d] = load_plane_at<R, RY, BC, float, NW, false>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
+        vm[d] = load_plane_at<R, RY, BC, float, NW, true, true>(w.cur, nx, ny, nz, min(zp + D, zend - 1), pidx, vin[d], vhalo[d]);
         __builtin_amdgcn_s_setprio(0);
     };
 
@@ -189,8 +189,9 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_ring_kernel(WaveLaunch w, i
                         }
                     }
                     if (w.trace_t != nullptr && zo == w.rec_z) w.trace_t[o] = v;
-                    if constexpr (LAP) __builtin_nontemporal_store(a, &w.lap_out[zoff + o]);
-                    __builtin_nontemporal_store(v, &np_[o]);
+                    // pidx.off[i] is this output cell's byte offset in its plane.
+                    if constexpr (LAP) store_at_nt(w.lap_out + zoff, pidx.off[i], a);
+                    store_at_nt(np_, pidx.off[i], v);
                 }
             }
             issue_point(d, zp + D - R);
