@@ -60,6 +60,9 @@ def parse():
                          "the launches of --kernel after the first --skip of them)")
     ap.add_argument("--kernel", default="wave3d_ring_kernel", help="kernel name substring for --summarize-trace")
     ap.add_argument("--skip", type=int, default=0, help="launches to skip (warm-up) for --summarize-trace")
+    ap.add_argument("--summarize-clock", default="",
+                    help="instead of benchmarking: clock per dispatch (GRBM_COUNT / traced duration) from a "
+                         "rocprofv3 --kernel-trace --pmc GRBM_COUNT output directory")
     ap.add_argument("--no-stream-ceiling", action="store_true",
                     help="skip the plain streaming kernels (copy, read-2/write-1, read-3/write-1) timed "
                          "after the headline as this device's practical bandwidth ceiling")
@@ -67,7 +70,7 @@ def parse():
 
 
 PMC_TARGETS = ("wave", "box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
-               "box2d_f32", "batch64", "wavegrad")
+               "box2d_f32", "batch64", "wavegrad", "clock")
 
 
 def pmc_target(name, dev, st, wl, torch):
@@ -107,6 +110,28 @@ def pmc_target(name, dev, st, wl, torch):
                                 for c in cases])
         ins = [torch.from_numpy(c.u0).to(dev) for c in cases]
         bs.apply(ins, 2 * max(1, bs.describe()["tsteps"]))
+    elif name == "clock":
+        # Twelve launches each of the headline leapfrog, the fp16 27-point
+        # box (VALU-bound) and torch's read-3/write-1 stream, for the clock
+        # each keeps (GRBM_COUNT over the kernel trace's durations).
+        case = wl.wave3d(n=512, steps=2)
+        u0 = torch.from_numpy(case.u0).to(dev)
+        prev = torch.from_numpy(case.u_prev).to(dev)
+        kap = torch.from_numpy(case.kappa).to(dev)
+        st.WaveModel(case.n, radius=4, boundary="zero").forward(u0, prev, kap, 12, out=torch.empty_like(u0),
+                                                                  prev_inout=True)
+        torch.cuda.synchronize()
+        del u0, prev, kap
+        c = wl.box3d(dtype=wl.F16)
+        s = st.Stencil(c.n, wl.SHAPE_NAMES[c.shape], c.radius, c.coeffs, dtype=wl.DTYPE_TAGS[c.dtype])
+        u = torch.from_numpy(c.u0).to(dev)
+        s.apply(u, 12 * fused_depth(s.describe(), 3), out=torch.empty_like(u))
+        torch.cuda.synchronize()
+        del u
+        n = 256 * 1024 * 1024
+        a, b, cc, d = (torch.rand(n, device=dev) for _ in range(4))
+        for _ in range(12):
+            torch.addcmul(a, b, cc, out=d)
     elif name == "wavegrad":
         case = wl.wavegrad3d(steps=40)
         n = case.n
@@ -121,6 +146,36 @@ def pmc_target(name, dev, st, wl, torch):
         raise SystemExit(f"unknown profiler target {name!r}; one of {PMC_TARGETS}")
     torch.cuda.synchronize()
     log(f"pmc target {name} done")
+
+
+def summarize_clock(directory):
+    """Clock kept by each kernel family of a `--pmc GRBM_COUNT --kernel-trace`
+    run: GRBM_COUNT (GPU clock cycles, summed over the 8 XCDs) over each
+    dispatch's traced duration.  Prints one JSON line."""
+    import csv
+    import glob
+    kt = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)[0]
+    cc = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)[0]
+    dur, name = {}, {}
+    with open(kt, newline="") as f:
+        for r in csv.DictReader(f):
+            dur[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            name[r["Dispatch_Id"]] = r["Kernel_Name"]
+    cyc = {}
+    with open(cc, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == "GRBM_COUNT":
+                cyc[r["Dispatch_Id"]] = cyc.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"] or 0)
+    fam = {}
+    for d in sorted(cyc, key=int):
+        if d not in dur or dur[d] < 50:
+            continue
+        k = name[d].split("(")[0].replace("void ", "")[:80]
+        fam.setdefault(k, []).append((dur[d], cyc[d] / 8 / (dur[d] * 1e3)))
+    out = {k: {"launches": len(v), "us": [round(t, 1) for t, _ in v], "ghz": [round(g, 3) for _, g in v]}
+           for k, v in fam.items()}
+    print(json.dumps(out), flush=True)
+    return out
 
 
 def summarize_counters(paths):
@@ -637,6 +692,9 @@ def main():
         return
     if args.summarize_counters is not None:
         summarize_counters(args.summarize_counters)
+        return
+    if args.summarize_clock:
+        summarize_clock(args.summarize_clock)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the stencil library runs on one GPU; run with --gpus 1"}))
