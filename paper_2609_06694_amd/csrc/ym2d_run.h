@@ -30,6 +30,8 @@
 // outside the grid are zero at every level.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace stk {
@@ -147,11 +149,20 @@ __device__ void ym2d_run(const T* __restrict__ in, T* __restrict__ out, int nx, 
                             q = q >= C ? q - C : q;
                             col[j] = src[q * RW + R + x + dx];
                         }
+                        // This column's weights in vector registers (f32: a
+                        // multiply-add with all operands in vector registers
+                        // issues faster than one taking a scalar register).
+                        A w[2 * R + 1];
+#pragma unroll
+                        for (int dy = -R; dy <= R; ++dy) {
+                            w[dy + R] = A(tp.c[box2<R>(dy, dx)]);
+                            if constexpr (std::is_same_v<A, float>) asm volatile("" : "+v"(w[dy + R]));
+                        }
 #pragma unroll
                         for (int j = 0; j < RY; ++j)
 #pragma unroll
                             for (int dy = -R; dy <= R; ++dy)
-                                acc[j] = fma_acc(A(tp.c[box2<R>(dy, dx)]), col[j + R + dy], acc[j]);
+                                acc[j] = fma_acc(w[dy + R], col[j + R + dy], acc[j]);
                     }
                 } else {
                     A col[NRD];
