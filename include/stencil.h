@@ -84,8 +84,8 @@ typedef enum {
     ST_VARIANT_YM2D = 5,  /* 2D row march, k fused time steps held in LDS row rings */
     ST_VARIANT_ZM3D_MFMA = 6, /* 3D 27-point box, fp16 storage: in-plane contraction on MFMA */
     ST_VARIANT_VC3D = 7,  /* variable-coefficient plane march (ST_VARCOEF plans, 2D and 3D) */
-    ST_VARIANT_ZM3D_H2 = 8, /* 3D box r = 1..2, fp16 storage, even nx: two cells per lane,
-                              packed-half dot products with f32 accumulation */
+    ST_VARIANT_ZM3D_H2 = 8, /* 3D box r = 1..2 or star r = 1, fp16 storage, even nx: two
+                              cells per lane, packed-half dot products with f32 accumulation */
     ST_VARIANT_YM2D_H2 = 9, /* 2D box r = 1..2, fp16 storage, even nx: the row march on
                                packed-half dot products */
     ST_VARIANT_YM3D = 10  /* 3D box r = 1..2 marched along y (slabs with few z planes):

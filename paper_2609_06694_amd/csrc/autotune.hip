@@ -142,7 +142,7 @@ std::vector<LaunchCfg> candidates(const st_problem& p) {
                 LaunchCfg c{ST_VARIANT_ZM3D, 0, ty, 2, zc};
                 if (cfg_legal(p, c)) out.push_back(c);
             }
-        // Packed-half form of the fp16 27-point box (two cells per lane).
+        // Packed-half form of the fp16 boxes and 7-point star (two cells per lane).
         for (int ty : {8, 16, 32})
             for (int zc : {8, 16, 32, 64, 128, 256, 0}) {
                 if (zc != 0 && zc >= p.n[2]) continue;

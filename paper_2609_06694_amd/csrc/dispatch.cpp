@@ -327,7 +327,7 @@ bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
                    c.tsteps >= 0 && c.tsteps <= 1;
         }
         if (c.variant == ST_VARIANT_ZM3D_H2)
-            return p.shape == ST_BOX && p.radius <= 2 && p.dtype == ST_F16 && p.n[0] % 2 == 0 &&
+            return (p.shape == ST_BOX ? p.radius <= 2 : p.radius == 1) && p.dtype == ST_F16 && p.n[0] % 2 == 0 &&
                    (c.tile_y == 8 || c.tile_y == 16 || c.tile_y == 32) && c.zchunk >= 0 && c.tsteps <= 1;
         if (c.variant == ST_VARIANT_ZM3D && c.tsteps == 2 &&
             (!zm3d_tb2_supported(p.radius, p.shape) || (c.tile_y != 16 && c.tile_y != 32)))

@@ -19,6 +19,12 @@
 // taps that leave the grid read zero rather than the centre value, so there
 // the residual sum runs over the taps inside the grid only.
 //
+// The 7-point star (radius 1) is the box with its off-axis weights zero; it
+// runs the same code with the rows and terms those zeros would feed left
+// out (the centre row keeps all four instructions, the four axis rows
+// keep the two dot products), so it matches the box kernel given those
+// zero weights, at a third of its arithmetic.
+//
 // Radius 2 (the 125-point box) uses the same pairs: for a row of weights
 // w_-2..w_2,
 //   out(x)   += dot2((u_x-2, u_x-1), (w_-2, w_-1)) + dot2((u_x, u_x+1), (w_0, w_1)) + w_2 u_x+2
@@ -99,7 +105,7 @@ __device__ __forceinline__ half2_t as_h2(uint32_t v) { return __builtin_bit_cast
 template <int R>
 using H2TapsOf = std::conditional_t<R == 1, H2Taps, H2Taps5>;
 
-template <int R, int BC, int RY, int NW, int D>
+template <int R, int SH, int BC, int RY, int NW, int D>
 __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out, int nxp, int ny,
                                                              int nz, int zc, int tiles_x, int tiles_y,
@@ -235,14 +241,16 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                     const int q = 1 - dz;
 #pragma unroll
                     for (int dy = -1; dy <= 1; ++dy) {
+                        if (SH == kStar && dz != 0 && dy != 0) continue;   // an all-zero row
+                        const bool ends = SH == kBox || (dz == 0 && dy == 0);   // w_-1, w_1 nonzero
                         const int k = (dz + 1) * 3 + (dy + 1);
 #pragma unroll
                         for (int i = 0; i < RY; ++i) {
                             const int j = i + 1 + dy;
                             ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.p01[k]), ax[q][i], false);
-                            ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
+                            if (ends) ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
                             ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.pm0[k]), ay[q][i], false);
-                            ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
+                            if (ends) ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
                         }
                     }
                 }
@@ -342,7 +350,24 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
 }
 
 bool zm3d_h2_supported(const Geom& g) {
-    return g.ndim == 3 && g.shape == kBox && (g.r == 1 || g.r == 2) && g.dtype == 1 && g.nx % 2 == 0;
+    const bool shape_ok = g.shape == kBox ? (g.r == 1 || g.r == 2) : g.r == 1;
+    return g.ndim == 3 && shape_ok && g.dtype == 1 && g.nx % 2 == 0;
+}
+
+// The 7-point star's weights (centre, then the x, y and z arms) placed in
+// the dense (dz, dy, dx) layout of the radius-1 box, zero off the axes.
+static Taps star_as_box(const Taps& t) {
+    Taps b;
+    memset(&b, 0, sizeof b);
+    auto at = [](int dz, int dy, int dx) { return ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1); };
+    b.c[at(0, 0, 0)] = t.c[0];
+    for (int d = -1; d <= 1; d += 2) {
+        b.c[at(0, 0, d)] = t.c[star_x<1>(d)];
+        b.c[at(0, d, 0)] = t.c[star_y<1>(d)];
+        b.c[at(d, 0, 0)] = t.c[star_z<1>(d)];
+    }
+    b.sum = t.sum;
+    return b;
 }
 
 // Host-side weight preparation (dense (dz,dy,dx) box weights, f32).
@@ -404,24 +429,24 @@ static H2Taps5 pack_h2_r2(const Taps& t) {
     return h;
 }
 
-template <int R, int BC, int RY, int NW>
+template <int R, int SH, int BC, int RY, int NW>
 static hipError_t go(const Geom& g, int zc, const H2TapsOf<R>& tp, const void* in, void* out, hipStream_t s) {
     using G = H2Geom<RY, NW, R>;
     const int nxp = g.nx / 2;
     const int tiles_x = (nxp + G::BXP - 1) / G::BXP, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
     constexpr int D = 2;
-    hipLaunchKernelGGL((zm3d_h2_kernel<R, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks), dim3(G::NT), 0, s,
+    hipLaunchKernelGGL((zm3d_h2_kernel<R, SH, BC, RY, NW, D>), dim3(tiles_x * tiles_y * nchunks), dim3(G::NT), 0, s,
                        (const uint32_t*)in, (uint32_t*)out, nxp, g.ny, g.nz, zc, tiles_x, tiles_y, tp);
     return hipGetLastError();
 }
 
-template <int R, int BC>
+template <int R, int SH, int BC>
 static hipError_t go_rows(const Geom& g, int rows, int zc, const H2TapsOf<R>& tp, const void* in, void* out,
                           hipStream_t s) {
-    if (rows == 8) return go<R, BC, 2, 4>(g, zc, tp, in, out, s);
-    if (rows == 16) return go<R, BC, 4, 4>(g, zc, tp, in, out, s);
-    return go<R, BC, 8, 4>(g, zc, tp, in, out, s);
+    if (rows == 8) return go<R, SH, BC, 2, 4>(g, zc, tp, in, out, s);
+    if (rows == 16) return go<R, SH, BC, 4, 4>(g, zc, tp, in, out, s);
+    return go<R, SH, BC, 8, 4>(g, zc, tp, in, out, s);
 }
 
 // tile_y: 8, 16 or 32 rows per workgroup (4 waves of 2, 4 or 8 rows).
@@ -432,12 +457,17 @@ hipError_t launch_zm3d_h2(const Geom& g, const LaunchCfg& cfg, const Taps& taps,
     const int rows = cfg.tile_y >= 32 ? 32 : (cfg.tile_y >= 16 ? 16 : 8);
     if (g.r == 2) {
         const H2Taps5 tp = pack_h2_r2(taps);
-        return g.boundary == kPeriodic ? go_rows<2, kPeriodic>(g, rows, zc, tp, in, out, s)
-                                       : go_rows<2, kZero>(g, rows, zc, tp, in, out, s);
+        return g.boundary == kPeriodic ? go_rows<2, kBox, kPeriodic>(g, rows, zc, tp, in, out, s)
+                                       : go_rows<2, kBox, kZero>(g, rows, zc, tp, in, out, s);
+    }
+    if (g.shape == kStar) {
+        const H2Taps tp = pack_h2(star_as_box(taps));
+        return g.boundary == kPeriodic ? go_rows<1, kStar, kPeriodic>(g, rows, zc, tp, in, out, s)
+                                       : go_rows<1, kStar, kZero>(g, rows, zc, tp, in, out, s);
     }
     const H2Taps tp = pack_h2(taps);
-    return g.boundary == kPeriodic ? go_rows<1, kPeriodic>(g, rows, zc, tp, in, out, s)
-                                   : go_rows<1, kZero>(g, rows, zc, tp, in, out, s);
+    return g.boundary == kPeriodic ? go_rows<1, kBox, kPeriodic>(g, rows, zc, tp, in, out, s)
+                                   : go_rows<1, kBox, kZero>(g, rows, zc, tp, in, out, s);
 }
 
 }  // namespace stk

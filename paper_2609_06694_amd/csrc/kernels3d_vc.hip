@@ -81,8 +81,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
             if constexpr (!ADJ) {
                 const char* pl = reinterpret_cast<const char*>(fk + (size_t)zo * plane_sz);
 #pragma unroll
-                for (int i = 0; i < RY; ++i)
-                    cv[k][i] = __builtin_nontemporal_load(reinterpret_cast<const T*>(pl + pidx.off[i]));
+                for (int i = 0; i < RY; ++i) cv[k][i] = load_at_nt<T, true>(pl, pidx.off[i]);
             } else {
                 int gz = zo - kOff.d[k][0];
                 fix_coord<BC>(gz, nz);
@@ -100,7 +99,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
     };
 
     T vin[RY], vhalo[G::HT];
-    uint32_t vm = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, zbeg, pidx, vin, vhalo);
+    uint32_t vm = load_plane_at<R, RY, BC, T, NW, true, true>(in, nx, ny, nz, zbeg, pidx, vin, vhalo);
     load_coef(z0);
 
     int slot = 0;   // ring slot of plane zp
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
         // A 2D grid is a single pass with nothing to prefetch.  In 3D the
         // last pass reloads a clamped plane: cheaper than a branch here.
         if constexpr (NDIM == 3)
-            vm = load_plane_at<R, RY, BC, T, NW>(in, nx, ny, nz, min(zp + 1, zend - 1), pidx, vin, vhalo);
+            vm = load_plane_at<R, RY, BC, T, NW, true, true>(in, nx, ny, nz, min(zp + 1, zend - 1), pidx, vin, vhalo);
         __syncthreads();
 
         const int zo = zp - RZ;
@@ -138,7 +137,7 @@ __global__ __launch_bounds__(NW * kWave) void vc3d_kernel(const T* __restrict__ 
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     const int gy = y0 + ty * RY + i;
-                    if (gy < ny) __builtin_nontemporal_store(from_acc<T>(acc[i]), &o[(uint32_t)(gy * nx + gx)]);
+                    if (gy < ny) store_at_nt(o, pidx.off[i], from_acc<T>(acc[i]));   // the cell's byte offset
                 }
             }
             if constexpr (NDIM == 3) {

@@ -1,9 +1,11 @@
 """Regenerate the shipped dispatch map (dispatch_mi355x.txt next to the
 library) by running the autotuner on the benchmark workloads' cases.
 
-Usage (on the GPU machine): python -m paper_2609_06694_amd.tune_defaults OUT
+Usage (on the GPU machine): python -m paper_2609_06694_amd.tune_defaults OUT [WORDS]
 Each tuned case key is appended to OUT; copy OUT to the package directory as
-dispatch_mi355x.txt to make it the default map.
+dispatch_mi355x.txt to make it the default map.  WORDS (comma-separated)
+tunes only the workloads whose name contains every word, for refreshing
+some entries of the map.
 """
 from __future__ import annotations
 
@@ -12,7 +14,7 @@ import sys
 
 
 
-def main(out: str) -> None:
+def main(out: str, words: str = "") -> None:
     os.environ["STENCIL_TUNE_CACHE"] = out
     os.environ.pop("STENCIL_TUNE_FAULT", None)
     import torch  # noqa: F401  (device memory for the scratch buffers)
@@ -70,7 +72,10 @@ def main(out: str) -> None:
             continue
         seen.add(key)
         plans.append((g.name, st.Stencil(g.n[:2], wl.SHAPE_NAMES[g.shape], g.radius, g.coeffs)))
+    need = [w for w in words.split(",") if w]
     for name, p in plans:
+        if not all(w in name for w in need):
+            continue
         stats = p.autotune()
         print(f"{name}: {p.describe()} {stats}", flush=True)
         torch.cuda.empty_cache()
@@ -82,4 +87,4 @@ def main(out: str) -> None:
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "dispatch_tuned.txt")
+    main(sys.argv[1] if len(sys.argv) > 1 else "dispatch_tuned.txt", sys.argv[2] if len(sys.argv) > 2 else "")

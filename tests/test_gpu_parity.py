@@ -437,6 +437,36 @@ def test_3d_box_fp16_packed_half_vs_oracle(st, bc, r, ty):
         assert rel_l2(gotT, oracle.sweep(v, c, wl.BOX, r, bcode, steps, adjoint=True)) <= TOL["f16"]
 
 
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+@pytest.mark.parametrize("ty", [8, 16, 32])
+def test_3d_star_fp16_packed_half_vs_oracle(st, bc, ty):
+    """Packed-half 7-point star (fp16 storage; the radius-1 box kernel with
+    the off-axis rows left out): ragged even sizes, grids smaller than a
+    tile and than 3, plane chunks; forward and transpose against the oracle
+    at the fp16 gate and within 5x of the binary16 storage floor, and the
+    forward equal to the packed-half box given the star's weights with
+    zeros off the axes."""
+    rng = np.random.default_rng(7170 + ty)
+    bcode = wl.PERIODIC if bc == "periodic" else wl.ZERO
+    for (nx, ny, nz), zc, steps in [((256, 40, 20), 0, 3), ((202, 70, 33), 5, 4), ((10, 5, 7), 0, 3),
+                                    ((2, 3, 4), 0, 2), ((386, 17, 9), 0, 6)]:
+        c = wl.random_unit_sum_coeffs(rng, 3, wl.STAR, 1)
+        u = wl.small_random_grid(rng, 3, (nx, ny, nz), np.float16, 0.0, 1.0)
+        s = st.Stencil((nx, ny, nz), "star", 1, c, dtype="f16", boundary=bc, variant=8, tile_y=ty, zchunk=zc)
+        assert s.describe()["variant"] == "zm3d_h2"
+        got_dev = s.apply(_dev(u), steps)
+        got = _host(got_dev).astype(np.float64)
+        ref = oracle.sweep(u, c, wl.STAR, 1, bcode, steps)
+        floor = rel_l2(oracle.sweep(u, c, wl.STAR, 1, bcode, steps, storage="binary16"), ref)
+        e = rel_l2(got, ref)
+        assert e <= TOL["f16"] and e <= 5 * floor, (nx, ny, nz, zc, e, floor)
+        sb = st.Stencil((nx, ny, nz), "box", 1, c, dtype="f16", boundary=bc, variant=8, tile_y=ty, zchunk=zc)
+        assert np.array_equal(_host(sb.apply(_dev(u), steps)), _host(got_dev)), (nx, ny, nz, zc)
+        v = wl.small_random_grid(rng, 3, (nx, ny, nz), np.float16, 0.0, 1.0)
+        gotT = _host(s.apply_adjoint(_dev(v), steps)).astype(np.float64)
+        assert rel_l2(gotT, oracle.sweep(v, c, wl.STAR, 1, bcode, steps, adjoint=True)) <= TOL["f16"]
+
+
 @pytest.mark.parametrize("r", [1, 2])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
 @pytest.mark.parametrize("nt,k,ych", [(256, 1, 0), (256, 2, 0), (512, 3, 32), (256, 4, 16), (512, 8, 0)])
