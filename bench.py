@@ -483,8 +483,6 @@ def bench_shapes(dev, st, wl, torch):
     for sname, r in (("star", 1), ("box", 1), ("box", 2)):
         c = wl.random_unit_sum_coeffs(rng, 3, wl.STAR if sname == "star" else wl.BOX, r)
         for dt in ("f16", "f32", "f64"):
-            if r == 2 and dt == "f64":
-                continue
             tdt = {"f16": torch.float16, "f32": torch.float32, "f64": torch.float64}[dt]
             for tag, n in SHAPES:
                 s = st.Stencil(n, sname, r, c, dtype=dt)
