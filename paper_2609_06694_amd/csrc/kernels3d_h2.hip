@@ -8,7 +8,12 @@
 // pair (x, x+1) and one (dz, dy) row of weights w_-1, w_0, w_1,
 //   out(x)   += dot2((u_x, u_x+1), (w_0, w_1))  + w_-1 * u_x-1
 //   out(x+1) += dot2((u_x, u_x+1), (w_-1, w_0)) + w_1  * u_x+2,
-// four instructions for six multiply-adds.  The packed weights are the
+// four instructions for six multiply-adds.  Of the three rows of one dz,
+// two end terms of each cell share a dot2: (u_x-1 of rows y-1, y) with
+// (w_-1 of those rows), and (u_x+2 of rows y, y+1) with their w_1, the
+// value pairs built by one v_perm per row and reused by the three dz; a
+// cell's nine rows take 9 + 3 + 3 = 15 instructions per plane for its 27
+// multiply-adds (18 unpaired).  The packed weights are the
 // binary16 roundings w_hi of the f32 weights; their residuals w - w_hi (at
 // most 2^-12 |w|) enter through one extra multiply-add per cell,
 // (sum of residuals) * u(x): the part of the residual sum that acts on the
@@ -55,6 +60,10 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 struct H2Taps {
     uint32_t p01[9], pm0[9];
     float wm[9], wp[9];
+    // Per dz: (w_-1 of row dy = -1, w_-1 of row dy = 0) and (w_1 of row
+    // dy = 0, w_1 of row dy = 1) as binary16 pairs, so two end terms of a
+    // cell take one dot2 (the pairs of values come from one v_perm).
+    uint32_t wmp[3], wpp[3];
     float res;
     float rr[27];
 };
@@ -235,22 +244,46 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                     p0[j] = cp[j * G::WP + 1];
                     pp[j] = cp[j * G::WP + 2];
                 }
-                // Plane zp feeds output plane zp - dz with the weights of dz.
+                // End values of the box rows in pairs: (u_x-1 of rows i, i+1)
+                // for out(x) and (u_x+2 of rows i+1, i+2) for out(x+1).
+                uint32_t em[SH == kBox ? RY : 1], ep[SH == kBox ? RY : 1];
+                if constexpr (SH == kBox) {
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        em[i] = __builtin_amdgcn_perm(pm[i + 1], pm[i], 0x07060302u);
+                        ep[i] = __builtin_amdgcn_perm(pp[i + 2], pp[i + 1], 0x05040100u);
+                    }
+                }
+                // Plane zp feeds output plane zp - dz with the weights of dz:
+                // the centre pairs of the dz rows, then the end terms.
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz) {
                     const int q = 1 - dz;
 #pragma unroll
                     for (int dy = -1; dy <= 1; ++dy) {
                         if (SH == kStar && dz != 0 && dy != 0) continue;   // an all-zero row
-                        const bool ends = SH == kBox || (dz == 0 && dy == 0);   // w_-1, w_1 nonzero
                         const int k = (dz + 1) * 3 + (dy + 1);
 #pragma unroll
                         for (int i = 0; i < RY; ++i) {
                             const int j = i + 1 + dy;
                             ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.p01[k]), ax[q][i], false);
-                            if (ends) ax[q][i] = fmaf(tp.wm[k], (float)as_h2(pm[j]).y, ax[q][i]);
                             ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[j]), as_h2(tp.pm0[k]), ay[q][i], false);
-                            if (ends) ay[q][i] = fmaf(tp.wp[k], (float)as_h2(pp[j]).x, ay[q][i]);
+                        }
+                    }
+                    if constexpr (SH == kBox) {
+                        const int k0 = (dz + 1) * 3;   // row dy = -1 of this dz
+#pragma unroll
+                        for (int i = 0; i < RY; ++i) {
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(em[i]), as_h2(tp.wmp[dz + 1]), ax[q][i], false);
+                            ax[q][i] = fmaf(tp.wm[k0 + 2], (float)as_h2(pm[i + 2]).y, ax[q][i]);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(ep[i]), as_h2(tp.wpp[dz + 1]), ay[q][i], false);
+                            ay[q][i] = fmaf(tp.wp[k0], (float)as_h2(pp[i]).x, ay[q][i]);
+                        }
+                    } else if (dz == 0) {   // the star's only end terms: row (0, 0)
+#pragma unroll
+                        for (int i = 0; i < RY; ++i) {
+                            ax[q][i] = fmaf(tp.wm[4], (float)as_h2(pm[i + 1]).y, ax[q][i]);
+                            ay[q][i] = fmaf(tp.wp[4], (float)as_h2(pp[i + 1]).x, ay[q][i]);
                         }
                     }
                 }
@@ -391,6 +424,15 @@ static H2Taps pack_h2(const Taps& t) {
         h.rr[k * 3 + 1] = (float)r0;
         h.rr[k * 3 + 2] = (float)rp;
         res += rm + r0 + rp;
+    }
+    for (int z = 0; z < 3; ++z) {   // rows k = 3z + (dy + 1)
+        half2_t a, c;
+        a.x = hi(t.c[(3 * z + 0) * 3 + 0]);   // w_-1 of dy = -1
+        a.y = hi(t.c[(3 * z + 1) * 3 + 0]);   // w_-1 of dy = 0
+        c.x = hi(t.c[(3 * z + 1) * 3 + 2]);   // w_1 of dy = 0
+        c.y = hi(t.c[(3 * z + 2) * 3 + 2]);   // w_1 of dy = 1
+        h.wmp[z] = __builtin_bit_cast(uint32_t, a);
+        h.wpp[z] = __builtin_bit_cast(uint32_t, c);
     }
     h.res = (float)res;
     return h;
