@@ -11,7 +11,9 @@
 //             out(x+1) = dot2((u_x, u_x+1), (w_-1, w_0)) + w_1 u_x+2;
 //   radius 2: out(x)   = dot2((u_x-2, u_x-1), (w_-2, w_-1)) + dot2((u_x, u_x+1), (w_0, w_1)) + w_2 u_x+2,
 //             out(x+1) = w_-2 u_x-1 + dot2((u_x, u_x+1), (w_-1, w_0)) + dot2((u_x+2, u_x+3), (w_1, w_2)),
-// 15 instructions for the 25 multiply-adds of a radius-2 cell.  The
+// and at radius 2 the end terms w_2 u_x+2 and w_-2 u_x-1 of two adjacent
+// rows share one dot2 on values paired by a v_perm: 13 instructions (15
+// unpaired) for the 25 multiply-adds of a radius-2 cell.  The
 // residuals w - w_hi enter as one multiply-add on the centre value, with
 // their sum over the taps inside the grid (all taps under a periodic
 // boundary; under a zero frame fewer at the edges).  A level
@@ -38,6 +40,9 @@ typedef _Float16 h2v_t __attribute__((ext_vector_type(2)));
 struct H2Taps2 {
     uint32_t pa[5], pb[5], pc[5], pd[5];
     float fa[5], fb[5];
+    // Radius 2: (w_2 of rows t, t+1) and (w_-2 of rows t, t+1) as binary16
+    // pairs, t = 0..3, so two end terms of a cell take one dot2.
+    uint32_t fap[4], fbp[4];
     float res;
     float rr[25];
 };
@@ -179,10 +184,38 @@ __global__ __launch_bounds__(NT) void ym2d_h2_kernel(const uint32_t* __restrict_
                         } else {
                             ax[j] = __builtin_amdgcn_fdot2(h2v(pm[r]), h2v(tp.pa[t]), ax[j], false);
                             ax[j] = __builtin_amdgcn_fdot2(h2v(p0[r]), h2v(tp.pb[t]), ax[j], false);
-                            ax[j] = fmaf(tp.fa[t], (float)h2v(pp[r]).x, ax[j]);
-                            ay[j] = fmaf(tp.fb[t], (float)h2v(pm[r]).y, ay[j]);
                             ay[j] = __builtin_amdgcn_fdot2(h2v(p0[r]), h2v(tp.pc[t]), ay[j], false);
                             ay[j] = __builtin_amdgcn_fdot2(h2v(pp[r]), h2v(tp.pd[t]), ay[j], false);
+                        }
+                    }
+                }
+                if constexpr (R == 2) {
+                    // The end terms w_2 u_x+2 (out x) and w_-2 u_x-1 (out x+1)
+                    // of rows r, r+1 (r even) share one dot2: the value pairs
+                    // come from one v_perm each; a row j takes the pairs that
+                    // start at its even rows and one end term alone.
+                    uint32_t ex[NRD / 2], ey[NRD / 2];
+#pragma unroll
+                    for (int h = 0; h < NRD / 2; ++h) {
+                        ex[h] = __builtin_amdgcn_perm(pp[2 * h + 1], pp[2 * h], 0x05040100u);   // (u_x+2 of 2h, 2h+1)
+                        ey[h] = __builtin_amdgcn_perm(pm[2 * h + 1], pm[2 * h], 0x07060302u);   // (u_x-1 of 2h, 2h+1)
+                    }
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        if (j % 2 == 0) {   // rows j, j+1 | j+2, j+3 | j+4
+                            ax[j] = __builtin_amdgcn_fdot2(h2v(ex[j / 2]), h2v(tp.fap[0]), ax[j], false);
+                            ax[j] = __builtin_amdgcn_fdot2(h2v(ex[j / 2 + 1]), h2v(tp.fap[2]), ax[j], false);
+                            ax[j] = fmaf(tp.fa[4], (float)h2v(pp[j + 4]).x, ax[j]);
+                            ay[j] = __builtin_amdgcn_fdot2(h2v(ey[j / 2]), h2v(tp.fbp[0]), ay[j], false);
+                            ay[j] = __builtin_amdgcn_fdot2(h2v(ey[j / 2 + 1]), h2v(tp.fbp[2]), ay[j], false);
+                            ay[j] = fmaf(tp.fb[4], (float)h2v(pm[j + 4]).y, ay[j]);
+                        } else {            // row j | j+1, j+2 | j+3, j+4
+                            ax[j] = fmaf(tp.fa[0], (float)h2v(pp[j]).x, ax[j]);
+                            ax[j] = __builtin_amdgcn_fdot2(h2v(ex[(j + 1) / 2]), h2v(tp.fap[1]), ax[j], false);
+                            ax[j] = __builtin_amdgcn_fdot2(h2v(ex[(j + 3) / 2]), h2v(tp.fap[3]), ax[j], false);
+                            ay[j] = fmaf(tp.fb[0], (float)h2v(pm[j]).y, ay[j]);
+                            ay[j] = __builtin_amdgcn_fdot2(h2v(ey[(j + 1) / 2]), h2v(tp.fbp[1]), ay[j], false);
+                            ay[j] = __builtin_amdgcn_fdot2(h2v(ey[(j + 3) / 2]), h2v(tp.fbp[3]), ay[j], false);
                         }
                     }
                 }
@@ -253,6 +286,13 @@ static H2Taps2 pack_h2_2d(const Taps& t, int R) {
             h.fb[tix] = (float)c[0];
         }
     }
+    if (R == 2)
+        for (int r = 0; r < 4; ++r) {   // rows r and r + 1
+            const _Float16 a0 = (_Float16)t.c[r * w + 4], a1 = (_Float16)t.c[(r + 1) * w + 4];
+            const _Float16 b0 = (_Float16)t.c[r * w + 0], b1 = (_Float16)t.c[(r + 1) * w + 0];
+            h.fap[r] = pk(a0, a1);
+            h.fbp[r] = pk(b0, b1);
+        }
     h.res = (float)res;
     return h;
 }
