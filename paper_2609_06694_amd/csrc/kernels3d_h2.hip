@@ -70,7 +70,9 @@ struct H2Taps {
 
 // Radius 2: per (dz, dy) row k = (dz+2)*5 + (dy+2), words [8k .. 8k+5] of
 // `row` hold (w_-2, w_-1), (w_0, w_1), (w_-1, w_0), (w_1, w_2) as binary16
-// pairs and w_2, w_-2 as f32 bit patterns; rr holds the 125 residuals in
+// pairs and w_2, w_-2 as f32 bit patterns; for dy = -2 and 0, words 6 and 7
+// hold (w_2 of rows k, k+1) and (w_-2 of rows k, k+1) as binary16 pairs; rr
+// holds the 125 residuals in
 // (dz, dy, dx) order.  A kernel argument (1.3 KB), read per row through
 // the scalar cache.
 struct H2Taps5 {
@@ -288,13 +290,55 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                     }
                 }
             } else {
-                // Radius 2: a rolled loop over dy (five weight rows and the
-                // thread's RY rows at offset dy live at a time; unrolled, the
+                // Radius 2: rolled loops over dy (the weight rows and the
+                // thread's rows at offset dy live at a time; unrolled, the
                 // compiler would load all 25 weight rows, 150 registers, at
                 // once), the dz groups unrolled so each sum stays in its
-                // register.
+                // register.  Rows dy, dy + 1 go together (dy = -2, 0): their
+                // end terms w_2 u_x+2 and w_-2 u_x-1 share one dot2 on values
+                // paired by a v_perm; row 2 goes alone.
 #pragma unroll 1
-                for (int dy = -R; dy <= R; ++dy) {
+                for (int dy = -R; dy < R; dy += 2) {
+                    uint32_t pm[RY], p0[RY], pp[RY], qm[RY], q0[RY], qp[RY], ex[RY], ey[RY];
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        const uint32_t* r = cp + (i + R + dy) * G::WP;
+                        pm[i] = r[0];
+                        p0[i] = r[1];
+                        pp[i] = r[2];
+                        qm[i] = r[G::WP];
+                        q0[i] = r[G::WP + 1];
+                        qp[i] = r[G::WP + 2];
+                        ex[i] = __builtin_amdgcn_perm(qp[i], pp[i], 0x05040100u);   // (u_x+2 of rows dy, dy+1)
+                        ey[i] = __builtin_amdgcn_perm(qm[i], pm[i], 0x07060302u);   // (u_x-1 of rows dy, dy+1)
+                    }
+#pragma unroll
+                    for (int dz = -R; dz <= R; ++dz) {
+                        const int q = R - dz;
+                        const int k = (dz + R) * Q + (dy + R);   // row dy; row dy + 1 is k + 1
+                        // (w_-2, w_-1), (w_0, w_1), (w_-1, w_0), (w_1, w_2) of both
+                        // rows and the two end pairs (scalar loads from the
+                        // arguments: uniform, no LDS traffic)
+                        const uint4 wa = {tp.row[8 * k], tp.row[8 * k + 1], tp.row[8 * k + 2], tp.row[8 * k + 3]};
+                        const uint4 wb = {tp.row[8 * k + 8], tp.row[8 * k + 9], tp.row[8 * k + 10], tp.row[8 * k + 11]};
+                        const uint32_t fap = tp.row[8 * k + 6], fbp = tp.row[8 * k + 7];
+#pragma unroll
+                        for (int i = 0; i < RY; ++i) {
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(pm[i]), as_h2(wa.x), ax[q][i], false);
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[i]), as_h2(wa.y), ax[q][i], false);
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(qm[i]), as_h2(wb.x), ax[q][i], false);
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(q0[i]), as_h2(wb.y), ax[q][i], false);
+                            ax[q][i] = __builtin_amdgcn_fdot2(as_h2(ex[i]), as_h2(fap), ax[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(p0[i]), as_h2(wa.z), ay[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(pp[i]), as_h2(wa.w), ay[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(q0[i]), as_h2(wb.z), ay[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(qp[i]), as_h2(wb.w), ay[q][i], false);
+                            ay[q][i] = __builtin_amdgcn_fdot2(as_h2(ey[i]), as_h2(fbp), ay[q][i], false);
+                        }
+                    }
+                }
+                {
+                    constexpr int dy = R;   // the last row, alone
                     uint32_t pm[RY], p0[RY], pp[RY];
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
@@ -308,7 +352,6 @@ __global__ __launch_bounds__(NW * kWave) void zm3d_h2_kernel(const uint32_t* __r
                         const int q = R - dz;
                         const int k = (dz + R) * Q + (dy + R);
                         // (w_-2, w_-1), (w_0, w_1), (w_-1, w_0), (w_1, w_2), w_2, w_-2
-                        // (scalar loads from the arguments: uniform, no LDS traffic)
                         const uint4 wa = {tp.row[8 * k], tp.row[8 * k + 1], tp.row[8 * k + 2], tp.row[8 * k + 3]};
                         const float fa = __uint_as_float(tp.row[8 * k + 4]);
                         const float fb = __uint_as_float(tp.row[8 * k + 5]);
@@ -467,6 +510,13 @@ static H2Taps5 pack_h2_r2(const Taps& t) {
         memcpy(&h.row[8 * k + 4], &fa, 4);
         memcpy(&h.row[8 * k + 5], &fb, 4);
     }
+    // Rows k, k + 1 with dy = -2, 0: their end weights w_2 and w_-2 as
+    // binary16 pairs in the row's spare words 6 and 7.
+    for (int k = 0; k < 25; ++k)
+        if (k % 5 == 0 || k % 5 == 2) {
+            h.row[8 * k + 6] = pk((_Float16)t.c[k * 5 + 4], (_Float16)t.c[(k + 1) * 5 + 4]);
+            h.row[8 * k + 7] = pk((_Float16)t.c[k * 5 + 0], (_Float16)t.c[(k + 1) * 5 + 0]);
+        }
     h.res = (float)res;
     return h;
 }
