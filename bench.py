@@ -72,7 +72,7 @@ def parse():
     return ap.parse_args()
 
 
-PMC_TARGETS = ("wave", "box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
+PMC_TARGETS = ("wave", "wave_f64", "box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
                "box2d_f32", "box3d_r2_f16", "box3d_r2_f32", "batch64", "wavegrad", "clock")
 
 
@@ -94,6 +94,13 @@ def pmc_target(name, dev, st, wl, torch):
         out = torch.empty_like(u0)
         model = st.WaveModel(case.n, radius=4, boundary="zero")
         model.forward(u0, prev, kap, 2, out=out, prev_inout=True)
+    elif name == "wave_f64":
+        case = wl.wave3d(n=512, steps=2)
+        u0 = torch.from_numpy(case.u0).to(dev).double()
+        prev = torch.from_numpy(case.u_prev).to(dev).double()
+        kap = torch.from_numpy(case.kappa).to(dev).double()
+        model = st.WaveModel(case.n, radius=4, boundary="zero", dtype="f64")
+        model.forward(u0, prev, kap, 2, out=torch.empty_like(u0), prev_inout=True)
     elif name in ("box3d_f16", "box3d_f16_zm", "box3d_f32", "box3d_f16_mfma", "star3d_f16", "box2d_f16",
                   "box2d_f32", "box3d_r2_f16", "box3d_r2_f32"):
         case = {"box3d_f16": lambda: wl.box3d(dtype=wl.F16), "box3d_f32": lambda: wl.box3d(dtype=wl.F32),
@@ -354,6 +361,35 @@ def bench_wave_sponge(dev, st, wl, torch):
             "hbm_frac": g * WAVE_BYTES_PER_CELL / HBM_PEAK_GBS, "ms_plain": ms_p,
             "overhead_vs_plain": ms_d / ms_p, "dispatch": damped.describe(),
             "timing": f"median of {REPS} passes interleaved with the plain leapfrog"}
+
+
+WAVE_F64_BYTES_PER_CELL = 32   # the four operands of WAVE_BYTES_PER_CELL in binary64
+
+
+def bench_wave_f64(dev, st, wl, torch):
+    """The headline wave workload stored and computed in binary64 (fields
+    converted from the f32 case), median of passes that continue the
+    simulation from the previous pass's state."""
+    case = wl.wave3d(n=512, steps=20)
+    bufs = [torch.from_numpy(case.u0).to(dev).double(), torch.empty(case.u0.shape, dtype=torch.float64, device=dev)]
+    prev = torch.from_numpy(case.u_prev).to(dev).double()
+    kap = torch.from_numpy(case.kappa).to(dev).double()
+    model = st.WaveModel(case.n, radius=4, boundary="zero", dtype="f64")
+    state = {"i": 0}
+
+    def one_pass():
+        i = state["i"]
+        model.forward(bufs[i], prev, kap, case.steps, out=bufs[1 - i], prev_inout=True)
+        state["i"] = 1 - i
+
+    ms = timed(one_pass, REPS, 2, torch.cuda.synchronize)
+    g = gcells(case.cells, case.steps, ms)
+    finite = bool(torch.isfinite(bufs[state["i"]]).all().item())
+    return {"workload": "wave3d_star4_512^3_20steps_zero_frame_f64", "ms": ms, "gcells_s": g,
+            "bytes_per_cell_update": WAVE_F64_BYTES_PER_CELL, "hbm_frac": g * WAVE_F64_BYTES_PER_CELL / HBM_PEAK_GBS,
+            "flop_per_cell_update": 53, "valu_f64_frac": g * 53 / 1e3 / VALU_F64_PEAK_TFLOPS,
+            "finite": finite, "dispatch": model.describe(),
+            "timing": f"median of {REPS} passes (each continues the previous one's state)"}
 
 
 def bench_jacobi(dev, st, wl, torch):
@@ -762,6 +798,7 @@ def main():
             ("batch64", lambda: {"batch64": bench_batch(dev, st, wl, torch)}),
             ("wavegrad", lambda: {"wavegrad": bench_grad(dev, st, wl, torch)}),
             ("wave3d_sponge", lambda: {"wave3d_sponge": bench_wave_sponge(dev, st, wl, torch)}),
+            ("wave3d_f64", lambda: {"wave3d_f64": bench_wave_f64(dev, st, wl, torch)}),
         ]
         for name, fn in todo:
             if only and name not in only:

@@ -105,7 +105,8 @@ typedef struct {
     const float *coeffs;   /* HOST, (2r+1)^ndim dense; for ST_WAVE may be NULL,
                               meaning the central second-difference Laplacian
                               of accuracy order 2r */
-    int32_t dtype;         /* st_dtype (ST_WAVE requires ST_F32) */
+    int32_t dtype;         /* st_dtype (ST_WAVE: ST_F32, or ST_F64 for the forward
+                              leapfrog of stencil_apply only) */
     int32_t boundary;      /* st_boundary */
     int32_t update;        /* st_update (ST_WAVE requires ndim 3, star) */
 } st_problem;
@@ -126,14 +127,16 @@ typedef struct {
     int32_t ckpt_every;    /* wave gradient checkpoint interval (0 = 20) */
 } st_plan_opts;
 
-/* Extra operands of an ST_WAVE plan. */
+/* Extra operands of an ST_WAVE plan.  u_prev, kappa, wavelet and traces
+ * hold values of the plan's storage type (float for ST_F32, double for
+ * ST_F64); target is float (the gradient takes f32 plans only). */
 typedef struct {
     void *u_prev;          /* device, cells: u_{-1} on entry, u_{T-1} on exit */
-    const float *kappa;    /* device, cells */
+    const void *kappa;     /* device, cells */
     int64_t src[3];        /* point source (x, y, z); src[0] < 0 = none */
-    const float *wavelet;  /* device, steps: wavelet[t] is added at src to u_{t+1} */
+    const void *wavelet;   /* device, steps: wavelet[t] is added at src to u_{t+1} */
     int64_t rec_z;         /* receiver plane z index, -1 = none */
-    float *traces;         /* device, steps*ny*nx or NULL: traces[t] = plane rec_z of u_{t+1} */
+    void *traces;          /* device, steps*ny*nx or NULL: traces[t] = plane rec_z of u_{t+1} */
     const float *target;   /* device, steps*ny*nx: observed traces d (gradient only) */
     /* Absorbing layer (0 = none): a damping term gamma(x) u_t, from the
      * damped wave equation u_tt + gamma u_t = c^2 Lap u with central
@@ -146,6 +149,7 @@ typedef struct {
      * on a boundary cell), W = sponge_width, s = sponge_strength.  It needs
      * the zero frame and the LDS-ring kernels (ST_EUNSUPPORTED otherwise);
      * 0 <= W <= min(n) / 2 and 0 <= s <= 4, finite (ST_EINVAL otherwise).
+     * An ST_F64 plan evaluates the layer in binary64 (its forward step only).
      * The same layer applies to stencil_apply, stencil_apply_adjoint (the
      * transpose of the damped state map) and stencil_wave_gradient. */
     int32_t sponge_width;
@@ -197,7 +201,9 @@ st_status stencil_plan_coefficients(const st_plan *plan, float *dense, int32_t c
  *  ST_LINEAR: u_out = A^steps u_in.  u_in == u_out is allowed; other overlap
  *             is not.  `wave` must be NULL.
  *  ST_WAVE:   u_in = u_0 and wave->u_prev = u_{-1}; on return u_out = u_T and
- *             wave->u_prev = u_{T-1}.  Source and receiver are optional.
+ *             wave->u_prev = u_{T-1}.  Source and receiver are optional.  An
+ *             ST_F64 plan runs the leapfrog in binary64 with binary64 weights
+ *             (the built-in Laplacian's rationals rounded once).
  * Device buffers hold n[0]*n[1]*n[2] values of the plan's storage type.
  * steps == 0 copies u_in to u_out. */
 st_status stencil_apply(const st_plan *plan, const void *u_in, void *u_out, int32_t steps,
@@ -228,7 +234,7 @@ size_t stencil_noalloc_capacity(void);
  *             (no source): on entry v_in and wave->u_prev are the co-states of
  *             u_T and u_{T-1}; on return v_out and wave->u_prev are the
  *             co-states of u_0 and u_{-1}.
- * Same buffer rules as stencil_apply. */
+ * Same buffer rules as stencil_apply.  ST_EUNSUPPORTED for an ST_F64 wave plan. */
 st_status stencil_apply_adjoint(const st_plan *plan, const void *v_in, void *v_out,
                                 int32_t steps, const st_wave_args *wave, void *workspace,
                                 size_t ws_bytes, void *stream);
@@ -261,7 +267,7 @@ st_status stencil_apply_varcoef_adjoint(const st_plan *plan, const void *v_in, v
  * wave->src, wavelet, rec_z (required >= 0) and target are used; traces, if
  * non-NULL, receive the recorded traces.  dkappa (device, cells) is
  * overwritten; *loss_dev (device, one double) receives J.  Workspace from
- * stencil_workspace_bytes(plan, steps, 1). */
+ * stencil_workspace_bytes(plan, steps, 1).  ST_EUNSUPPORTED for an ST_F64 plan. */
 st_status stencil_wave_gradient(const st_plan *plan, const void *u0, const st_wave_args *wave,
                                 int32_t steps, float *dkappa, double *loss_dev,
                                 void *workspace, size_t ws_bytes, void *stream);
@@ -314,7 +320,8 @@ st_status stencil_plan_describe_batched(const st_plan *plan, int32_t steps, int3
  * stencil_workspace_bytes(plan, 0, 2) bytes.  Synchronises `stream`.
  * Setting STENCIL_TUNE_FAULT=1 deliberately perturbs the coefficients of part
  * of the candidates (fused-step or 32-row ones) so tests can check that the
- * parity filter rejects wrong-but-faster candidates. */
+ * parity filter rejects wrong-but-faster candidates.  An ST_F64 wave plan
+ * keeps its map configuration (ST_EUNSUPPORTED, nothing changed). */
 st_status stencil_autotune(st_plan *plan, void *scratch, size_t scratch_bytes, void *stream);
 
 /* Counts from the plan's last stencil_autotune: candidates tried and

@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["stencil_api.cpp", "dispatch.cpp", "kernels2d.hip", "kernels2d_ym.hip", "kernels3d.hip", "kernels3d_mfma.hip", "kernels3d_tb2.hip",
            "kernels3d_vc.hip", "kernels3d_h2.hip", "kernels2d_h2.hip",
-           "kernels_wave.hip", "kernels_wave_tb2.hip", "kernels_wave_ring.hip", "kernels_wave_ring_adj.hip", "batched.hip", "autotune.hip",
+           "kernels_wave.hip", "kernels_wave_tb2.hip", "kernels_wave_ring.hip", "kernels_wave_f64.hip", "kernels_wave_ring_adj.hip", "batched.hip", "autotune.hip",
            "noalloc.hip"]
 
 # Packed FP32 instructions are disabled for every device pass: the compiler

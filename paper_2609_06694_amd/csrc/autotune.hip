@@ -668,6 +668,10 @@ st_status stencil_autotune(st_plan* plan, void* scratch, size_t scratch_bytes, v
         set_error("scratch is NULL");
         return ST_EWORKSPACE;
     }
+    if (!plan->batched && plan->prob.update == ST_WAVE && plan->prob.dtype == ST_F64) {
+        set_error("an f64 wave plan keeps its map configuration");
+        return ST_EUNSUPPORTED;
+    }
     hipStream_t s = (hipStream_t)stream;
     TuneStats st;
     if (!plan->batched) {

@@ -107,6 +107,16 @@ static LaunchCfg default_cfg(const CaseKey& k) {
         c.zchunk = kAutoChunk;
         return c;
     }
+    if (k.update == ST_WAVE && k.dtype == 2) {
+        // FP64 leapfrog: the z-march with queued partial sums, 64 x 8 tiles
+        // (its radius-4 queue and weights take about 220 VGPRs at 2 rows per
+        // thread).
+        c.variant = ST_VARIANT_WAVE3D;
+        c.tile_y = 8;
+        c.tsteps = 1;
+        c.zchunk = kAutoChunk;
+        return c;
+    }
     if (k.update == ST_WAVE) {
         c.variant = ST_VARIANT_WAVE3D_LDS;
         c.tile_y = 32;
@@ -258,6 +268,7 @@ void dispatch_store(const CaseKey& k, const LaunchCfg& c, bool persist) {
 // kernels (adjoint, gradient) hold about two waves per SIMD; the linear
 // z-march runs four 4-wave workgroups.
 static int resident_wgs(const st_problem& p, const LaunchCfg& c) {
+    if (p.update == ST_WAVE && p.dtype == ST_F64) return c.tile_y >= 16 ? 1 : 2;   // 4-wave groups, 1-2 waves per SIMD
     if (p.update == ST_WAVE && c.variant == ST_VARIANT_WAVE3D_LDS)
         return c.tile_y >= 32 ? 1 : (c.tile_y >= 16 ? 2 : 3);
     if (p.update == ST_WAVE) return c.tile_y >= 32 ? 1 : 2;   // adjoint/gradient: ~2 waves per SIMD
@@ -304,6 +315,9 @@ bool adj_cfg_legal(const st_problem& p, const LaunchCfg& c) {
 }
 
 bool cfg_legal(const st_problem& p, const LaunchCfg& c) {
+    if (p.update == ST_WAVE && p.dtype == ST_F64)   // one FP64 kernel: 8- or 16-row tiles, one step
+        return c.variant == ST_VARIANT_WAVE3D && (c.tile_y == 8 || c.tile_y == 16) && c.tile_x == 0 &&
+               c.zchunk >= 0 && c.tsteps >= 0 && c.tsteps <= 1;
     if (p.update == ST_WAVE) {
         if (c.tsteps == 2 && !wave3d_tb2_supported(p.radius)) return false;
         if (c.variant == ST_VARIANT_WAVE3D_LDS)   // tile_x: planes staged per barrier (0 or 1: one, 2: two)

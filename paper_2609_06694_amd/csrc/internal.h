@@ -70,6 +70,27 @@ __device__ __forceinline__ float sponge_ramp(int i, int n, int w, float s, float
     return s * q * q;
 }
 
+// Operands of one FP64 forward leapfrog step (fields as in WaveLaunch, in
+// binary64).
+struct WaveLaunchF64 {
+    const double* prev;     // u_{t-1}
+    const double* cur;      // u_t
+    double* next;           // u_{t+1}; may alias prev
+    const double* kappa;
+    int src_x, src_y, src_z;  // src_x < 0 = none
+    const double* src_amp;  // device pointer to the amplitude added at the source
+    int rec_z;
+    double* trace_t;        // plane written with u_{t+1}[rec_z] or null
+    int sp_w;               // absorbing layer width (0 = none) and strength
+    double sp_s;
+};
+
+// Star weights in binary64, in the compact star layout of Taps (c[0] the
+// centre, then the x, y and z arms by star_x / star_y / star_z).
+struct TapsD {
+    double c[6 * kMaxRadius + 1];
+};
+
 // Two fused forward leapfrog steps: (u_{t-1}, u_t) -> (u_{t+1}, u_{t+2}).
 // out1/out2 must not alias prev/cur (other workgroups read their halos).
 struct WaveTB2 {
@@ -130,6 +151,9 @@ bool zm3d_tb2_supported(int r, int shape);
 hipError_t launch_vc3d(const Geom& g, const LaunchCfg& cfg, const void* in, void* out, const void* fields,
                        bool adjoint, hipStream_t stream);
 bool vc3d_supported(int r, int shape);
+// One FP64 forward leapfrog step (cfg.tile_y: 8 or 16 rows per workgroup).
+hipError_t launch_wave3d_f64(const Geom& g, const LaunchCfg& cfg, const TapsD& taps, const WaveLaunchF64& w,
+                             hipStream_t stream);
 
 // One launch of a 3D linear sweep (k = 1 or 2 fused steps) through the
 // kernel family the configuration names.

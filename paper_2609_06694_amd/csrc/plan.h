@@ -12,6 +12,7 @@ struct st_plan {
     std::vector<float> dense;       // (2r+1)^ndim coefficients as given
     stk::Taps taps;                 // compact forward taps
     stk::Taps taps_t;               // compact transposed taps (offsets negated)
+    stk::TapsD taps64;              // ST_F64 wave plans: the star weights in binary64
     stk::LaunchCfg cfg;
     stk::LaunchCfg adj_cfg;         // wave adjoint and gradient steps (direct-form kernel)
     int ckpt_every;

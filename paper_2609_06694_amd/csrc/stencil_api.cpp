@@ -38,6 +38,11 @@ size_t cells_of(const st_problem& p) { return (size_t)p.n[0] * (size_t)p.n[1] * 
 
 size_t grid_bytes(const st_problem& p) { return cells_of(p) * elem_bytes(p.dtype); }
 
+// The f32 views of a wave plan's operands (ST_F64 plans take run_wave_f64).
+const float* wkappa(const st_wave_args* wa) { return static_cast<const float*>(wa->kappa); }
+const float* wwavelet(const st_wave_args* wa) { return static_cast<const float*>(wa->wavelet); }
+float* wtraces(const st_wave_args* wa) { return static_cast<float*>(wa->traces); }
+
 bool in_shape(int ndim, int shape, int r, int idx) {
     const int w = 2 * r + 1;
     const int dx = idx % w - r;
@@ -127,7 +132,8 @@ st_status validate(const st_problem* p) {
     } else if (p->update == ST_WAVE) {
         if (p->ndim != 3 || p->shape != ST_STAR)
             ST_FAIL(ST_EUNSUPPORTED, "the wave update needs a 3D star stencil");
-        if (p->dtype != ST_F32) ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 storage");
+        if (p->dtype != ST_F32 && p->dtype != ST_F64)
+            ST_FAIL(ST_EUNSUPPORTED, "the wave update needs f32 or f64 storage");
     } else {
         if (!p->coeffs) ST_FAIL(ST_EINVAL, "coefficients are NULL");
         if (p->ndim == 2 && !tb2d_supported(p->radius, p->shape))
@@ -172,6 +178,27 @@ st_status build_plan(const st_problem* p, const st_plan_opts* opts, st_plan** ou
         // spurious multiple of u to every evaluation.
         pl->taps.sum = 0.f;
         pl->taps_t.sum = 0.f;
+    }
+    memset(&pl->taps64, 0, sizeof pl->taps64);
+    if (p->update == ST_WAVE && p->dtype == ST_F64) {
+        // Binary64 star weights: the caller's (exact as doubles) or the
+        // built-in Laplacian's rationals, each rounded once to binary64.
+        const int r = p->radius;
+        auto slot = [r](int d) { return d < 0 ? 1 + (d + r) : r + d; };
+        if (p->coeffs) {
+            pl->taps64.c[0] = (double)pl->taps.c[0];
+            for (int i = 1; i <= 6 * r; ++i) pl->taps64.c[i] = (double)pl->taps.c[i];
+        } else {
+            const double* f = kFd2[r - 1];
+            pl->taps64.c[0] = 3.0 * f[0];
+            for (int d = -r; d <= r; ++d) {
+                if (d == 0) continue;
+                const double v = f[d < 0 ? -d : d];
+                pl->taps64.c[slot(d)] = v;
+                pl->taps64.c[2 * r + slot(d)] = v;
+                pl->taps64.c[4 * r + slot(d)] = v;
+            }
+        }
     }
     pl->iso = false;
     if (p->shape == ST_STAR) {
@@ -336,8 +363,8 @@ st_status run_wave_tb2(const st_plan* pl, const void* u_in, void* u_out, int ste
                    (float*)((char*)ws + 3 * gb)};
     const float* prev = P;
     const float* cur = (const float*)u_in;
-    const bool has_src = wa->src[0] >= 0 && wa->wavelet;
-    const bool rec = wa->rec_z >= 0 && wa->traces;
+    const bool has_src = wa->src[0] >= 0 && wwavelet(wa);
+    const bool rec = wa->rec_z >= 0 && wtraces(wa);
     int t = 0;
     if (steps % 2 == 1) {
         // One single step in place on the prev buffer: (P, I) -> (I, P).
@@ -345,16 +372,16 @@ st_status run_wave_tb2(const st_plan* pl, const void* u_in, void* u_out, int ste
         w.prev = P;
         w.cur = cur;
         w.next = P;
-        w.kappa = wa->kappa;
+        w.kappa = wkappa(wa);
         if (has_src) {
             w.src_x = (int)wa->src[0];
             w.src_y = (int)wa->src[1];
             w.src_z = (int)wa->src[2];
-            w.src_amp = wa->wavelet;
+            w.src_amp = wwavelet(wa);
         }
         if (rec) {
             w.rec_z = (int)wa->rec_z;
-            w.trace_t = wa->traces;
+            w.trace_t = wtraces(wa);
         }
         HIP_TRY(wave_forward_launch(pl, w, s));
         prev = cur;
@@ -365,12 +392,12 @@ st_status run_wave_tb2(const st_plan* pl, const void* u_in, void* u_out, int ste
     if (L == 1 && (prev == P || cur == P || cur == O)) {
         // The only fused launch cannot write A; land in B and copy.
         WaveTB2 w{};
-        w.prev = prev; w.cur = cur; w.out1 = W[0]; w.out2 = W[1]; w.kappa = wa->kappa;
+        w.prev = prev; w.cur = cur; w.out1 = W[0]; w.out2 = W[1]; w.kappa = wkappa(wa);
         w.src_x = has_src ? (int)wa->src[0] : -1; w.src_y = (int)wa->src[1]; w.src_z = (int)wa->src[2];
-        w.amp1 = has_src ? wa->wavelet + t : nullptr; w.amp2 = has_src ? wa->wavelet + t + 1 : nullptr;
+        w.amp1 = has_src ? wwavelet(wa) + t : nullptr; w.amp2 = has_src ? wwavelet(wa) + t + 1 : nullptr;
         w.rec_z = rec ? (int)wa->rec_z : -1;
-        w.trace1 = rec ? wa->traces + (size_t)t * plane : nullptr;
-        w.trace2 = rec ? wa->traces + (size_t)(t + 1) * plane : nullptr;
+        w.trace1 = rec ? wtraces(wa) + (size_t)t * plane : nullptr;
+        w.trace2 = rec ? wtraces(wa) + (size_t)(t + 1) * plane : nullptr;
         HIP_TRY(launch_wave3d_tb2(g, pl->cfg, pl->taps, w, s));
         HIP_TRY(hipMemcpyAsync(P, W[0], cells * 4, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(O, W[1], cells * 4, hipMemcpyDeviceToDevice, s));
@@ -384,12 +411,12 @@ st_status run_wave_tb2(const st_plan* pl, const void* u_in, void* u_out, int ste
         else if (back % 2 == 1) { o1 = W[0]; o2 = W[1]; }
         else { o1 = W[2]; o2 = W[3]; }
         WaveTB2 w{};
-        w.prev = prev; w.cur = cur; w.out1 = o1; w.out2 = o2; w.kappa = wa->kappa;
+        w.prev = prev; w.cur = cur; w.out1 = o1; w.out2 = o2; w.kappa = wkappa(wa);
         w.src_x = has_src ? (int)wa->src[0] : -1; w.src_y = (int)wa->src[1]; w.src_z = (int)wa->src[2];
-        w.amp1 = has_src ? wa->wavelet + t : nullptr; w.amp2 = has_src ? wa->wavelet + t + 1 : nullptr;
+        w.amp1 = has_src ? wwavelet(wa) + t : nullptr; w.amp2 = has_src ? wwavelet(wa) + t + 1 : nullptr;
         w.rec_z = rec ? (int)wa->rec_z : -1;
-        w.trace1 = rec ? wa->traces + (size_t)t * plane : nullptr;
-        w.trace2 = rec ? wa->traces + (size_t)(t + 1) * plane : nullptr;
+        w.trace1 = rec ? wtraces(wa) + (size_t)t * plane : nullptr;
+        w.trace2 = rec ? wtraces(wa) + (size_t)(t + 1) * plane : nullptr;
         HIP_TRY(launch_wave3d_tb2(g, pl->cfg, pl->taps, w, s));
         prev = o1;
         cur = o2;
@@ -427,17 +454,17 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
         w.prev = prev;
         w.cur = cur;
         w.next = next;
-        w.kappa = wa->kappa;
+        w.kappa = wkappa(wa);
         if (!adjoint) {
-            if (wa->src[0] >= 0 && wa->wavelet) {
+            if (wa->src[0] >= 0 && wwavelet(wa)) {
                 w.src_x = (int)wa->src[0];
                 w.src_y = (int)wa->src[1];
                 w.src_z = (int)wa->src[2];
-                w.src_amp = wa->wavelet + t;
+                w.src_amp = wwavelet(wa) + t;
             }
-            if (wa->rec_z >= 0 && wa->traces) {
+            if (wa->rec_z >= 0 && wtraces(wa)) {
                 w.rec_z = (int)wa->rec_z;
-                w.trace_t = wa->traces + (size_t)t * plane;
+                w.trace_t = wtraces(wa) + (size_t)t * plane;
             }
             HIP_TRY(wave_forward_launch(pl, w, s));
         } else {
@@ -460,10 +487,62 @@ st_status run_wave(const st_plan* pl, bool adjoint, const void* u_in, void* u_ou
     return ST_OK;
 }
 
+// FP64 forward leapfrog, with run_wave's buffer schedule (u_T ends in u_out,
+// u_{T-1} in the caller's prev buffer).
+st_status run_wave_f64(const st_plan* pl, const void* u_in, void* u_out, int steps, const st_wave_args* wa,
+                       void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t gb = grid_bytes(pl->prob);
+    double* P = static_cast<double*>(wa->u_prev);
+    double* O = static_cast<double*>(u_out);
+    const double* cur = static_cast<const double*>(u_in);
+    if (steps == 0) {
+        if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, gb, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    if (u_in == u_out && (steps % 2) == 1) {
+        if (!ws || ws_bytes < gb) ST_FAIL(ST_EWORKSPACE, "workspace of %zu bytes needed", gb);
+        HIP_TRY(hipMemcpyAsync(ws, u_in, gb, hipMemcpyDeviceToDevice, s));
+        cur = static_cast<const double*>(ws);
+    }
+    const Geom g = plan_geom(pl);
+    const double* prev = P;
+    const size_t plane = (size_t)pl->prob.n[0] * pl->prob.n[1];
+    for (int t = 0; t < steps; ++t) {
+        double* next = ((steps - (t + 1)) % 2 == 0) ? O : P;
+        WaveLaunchF64 w;
+        memset(&w, 0, sizeof w);
+        w.prev = prev;
+        w.cur = cur;
+        w.next = next;
+        w.kappa = static_cast<const double*>(wa->kappa);
+        w.src_x = -1;
+        w.rec_z = -1;
+        if (wa->src[0] >= 0 && wa->wavelet) {
+            w.src_x = (int)wa->src[0];
+            w.src_y = (int)wa->src[1];
+            w.src_z = (int)wa->src[2];
+            w.src_amp = static_cast<const double*>(wa->wavelet) + t;
+        }
+        if (wa->rec_z >= 0 && wa->traces) {
+            w.rec_z = (int)wa->rec_z;
+            w.trace_t = static_cast<double*>(wa->traces) + (size_t)t * plane;
+        }
+        if (wa->sponge_width > 0) {
+            w.sp_w = wa->sponge_width;
+            w.sp_s = (double)wa->sponge_strength;
+        }
+        HIP_TRY(launch_wave3d_f64(g, pl->cfg, pl->taps64, w, s));
+        prev = cur;
+        cur = next;
+    }
+    if (prev != P) HIP_TRY(hipMemcpyAsync(P, prev, gb, hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
 st_status check_wave_args(const st_plan* pl, const st_wave_args* wa, bool need_kappa) {
     if (!wa) ST_FAIL(ST_EINVAL, "wave plan needs st_wave_args");
     if (!wa->u_prev) ST_FAIL(ST_EINVAL, "wave->u_prev is NULL");
-    if (need_kappa && !wa->kappa) ST_FAIL(ST_EINVAL, "wave->kappa is NULL");
+    if (need_kappa && !wkappa(wa)) ST_FAIL(ST_EINVAL, "wkappa(wave) is NULL");
     const st_problem& p = pl->prob;
     if (wa->src[0] >= 0) {
         for (int a = 0; a < 3; ++a)
@@ -479,7 +558,8 @@ st_status check_wave_args(const st_plan* pl, const st_wave_args* wa, bool need_k
     }
     if (wa->sponge_width > 0) {
         if (p.boundary != ST_ZERO) ST_FAIL(ST_EUNSUPPORTED, "the absorbing layer needs the zero frame");
-        if (pl->cfg.variant != ST_VARIANT_WAVE3D_LDS || pl->adj_cfg.variant != ST_VARIANT_WAVE3D_LDS)
+        if (p.dtype != ST_F64 &&
+            (pl->cfg.variant != ST_VARIANT_WAVE3D_LDS || pl->adj_cfg.variant != ST_VARIANT_WAVE3D_LDS))
             ST_FAIL(ST_EUNSUPPORTED, "the absorbing layer is fused into the LDS-ring kernels only");
     }
     return ST_OK;
@@ -562,6 +642,8 @@ st_status stencil_apply(const st_plan* plan, const void* u_in, void* u_out, int3
         if (s != ST_OK) return s;
         if (wave->u_prev == u_in || wave->u_prev == u_out)
             ST_FAIL(ST_EINVAL, "wave->u_prev must not alias u_in or u_out");
+        if (plan->prob.dtype == ST_F64)
+            return run_wave_f64(plan, u_in, u_out, steps, wave, workspace, ws_bytes, as_stream(stream));
         return run_wave(plan, false, u_in, u_out, steps, wave, workspace, ws_bytes, as_stream(stream));
     }
     if (plan->prob.update == ST_VARCOEF) ST_FAIL(ST_EINVAL, "variable-coefficient plan: use stencil_apply_varcoef");
@@ -625,6 +707,7 @@ st_status stencil_apply_adjoint(const st_plan* plan, const void* v_in, void* v_o
     if (!v_in || !v_out) ST_FAIL(ST_EINVAL, "grid pointer is NULL");
     if (steps < 0) ST_FAIL(ST_EINVAL, "steps must be >= 0");
     if (plan->prob.update == ST_WAVE) {
+        if (plan->prob.dtype == ST_F64) ST_FAIL(ST_EUNSUPPORTED, "the wave adjoint takes f32 plans");
         st_status s = check_wave_args(plan, wave, true);
         if (s != ST_OK) return s;
         if (wave->u_prev == v_in || wave->u_prev == v_out)
@@ -718,6 +801,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
     stk::set_error("%s", "");
     if (!plan) ST_FAIL(ST_EINVAL, "plan is NULL");
     if (plan->prob.update != ST_WAVE) ST_FAIL(ST_EINVAL, "gradient needs a wave plan");
+    if (plan->prob.dtype == ST_F64) ST_FAIL(ST_EUNSUPPORTED, "the wave gradient takes f32 plans");
     if (!u0 || !dkappa || !loss_dev) ST_FAIL(ST_EINVAL, "u0, dkappa and loss must be non-NULL");
     if (steps < 1) ST_FAIL(ST_EINVAL, "steps must be >= 1");
     st_status st = check_wave_args(plan, wave, true);
@@ -736,8 +820,8 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
     };
     float* scratch[3] = {(float*)(ws + L.scratch_off), (float*)(ws + L.scratch_off + L.grid),
                          (float*)(ws + L.scratch_off + 2 * L.grid)};
-    float* traces = wave->traces ? wave->traces : (float*)(ws + L.traces_off);
-    const bool has_src = wave->src[0] >= 0 && wave->wavelet;
+    float* traces = wtraces(wave) ? wtraces(wave) : (float*)(ws + L.traces_off);
+    const bool has_src = wave->src[0] >= 0 && wwavelet(wave);
 
     auto fwd_step = [&](const float* prev, const float* cur, float* next, int t, bool record,
                         float* lap_out = nullptr) {
@@ -749,13 +833,13 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
         w.prev = prev;
         w.cur = cur;
         w.next = next;
-        w.kappa = wave->kappa;
+        w.kappa = wkappa(wave);
         w.lap_out = lap_out;
         if (has_src) {
             w.src_x = (int)wave->src[0];
             w.src_y = (int)wave->src[1];
             w.src_z = (int)wave->src[2];
-            w.src_amp = wave->wavelet + t;
+            w.src_amp = wwavelet(wave) + t;
         }
         if (record) {
             w.rec_z = (int)wave->rec_z;
@@ -825,7 +909,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
             w.prev = l_next2;
             w.cur = l_next;
             w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place
-            w.kappa = wave->kappa;
+            w.kappa = wkappa(wave);
             w.grad = dkappa;
             w.lap = t <= T - 1 ? lap(t, t0) : nullptr;   // lambda_{T+1} = 0: no term at t = T
             w.rec_z = (int)wave->rec_z;
@@ -859,7 +943,7 @@ st_status stencil_wave_gradient(const st_plan* plan, const void* u0, const st_wa
             w.prev = l_next2;
             w.cur = l_next;
             w.next = l_next2;   // lambda_t overwrites lambda_{t+2} in place
-            w.kappa = wave->kappa;
+            w.kappa = wkappa(wave);
             w.u = state(t);
             w.grad = dkappa;
             w.rec_z = (int)wave->rec_z;

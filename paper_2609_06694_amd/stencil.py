@@ -261,14 +261,22 @@ class WaveModel(_Plan):
     gamma = sum over axes of strength ((width - e) / width)^2 within `width`
     cells of each face, and the step u_{t+1} = A (2u_t + kappa L u_t) -
     B u_{t-1} with A = 1/(1 + gamma/2), B = (1 - gamma/2) A; it applies to
-    the forward, adjoint and gradient calls alike."""
+    the forward, adjoint and gradient calls alike.
 
-    def __init__(self, n: Sequence[int], radius: int = 4, boundary="zero", coeffs=None, sponge=None, **opts):
+    dtype="f64" stores every field (state, kappa, wavelet, traces) in
+    binary64 and runs the forward leapfrog in binary64; the adjoint and the
+    gradient take f32 models only."""
+
+    def __init__(self, n: Sequence[int], radius: int = 4, boundary="zero", coeffs=None, sponge=None,
+                 dtype: str = "f32", **opts):
         super().__init__()
+        if dtype not in ("f32", "f64"):
+            raise ValueError("the wave model stores f32 or f64")
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
         self.sponge = (0, 0.0) if sponge is None else (int(sponge[0]), float(sponge[1]))
         self.n = tuple(int(v) for v in n)
         keep: list = []
-        prob = _problem(3, self.n, _abi.ST_STAR, radius, coeffs, _abi.ST_F32, _enum(_BC, boundary),
+        prob = _problem(3, self.n, _abi.ST_STAR, radius, coeffs, self.dtype_code, _enum(_BC, boundary),
                         _abi.ST_WAVE, keep)
         o = _opts(**opts) if opts else None
         check(lib().stencil_plan(ctypes.byref(prob), ctypes.byref(o) if o is not None else None,
@@ -281,15 +289,17 @@ class WaveModel(_Plan):
         return self._describe(lib().stencil_plan_describe_reverse)
 
     def _chk(self, ops):
-        """Each (name, tensor, shape, min_len) must be a contiguous float32
-        device tensor of that shape (or, with min_len, at least that many
-        elements); None passes.  Shapes and lengths are checked for every
-        operand before any placement check."""
+        """Each (name, tensor, shape, min_len) must be a contiguous device
+        tensor of the model's storage type (target: float32) and of that
+        shape (or, with min_len, at least that many elements); None passes.
+        Shapes and lengths are checked for every operand before any
+        placement check."""
         for name, t, shape, min_len in ops:
             if t is None:
                 continue
-            if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
-                raise ValueError(f"{name} must be a float32 tensor")
+            want = torch.float32 if name == "target" else self.torch_dtype
+            if not isinstance(t, torch.Tensor) or t.dtype != want:
+                raise ValueError(f"{name} must be a {want} tensor")
             if shape is not None and tuple(t.shape) != tuple(shape):
                 raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
             if min_len is not None and t.numel() < min_len:
@@ -330,7 +340,7 @@ class WaveModel(_Plan):
         out = torch.empty_like(u0) if out is None else out
         traces = None
         if record and rec_z >= 0:
-            traces = torch.empty((steps, self.n[1], self.n[0]), dtype=torch.float32, device=u0.device)
+            traces = torch.empty((steps, self.n[1], self.n[0]), dtype=self.torch_dtype, device=u0.device)
         wa = self._args(prev, kappa, src, wavelet, rec_z, traces)
         ws, nb = self._workspace(u0.device, self.workspace_bytes(steps))
         check(lib().stencil_apply(self._h, _ptr(u0), _ptr(out), int(steps), ctypes.byref(wa), ws, nb,

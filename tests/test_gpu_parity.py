@@ -610,6 +610,78 @@ def test_wave_two_planes_per_barrier_bitwise(st, bc, ty, zc):
 
 
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("r,ty,zc", [(4, 8, 0), (4, 16, 9), (2, 8, 5), (1, 16, 0), (3, 8, 16)])
+@pytest.mark.parametrize("aniso", [False, True])
+def test_wave_f64_forward_vs_oracle(st, bc, r, ty, zc, aniso):
+    """FP64 leapfrog (binary64 fields, weights and arithmetic) with source and
+    receiver against the FP64 oracle at the f64 gate, on ragged tiles and z
+    chunks; both the built-in Laplacian (its rationals rounded once to
+    binary64 on both sides) and an anisotropic star given in f32."""
+    rng = np.random.default_rng(41 + r)
+    n = (75, 41, 33)
+    nx, ny, nz = n
+    kappa = rng.uniform(0.05, 0.2, (nz, ny, nx))
+    u0 = wl.gaussian_pulse(n, (nx // 2, ny // 3, nz // 2), 3.0).astype(np.float64)
+    up = u0 * 0.97
+    steps, src, rec = 7, (30, 20, 17), 5
+    wav = wl.ricker(steps, 4.0).astype(np.float64)
+    bcode = wl.ZERO if bc == "zero" else wl.PERIODIC
+    lap = None
+    if aniso:
+        w = 2 * r + 1
+        lap = oracle.laplacian3d(r)
+        for j in range(1, r + 1):
+            lap[(r * w + r) * w + r + j] *= 1.0 + 0.1 * j
+            lap[(r * w + r - j) * w + r] *= 1.0 - 0.05 * j
+        lap = lap.astype(np.float32)
+    m = st.WaveModel(n, radius=r, boundary=bc, coeffs=lap, dtype="f64", tile_y=ty, zchunk=zc)
+    d = m.describe()
+    assert (d["variant"], d["tile_y"], d["tsteps"]) == ("wave3d", ty, 1)
+    uT, uT1, tr = m.forward(_dev(u0), _dev(up), _dev(kappa), steps, src=src, wavelet=_dev(wav), rec_z=rec,
+                            record=True)
+    assert uT.dtype == torch.float64 and tr.dtype == torch.float64
+    ra, rb, rtr = oracle.wave_forward(up, u0, kappa, steps, r=r, boundary=bcode, src=src, wavelet=wav, rec_z=rec,
+                                      lap=None if lap is None else lap.astype(np.float64))
+    e = max(rel_l2(_host(uT), rb), rel_l2(_host(uT1), ra), rel_l2(_host(tr), rtr))
+    print(f"f64 wave r={r} {bc} ty={ty} zc={zc} aniso={aniso}: rel-L2 {e:.2e}")
+    assert e <= TOL["f64"]
+
+
+@pytest.mark.parametrize("steps", [1, 4, 5])
+def test_wave_f64_sponge_inplace_and_f32_contrast(st, steps):
+    """FP64 leapfrog with the absorbing layer against the oracle's damped
+    recursion, in place (u_in == u_out, odd and even step counts); and the
+    same case through the f32 model, whose binary32 storage sits orders of
+    magnitude above the f64 gate (so the f64 path is not f32 in disguise)."""
+    rng = np.random.default_rng(51)
+    n = (67, 35, 30)
+    nx, ny, nz = n
+    W, s = 6, 1.2
+    kappa = rng.uniform(0.05, 0.2, (nz, ny, nx))
+    u0 = wl.gaussian_pulse(n, (nx // 3, ny // 3, nz // 2), 3.0).astype(np.float64)
+    up = u0 * 0.98
+    src = (nx // 2, ny // 2, nz // 2)
+    wav = wl.ricker(steps, 4.0).astype(np.float64)
+    # The strength crosses the C ABI as a binary32 value; the layer then
+    # evaluates in binary64 from exactly that value.
+    gamma = oracle.sponge_profile((nz, ny, nx), W, float(np.float32(s)))
+    ra, rb, _ = oracle.wave_forward_damped(up, u0, kappa, gamma, steps, src=src, wavelet=wav)
+    m = st.WaveModel(n, dtype="f64", sponge=(W, s))
+    u = _dev(u0)
+    prev = _dev(up)
+    m.forward(u, prev, _dev(kappa), steps, src=src, wavelet=_dev(wav), out=u, prev_inout=True)
+    e = max(rel_l2(_host(u), rb), rel_l2(_host(prev), ra))
+    m32 = st.WaveModel(n, sponge=(W, s))
+    u32, p32, _ = m32.forward(_dev(u0.astype(np.float32)), _dev(up.astype(np.float32)),
+                              _dev(kappa.astype(np.float32)), steps, src=src,
+                              wavelet=_dev(wav.astype(np.float32)))
+    e32 = max(rel_l2(_host(u32), rb), rel_l2(_host(p32), ra))
+    print(f"f64 sponge steps={steps}: rel-L2 {e:.2e} (f32 model: {e32:.2e})")
+    assert e <= TOL["f64"]
+    assert e32 > 1e3 * TOL["f64"]
+
+
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
 @pytest.mark.parametrize("n,ty,zc", [((75, 41, 33), 8, 0), ((130, 37, 29), 16, 9), ((20, 9, 11), 8, 4)])
 @pytest.mark.parametrize("steps", [2, 3, 4, 7])
 def test_wave_two_step_fused_vs_oracle(st, bc, n, ty, zc, steps):
