@@ -18,6 +18,32 @@
 
 namespace stk {
 
+// In-plane part of the star (centre, x and y arms) at this thread's RY rows
+// of a staged binary64 plane.
+template <int R, int RY, int NW>
+__device__ __forceinline__ void star_plane_f64(const double* __restrict__ tile, const TapsD& tp,
+                                               double (&p)[RY]) {
+    using G = PlaneGeom<R, RY, NW>;
+    const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
+    const double* base = tile + (ty * RY) * G::W + R + tx;
+    double col[RY + 2 * R];
+#pragma unroll
+    for (int j = 0; j < RY + 2 * R; ++j) col[j] = base[j * G::W];
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const double* row = tile + (R + ty * RY + i) * G::W + R + tx;
+        double a = tp.c[0] * col[i + R];
+#pragma unroll
+        for (int d = 1; d <= R; ++d) {
+            a = fma(tp.c[star_y<R>(-d)], col[i + R - d], a);
+            a = fma(tp.c[star_y<R>(d)], col[i + R + d], a);
+            a = fma(tp.c[star_x<R>(-d)], row[-d], a);
+            a = fma(tp.c[star_x<R>(d)], row[d], a);
+        }
+        p[i] = a;
+    }
+}
+
 template <int R, int BC, int RY, int NW, int D, bool SP>
 __global__ __launch_bounds__(NW * kWave) void wave3d_f64_kernel(WaveLaunchF64 w, int nx, int ny, int nz, int zc,
                                                                 int tiles_x, int tiles_y, TapsD tp) {
@@ -89,7 +115,7 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_f64_kernel(WaveLaunchF64 w,
             __syncthreads();
 
             double p[RY];
-            star_plane<R, RY, NW>(t, tp, p);
+            star_plane_f64<R, RY, NW>(t, tp, p);
             // Plane zp feeds output zo = zp - e with the weight of offset +e.
 #pragma unroll
             for (int i = 0; i < RY; ++i) acc[R][i] += p[i];

@@ -333,8 +333,8 @@ __device__ __forceinline__ void star_plane_iso(const float* __restrict__ tile, c
 }
 
 // In-plane star contribution (centre, x and y arms) for this thread's RY rows.
-template <int R, int RY, int NW = 4, typename A = float, typename TT = Taps>
-__device__ __forceinline__ void star_plane(const A* __restrict__ tile, const TT& tp, A (&p)[RY]) {
+template <int R, int RY, int NW = 4, typename A = float>
+__device__ __forceinline__ void star_plane(const A* __restrict__ tile, const Taps& tp, A (&p)[RY]) {
     using G = PlaneGeom<R, RY, NW>;
     const int tx = threadIdx.x & (kWave - 1), ty = threadIdx.x >> 6;
     const A* base = tile + (ty * RY) * G::W + R + tx;   // row ty*RY - R + R, column tx
