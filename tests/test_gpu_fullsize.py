@@ -202,7 +202,8 @@ def test_fullsize_varcoef2d(st):
 def test_fullsize_wave3d(st):
     """The headline workload (512^3, 20 steps, zero frame) compared with the
     oracle on every cell of u_T and u_{T-1}, with the margin printed beside
-    the binary32 storage floor of the same run."""
+    the binary32 storage floor of the same run; and the same inputs through
+    the f64 leapfrog against the same oracle result at the f64 gate."""
     case = wl.wave3d(n=512, steps=20)
     m = st.WaveModel(case.n, radius=4, boundary="zero")
     out, prev, _ = m.forward(torch.from_numpy(case.u0).cuda(), torch.from_numpy(case.u_prev).cuda(),
@@ -213,6 +214,16 @@ def test_fullsize_wave3d(st):
     ra, rb, _ = oracle.wave_forward(case.u_prev, case.u0, case.kappa, T)
     e = max(rel_l2(got, rb), rel_l2(gotp, ra))
     del got, gotp
+    torch.cuda.empty_cache()
+    m64 = st.WaveModel(case.n, radius=4, boundary="zero", dtype="f64")
+    o64, p64, _ = m64.forward(torch.from_numpy(case.u0).cuda().double(),
+                              torch.from_numpy(case.u_prev).cuda().double(),
+                              torch.from_numpy(case.kappa).cuda().double(), case.steps)
+    e64 = max(rel_l2(o64.cpu().numpy(), rb), rel_l2(p64.cpu().numpy(), ra))
+    del o64, p64
+    torch.cuda.empty_cache()
+    print(f"wave 512^3 x{T} f64 all cells: rel-L2 {e64:.3e} (gate 1e-12)")
+    assert e64 <= 1e-12
     fa, fb, _ = oracle.wave_forward(case.u_prev, case.u0, case.kappa, T, storage="binary32")
     floor = max(rel_l2(fb, rb), rel_l2(fa, ra))
     print(f"wave 512^3 x{T} all cells: rel-L2 {e:.3e} (gate 1e-5, margin {1e-5 / e:.1f}x; "
