@@ -188,7 +188,8 @@ st_status stencil_plan_describe_reverse(const st_plan *plan, int32_t *variant, i
 /* The coefficients a plan applies (Section 2.1: the case's weights c_d).
  * `dense` (HOST, may be NULL) receives min(count, (2r+1)^ndim) floats in the
  * layout of st_problem.coeffs; for an ST_WAVE plan created without
- * coefficients these are the f32-rounded weights of the built-in Laplacian.
+ * coefficients these are the f32-rounded weights of the built-in Laplacian
+ * (an ST_F64 wave plan applies its rationals rounded to binary64 instead).
  * *weight_sum (may be NULL) receives the weight sum the difference-form
  * kernels use, sum_{d != 0} c_d (u(x+d) - u(x)) + (weight sum) u(x): the
  * FP64 sum of the given weights, and exactly 0 for the built-in Laplacian

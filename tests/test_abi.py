@@ -386,6 +386,28 @@ def test_binding_rejects_misshaped_wave_and_batch_operands(L):
         bs.apply([torch.zeros((16, 20))], 2, outs=[])
 
 
+def test_binding_f64_wave_operand_types(L):
+    """An f64 wave model takes float64 state, kappa, wavelet and traces
+    (float32 target), checked on the host; other storage types are refused."""
+    import torch
+    from paper_2609_06694_amd import stencil
+    n = (12, 10, 9)
+    with pytest.raises(ValueError, match="f32 or f64"):
+        stencil.WaveModel(n, dtype="f16")
+    m = stencil.WaveModel(n, dtype="f64")
+    assert m.describe()["variant"] == "wave3d"
+    g64 = torch.zeros(n[::-1], dtype=torch.float64)
+    g32 = torch.zeros(n[::-1], dtype=torch.float32)
+    with pytest.raises(ValueError, match="float64"):
+        m.forward(g32, g64, g64, 3)
+    with pytest.raises(ValueError, match="float64"):
+        m.forward(g64, g64, g32, 3)
+    with pytest.raises(ValueError, match="float64"):
+        m.forward(g64, g64, g64, 3, src=(1, 1, 1), wavelet=torch.zeros(3))
+    with pytest.raises(ValueError, match="device"):   # right types and shapes, host memory
+        m.forward(g64, g64, g64, 3, src=(1, 1, 1), wavelet=torch.zeros(3, dtype=torch.float64))
+
+
 def test_sponge_argument_checks_before_device(L):
     """The absorbing layer needs the zero frame and the LDS-ring kernels;
     width and strength are range-checked on the host."""
