@@ -174,10 +174,11 @@ __global__ __launch_bounds__(NW * kWave) void wave3d_f64_kernel(WaveLaunchF64 w,
     }
 }
 
-// Two planes in flight; 64 x 8 tiles (two rows per thread) or 64 x 16 (four).
-template <int R, int BC, int RY, bool SP>
+// Two planes in flight, two rows per thread; 64 x 8 tiles of four waves or
+// 64 x 16 of eight (the same registers per thread, a smaller halo share).
+template <int R, int BC, int NW, bool SP>
 static hipError_t go(const Geom& g, int zc, const TapsD& tp, const WaveLaunchF64& w, hipStream_t s) {
-    constexpr int NW = 4, D = 2;
+    constexpr int RY = 2, D = 2;
     using G = PlaneGeom<R, RY, NW>;
     const int tiles_x = (g.nx + G::BX - 1) / G::BX, tiles_y = (g.ny + G::BY - 1) / G::BY;
     const int nchunks = (g.nz + zc - 1) / zc;
@@ -192,11 +193,11 @@ static hipError_t go_ry(const Geom& g, const LaunchCfg& c, const TapsD& tp, cons
     const int zc = c.zchunk > 0 ? c.zchunk : g.nz;
     if constexpr (BC == kZero) {
         if (w.sp_w > 0)
-            return c.tile_y >= 16 ? go<R, BC, 4, true>(g, zc, tp, w, s) : go<R, BC, 2, true>(g, zc, tp, w, s);
+            return c.tile_y >= 16 ? go<R, BC, 8, true>(g, zc, tp, w, s) : go<R, BC, 4, true>(g, zc, tp, w, s);
     } else {
         if (w.sp_w > 0) return hipErrorInvalidValue;   // the layer lines a zero frame only
     }
-    return c.tile_y >= 16 ? go<R, BC, 4, false>(g, zc, tp, w, s) : go<R, BC, 2, false>(g, zc, tp, w, s);
+    return c.tile_y >= 16 ? go<R, BC, 8, false>(g, zc, tp, w, s) : go<R, BC, 4, false>(g, zc, tp, w, s);
 }
 
 template <int R>

@@ -182,7 +182,7 @@ def test_wave_argument_errors_before_device(L):
 
 def test_f64_wave_plan_forward_only(L):
     """An f64 wave plan is accepted for the forward leapfrog (the FP64 z-march
-    family, 8-row tiles by default; 32-row tiles and fused steps illegal);
+    family, 16-row tiles by default; 32-row tiles and fused steps illegal);
     the adjoint, the gradient and the autotuner refuse it before any device
     work, and the absorbing layer still needs the zero frame."""
     p, keep = _prob(ndim=3, n=(40, 24, 16), update=1, coeffs=None, dtype=2, r=4)
@@ -191,7 +191,7 @@ def test_f64_wave_plan_forward_only(L):
     v, tx, ty, k, zc = (ctypes.c_int32() for _ in range(5))
     assert L.stencil_plan_describe(h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(k),
                                    ctypes.byref(zc)) == _abi.ST_OK
-    assert (v.value, tx.value, ty.value, k.value) == (_abi.ST_VARIANT_WAVE3D, 0, 8, 1)
+    assert (v.value, tx.value, ty.value, k.value) == (_abi.ST_VARIANT_WAVE3D, 0, 16, 1)
     assert L.stencil_workspace_bytes(h, 3, 0) == 40 * 24 * 16 * 8
     fake = ctypes.c_void_p(0x1000)
     wa = _abi.StWaveArgs(ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), (ctypes.c_int64 * 3)(-1, 0, 0),
@@ -204,7 +204,7 @@ def test_f64_wave_plan_forward_only(L):
     for opts in (_abi.StPlanOpts(4, 0, 32, 1, 0, 0), _abi.StPlanOpts(3, 0, 32, 1, 0, 0),
                  _abi.StPlanOpts(3, 0, 8, 2, 0, 0), _abi.StPlanOpts(3, 2, 8, 1, 0, 0)):
         assert _plan(L, p, opts)[0] == _abi.ST_EINVAL
-    st, h = _plan(L, p, _abi.StPlanOpts(3, 0, 16, 1, 8, 0))
+    st, h = _plan(L, p, _abi.StPlanOpts(3, 0, 8, 1, 8, 0))
     assert st == _abi.ST_OK
     L.stencil_plan_destroy(h)
     p, keep = _prob(ndim=3, n=(40, 24, 16), update=1, coeffs=None, dtype=2, r=4, bc=_abi.ST_PERIODIC)
