@@ -911,3 +911,12 @@ def test_degenerate_extents(st, bc):
         uT, uT1, _ = m.forward(_dev(u0), _dev(up), _dev(kappa), 4)
         ra, rb, _ = oracle.wave_forward(up, u0, kappa, 4, boundary=bcode)
         assert rel_l2(_host(uT), rb) <= 1e-5 and rel_l2(_host(uT1), ra) <= 1e-5, (n, kw)
+    # The f64 leapfrog on the same kinds of extents (both tile heights).
+    for n, ty in [((1, 1, 40), 16), ((50, 1, 2), 8), ((3, 60, 1), 16), ((2, 2, 2), 8)]:
+        kappa = 0.05 + 0.1 * rng.random(n[::-1])
+        u0 = wl.small_random_grid(rng, 3, n, np.float64, -1.0, 1.0)
+        up = u0 * 0.9
+        m = st.WaveModel(n, boundary=bc, dtype="f64", tile_y=ty)
+        uT, uT1, _ = m.forward(_dev(u0), _dev(up), _dev(kappa), 4)
+        ra, rb, _ = oracle.wave_forward(up, u0, kappa, 4, boundary=bcode)
+        assert rel_l2(_host(uT), rb) <= TOL["f64"] and rel_l2(_host(uT1), ra) <= TOL["f64"], (n, ty)
