@@ -322,7 +322,7 @@ st_status stencil_plan_describe_batched(const st_plan *plan, int32_t steps, int3
  * Setting STENCIL_TUNE_FAULT=1 deliberately perturbs the coefficients of part
  * of the candidates (fused-step or 32-row ones) so tests can check that the
  * parity filter rejects wrong-but-faster candidates.  An ST_F64 wave plan
- * keeps its map configuration (ST_EUNSUPPORTED, nothing changed). */
+ * tunes its forward step only (it has no reverse step). */
 st_status stencil_autotune(st_plan *plan, void *scratch, size_t scratch_bytes, void *stream);
 
 /* Counts from the plan's last stencil_autotune: candidates tried and

@@ -146,6 +146,33 @@ def test_autotune_f64(st):
         assert rel_l2(o.cpu().numpy(), oracle.sweep(cb.u0, cb.coeffs, cb.shape, cb.radius, wl.PERIODIC, 6)) <= 1e-12
 
 
+def test_autotune_f64_wave(st, monkeypatch):
+    """The FP64 leapfrog tunes tile height and plane chunk within its own
+    family; the planted wrong candidates (16-row tiles) are rejected at the
+    f64 gate, and the tuned plan stays at the oracle's values."""
+    monkeypatch.setenv("STENCIL_TUNE_FAULT", "1")
+    n = (96, 64, 80)
+    m = st.WaveModel(n, dtype="f64", boundary="zero")
+    stats = m.autotune()
+    d = m.describe()
+    print("f64 wave tuned:", d, stats)
+    assert stats["rejected"] > 0 and d["variant"] == "wave3d" and d["tile_y"] == 8 and d["tsteps"] <= 1
+    monkeypatch.delenv("STENCIL_TUNE_FAULT")
+    m2 = st.WaveModel(n, dtype="f64", boundary="zero")
+    stats2 = m2.autotune()
+    d2 = m2.describe()
+    print("f64 wave tuned (no fault):", d2, stats2)
+    assert stats2["rejected"] == 0 and d2["variant"] == "wave3d" and d2["tile_y"] in (8, 16)
+    rng = np.random.default_rng(67)
+    kappa = rng.uniform(0.05, 0.2, n[::-1])
+    u0 = wl.gaussian_pulse(n, (40, 30, 35), 3.0).astype(np.float64)
+    up = u0 * 0.97
+    uT, uT1, _ = m2.forward(torch.from_numpy(u0).cuda(), torch.from_numpy(up).cuda(),
+                            torch.from_numpy(kappa).cuda(), 5)
+    ra, rb, _ = oracle.wave_forward(up, u0, kappa, 5)
+    assert rel_l2(uT.cpu().numpy(), rb) <= 1e-12 and rel_l2(uT1.cpu().numpy(), ra) <= 1e-12
+
+
 def test_autotune_reverse_step(st, monkeypatch):
     """The reverse (adjoint/gradient) step has its own tuned map cell: the
     planted fault (16-row candidates, shifted centre weight of L^T) is
