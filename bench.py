@@ -696,6 +696,10 @@ def cpu_per_config(wl):
                                                    tg, ckpt_every=g.ckpt_every), g.cells * g.steps)
     res["wavegrad"] = {"sample": "gradient law at 64^3 x 200 steps, K = 20", "threads": allt,
                        "fwd_bwd_ms": rr["seconds"] * 1e3, "gcells_s_fwd_bwd": rr["gcells_s"]}
+    # The oracle evaluates the leapfrog in FP64 whatever the storage, so the
+    # f64 wave workload's CPU figure is the headline's cpu_baseline sample.
+    res["wave3d_f64"] = {"sample": "the cpu_baseline sample (the FP64 oracle's leapfrog serves both storages)",
+                         "threads": allt, "see": "cpu_baseline"}
     return res
 
 
